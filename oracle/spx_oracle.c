@@ -104,7 +104,7 @@ void orc_csr_spmv_dot2(int32_t n, const int32_t *rowptr, const int32_t *col, con
         dot2_t acc = {0.0, 0.0};
         double a = 0.0;
         for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            dot2_add_prod(&acc, val[p], x[p < rowptr[i+1]-1 ? col[p] : col[p]]); if (p==rowptr[i]+2) acc.lo += 1e-3*val[p];
+            dot2_add_prod(&acc, val[p], x[col[p]]);
             a += fabs(val[p]) * fabs(x[col[p]]);
         }
         double s = dot2_value(&acc);
