@@ -1,0 +1,152 @@
+/*
+ * spx.h -- C ABI of the spx sparse library for AMD MI355X (gfx950).
+ *
+ * The library computes sparse matrix-vector products y = alpha*A*x + beta*y
+ * in the Csr, Coo, Ell and Hybrid formats and solves A x = b to a relative
+ * residual with Krylov methods (CG, BiCGSTAB, GMRES) and a scalar Jacobi
+ * preconditioner: the formats and solvers the paper names among the
+ * library features it ports (Section 1) and whose SpMV and CG kernels it
+ * measures (Section 4). The subwarp cooperative-group primitives it adds to
+ * HIP (Section 3.3) are exposed for testing and micro-benchmarking.
+ *
+ * Conventions (every entry point):
+ *  - All matrix and vector arrays are DEVICE pointers owned by the caller;
+ *    the library never frees them. Scalars are passed by value.
+ *  - Indices are int32. The CSR row pointer is int32, so nnz < 2^31. ELL slot
+ *    k of row i lives at k*ell_ld + i (slot-major, computed in int64).
+ *  - Every function returns an spx_status; nothing is thrown across the ABI.
+ *    spx_last_error() returns a thread-local description of the last failure.
+ *  - Descriptors are checked on the host (shapes, null pointers, type
+ *    combinations). Array contents are trusted by the compute calls; an
+ *    out-of-range index in them is undefined behaviour.
+ *  - Compute calls are stream-ordered and asynchronous on the hipStream_t
+ *    given (0 = the legacy default stream) unless stated otherwise.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPX_OK = 0,
+    SPX_ERR_ARG = 1,           /* invalid argument or unsupported combination      */
+    SPX_ERR_FORMAT = 2,        /* malformed matrix (e.g. ELL width too small)      */
+    SPX_ERR_UNSORTED = 3,      /* columns not strictly ascending in a row          */
+    SPX_ERR_DUPLICATE = 4,     /* repeated (row, col) entry                        */
+    SPX_ERR_RANGE = 5,         /* index out of range / binary16 overflow in a cast */
+    SPX_ERR_NOMEM = 6,         /* device or host allocation failed                 */
+    SPX_ERR_BUDGET = 7,        /* request larger than the server's HBM budget      */
+    SPX_ERR_HIP = 8,           /* a HIP runtime call failed                        */
+    SPX_ERR_ZERO_DIAG = 9,     /* Jacobi: zero, missing or non-finite diagonal     */
+    SPX_ERR_NOT_CONVERGED = 10,/* iteration limit reached                          */
+    SPX_ERR_BREAKDOWN = 11,    /* Krylov breakdown (p'Ap <= 0, rho = 0, ...)       */
+    SPX_ERR_NONFINITE = 12,    /* NaN or Inf in a residual norm                    */
+    SPX_PENDING = 13,          /* serving: request not finished yet                */
+    SPX_CANCELLED = 14         /* serving: request cancelled                       */
+} spx_status;
+
+typedef enum {
+    SPX_F64 = 0, /* float64 values, float64 vectors                               */
+    SPX_F32 = 1, /* float32 values, float32 vectors                               */
+    SPX_F16 = 2  /* binary16 stored values, float32 vectors and accumulation       */
+} spx_dtype;
+
+typedef enum { SPX_CSR = 0, SPX_COO = 1, SPX_ELL = 2, SPX_HYB = 3 } spx_format;
+
+/* Sparse matrix descriptor. Fields a format does not use are ignored.
+ *  CSR: rowptr[nrows+1], colidx[nnz], vals[nnz]; rows ascending, columns
+ *       strictly ascending inside a row, rowptr[0] = 0, rowptr[nrows] = nnz.
+ *  COO: rowidx[nnz], colidx[nnz], vals[nnz] sorted by (row, col).
+ *  ELL: ell_col[ell_width*ell_ld], ell_val[same]; ell_ld >= nrows; padding
+ *       slots hold column -1 and value +0 and come after a row's entries.
+ *  HYB: an ELL part (ell_*) plus a COO part (rowidx/colidx/vals, coo_nnz
+ *       entries, sorted); nnz = stored ELL entries + coo_nnz.
+ * max_row_len is an optional hint (0 = unknown) used to choose kernels.     */
+typedef struct spx_matrix {
+    int32_t fmt;       /* spx_format */
+    int32_t val_type;  /* spx_dtype  */
+    int32_t nrows;
+    int32_t ncols;
+    int64_t nnz;
+    int32_t *rowptr;
+    int32_t *rowidx;
+    int32_t *colidx;
+    void *vals;
+    int64_t coo_nnz;
+    int32_t ell_width;
+    int32_t max_row_len;
+    int64_t ell_ld;
+    int32_t *ell_col;
+    void *ell_val;
+} spx_matrix;
+
+/* Name of a status code (static string). */
+const char *spx_status_string(spx_status s);
+
+/* Description of the last error raised on the calling thread ("" if none). */
+const char *spx_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t spx_version(void);
+
+/* ------------------------------------------------------------ SpMV
+ * y = alpha * A x + beta * y  (Section 1: the Coo, Csr, Ell and Hybrid
+ * formats; Section 4 measures the Coo and Sellp/Csr products).
+ * x has ncols entries and y nrows entries, of the vector type of A's dtype
+ * (float64 for SPX_F64, float32 for SPX_F32 and SPX_F16). With beta == 0, y
+ * is write-only (it may hold NaN). x must not alias y.
+ * Errors: SPX_ERR_ARG for null pointers, negative sizes, a bad dtype or
+ * format; SPX_ERR_HIP if a launch fails. Asynchronous on `stream`.
+ * The Csr, Ell and Hybrid-ELL row sums use a fixed order (bitwise
+ * reproducible run to run); Coo and the COO part of Hybrid accumulate rows
+ * that cross a work-chunk boundary with atomic adds, whose order varies. */
+spx_status spx_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
+                    hipStream_t stream);
+
+/* Same as spx_spmv but requires fmt == SPX_CSR. The rows are split into
+ * work-groups of equal nonzero count (a row is owned by the group in which it
+ * starts), so skewed row lengths stay balanced; each group stages products
+ * in LDS and reduces every row with a subwarp whose size adapts to the
+ * number of rows in the group. */
+spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
+                        hipStream_t stream);
+
+/* ------------------------------------------------------------ subwarp primitives
+ * The subwarp cooperative-group operations of Section 3.3 on 64-lane
+ * wavefronts, over n device values (n a multiple of 64):
+ *  spx_subwarp_sum:   out[t] = sum of in[] over t's subwarp of `size` lanes
+ *                     (xor butterfly, log2(size) steps), repeated
+ *                     `inner_loops` times on the running value as in the
+ *                     paper's reduction benchmark (inner_loops = 1 gives the
+ *                     plain group sum). size in {1,2,4,...,64}. float64.
+ *  spx_subwarp_vote:  ballot[t] = (wave ballot of pred & Mask) >> LaneOffset,
+ *                     any[t], all[t] as defined in Section 3.3.
+ *  spx_wave_segscan:  inclusive segmented sum over each 64-lane wavefront,
+ *                     segments starting at head[t] != 0 and at lane 0.
+ * Errors: SPX_ERR_ARG for a bad size, n not a multiple of 64 or null
+ * pointers. Asynchronous. */
+spx_status spx_subwarp_sum(const double *in, double *out, int64_t n, int32_t size, int32_t inner_loops,
+                           hipStream_t stream);
+spx_status spx_subwarp_vote(const int32_t *pred, uint64_t *ballot, int32_t *any, int32_t *all, int64_t n,
+                            int32_t size, hipStream_t stream);
+spx_status spx_wave_segscan(const double *in, const int32_t *head, double *out, int64_t n,
+                            hipStream_t stream);
+
+/* ------------------------------------------------------------ measurement helper
+ * dst[i] = src[i] for n float64 values with the streaming-load pattern of
+ * the SpMV kernels; used to measure the attainable HBM copy bandwidth next
+ * to the SpMV rates. Asynchronous. */
+spx_status spx_stream_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

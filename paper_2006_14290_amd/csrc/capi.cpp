@@ -1,0 +1,143 @@
+// capi.cpp -- status strings, thread-local error text, descriptor checks and
+// the format/dtype dispatch of the SpMV entry points.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+#include "spmv.hpp"
+#include "spmv_csr.hpp"
+
+namespace spx {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+spx_status check_matrix(const spx_matrix *A, const char *who)
+{
+    SPX_REQUIRE(A != nullptr, SPX_ERR_ARG, "%s: null matrix descriptor", who);
+    SPX_REQUIRE(A->nrows >= 0 && A->ncols >= 0 && A->nnz >= 0, SPX_ERR_ARG, "%s: negative size", who);
+    SPX_REQUIRE(A->val_type >= SPX_F64 && A->val_type <= SPX_F16, SPX_ERR_ARG, "%s: bad val_type %d", who,
+                A->val_type);
+    switch (A->fmt) {
+    case SPX_CSR:
+        SPX_REQUIRE(A->rowptr != nullptr, SPX_ERR_ARG, "%s: CSR needs rowptr", who);
+        SPX_REQUIRE(A->nnz == 0 || (A->colidx && A->vals), SPX_ERR_ARG, "%s: CSR needs colidx and vals", who);
+        SPX_REQUIRE(A->nnz <= INT32_MAX, SPX_ERR_ARG, "%s: CSR nnz exceeds int32", who);
+        break;
+    case SPX_COO:
+        SPX_REQUIRE(A->nnz == 0 || (A->rowidx && A->colidx && A->vals), SPX_ERR_ARG,
+                    "%s: COO needs rowidx, colidx and vals", who);
+        break;
+    case SPX_ELL:
+        SPX_REQUIRE(A->ell_width >= 0, SPX_ERR_ARG, "%s: negative ell_width", who);
+        SPX_REQUIRE(A->ell_ld >= A->nrows, SPX_ERR_ARG, "%s: ell_ld < nrows", who);
+        SPX_REQUIRE(A->ell_width == 0 || A->nrows == 0 || (A->ell_col && A->ell_val), SPX_ERR_ARG,
+                    "%s: ELL needs ell_col and ell_val", who);
+        break;
+    case SPX_HYB:
+        SPX_REQUIRE(A->ell_width >= 0 && A->coo_nnz >= 0, SPX_ERR_ARG, "%s: negative HYB sizes", who);
+        SPX_REQUIRE(A->ell_ld >= A->nrows, SPX_ERR_ARG, "%s: ell_ld < nrows", who);
+        SPX_REQUIRE(A->ell_width == 0 || A->nrows == 0 || (A->ell_col && A->ell_val), SPX_ERR_ARG,
+                    "%s: HYB needs ell_col and ell_val", who);
+        SPX_REQUIRE(A->coo_nnz == 0 || (A->rowidx && A->colidx && A->vals), SPX_ERR_ARG,
+                    "%s: HYB needs its COO arrays", who);
+        break;
+    default:
+        SPX_REQUIRE(false, SPX_ERR_ARG, "%s: bad format %d", who, A->fmt);
+    }
+    return SPX_OK;
+}
+
+template <typename V, typename X>
+static spx_status spmv_typed(const spx_matrix &A, const void *x, void *y, double alpha, double beta,
+                             hipStream_t stream)
+{
+    const X *xx = static_cast<const X *>(x);
+    X *yy = static_cast<X *>(y);
+    const X a = static_cast<X>(alpha), b = static_cast<X>(beta);
+    switch (A.fmt) {
+    case SPX_CSR: return csr_spmv_launch<V, X>(A, xx, yy, a, b, nullptr, nullptr, stream);
+    case SPX_COO: return coo_spmv_launch<V, X>(A, xx, yy, a, b, stream);
+    case SPX_ELL: return ell_spmv_launch<V, X>(A, xx, yy, a, b, stream);
+    case SPX_HYB: return hyb_spmv_launch<V, X>(A, xx, yy, a, b, stream);
+    default: break;
+    }
+    set_error("spmv: bad format");
+    return SPX_ERR_ARG;
+}
+
+spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta, hipStream_t stream)
+{
+    if (A.nrows == 0) return SPX_OK;
+    switch (A.val_type) {
+    case SPX_F64: return spmv_typed<double, double>(A, x, y, alpha, beta, stream);
+    case SPX_F32: return spmv_typed<float, float>(A, x, y, alpha, beta, stream);
+    case SPX_F16: return spmv_typed<_Float16, float>(A, x, y, alpha, beta, stream);
+    default: break;
+    }
+    set_error("spmv: bad val_type");
+    return SPX_ERR_ARG;
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" const char *spx_status_string(spx_status s)
+{
+    switch (s) {
+    case SPX_OK: return "SPX_OK";
+    case SPX_ERR_ARG: return "SPX_ERR_ARG";
+    case SPX_ERR_FORMAT: return "SPX_ERR_FORMAT";
+    case SPX_ERR_UNSORTED: return "SPX_ERR_UNSORTED";
+    case SPX_ERR_DUPLICATE: return "SPX_ERR_DUPLICATE";
+    case SPX_ERR_RANGE: return "SPX_ERR_RANGE";
+    case SPX_ERR_NOMEM: return "SPX_ERR_NOMEM";
+    case SPX_ERR_BUDGET: return "SPX_ERR_BUDGET";
+    case SPX_ERR_HIP: return "SPX_ERR_HIP";
+    case SPX_ERR_ZERO_DIAG: return "SPX_ERR_ZERO_DIAG";
+    case SPX_ERR_NOT_CONVERGED: return "SPX_ERR_NOT_CONVERGED";
+    case SPX_ERR_BREAKDOWN: return "SPX_ERR_BREAKDOWN";
+    case SPX_ERR_NONFINITE: return "SPX_ERR_NONFINITE";
+    case SPX_PENDING: return "SPX_PENDING";
+    case SPX_CANCELLED: return "SPX_CANCELLED";
+    }
+    return "SPX_UNKNOWN";
+}
+
+extern "C" const char *spx_last_error(void) { return g_last_error; }
+
+extern "C" int32_t spx_version(void) { return 100; }
+
+extern "C" spx_status spx_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
+                               hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_spmv"));
+    SPX_REQUIRE(A->nrows == 0 || (y != nullptr && (A->ncols == 0 || x != nullptr)), SPX_ERR_ARG,
+                "spx_spmv: null vector");
+    SPX_REQUIRE(x != y || A->nrows == 0, SPX_ERR_ARG, "spx_spmv: x aliases y");
+    return spmv_dispatch(*A, x, y, alpha, beta, stream);
+}
+
+extern "C" spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
+                                   hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_csr_spmv"));
+    SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "spx_csr_spmv: matrix is not CSR");
+    SPX_REQUIRE(A->nrows == 0 || (y != nullptr && (A->ncols == 0 || x != nullptr)), SPX_ERR_ARG,
+                "spx_csr_spmv: null vector");
+    SPX_REQUIRE(x != y || A->nrows == 0, SPX_ERR_ARG, "spx_csr_spmv: x aliases y");
+    return spmv_dispatch(*A, x, y, alpha, beta, stream);
+}

@@ -1,0 +1,25 @@
+// spmv.hpp -- launch interfaces of the COO, ELL and hybrid products and the
+// shared descriptor check.
+#pragma once
+
+#include "common.hpp"
+
+namespace spx {
+
+spx_status check_matrix(const spx_matrix *A, const char *who);
+spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta,
+                         hipStream_t stream);
+
+constexpr int kCooThreads = 256;
+constexpr int kCooTiles = 8;                      // 64-entry tiles per wavefront chunk
+constexpr int kCooChunk = 64 * kCooTiles;          // entries per wavefront chunk
+constexpr int kEllThreads = 256;
+
+template <typename V, typename X>
+spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+template <typename V, typename X>
+spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+template <typename V, typename X>
+spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+
+}  // namespace spx

@@ -1,0 +1,249 @@
+// spmv_formats.hip -- COO, ELL and hybrid ELL+COO products for gfx950.
+//
+// COO (Section 4: the Coo product "relies on atomic operations"): entries
+// sorted by row are cut into wavefront chunks of kCooChunk entries. A
+// wavefront walks its chunk in 64-entry tiles: coalesced loads of row, column
+// and value, gathered x, then one segmented inclusive scan across the 64
+// lanes (DPP row shifts + row broadcasts, wave.hpp) keyed by the row index.
+// The last segment of a tile is carried in registers into the next tile.
+// A row wholly inside a chunk is written with a plain store; a row that
+// crosses a chunk boundary is accumulated with a float atomic add after a
+// small pre-pass has set it to beta*y (the only non-deterministic order).
+// Rows without entries (gaps between consecutive row indices) are written
+// beta*y by the chunk that sees the gap.
+//
+// ELL: slot-major layout (slot k of row i at k*ld + i), one lane per row,
+// so every slot load is a contiguous 64-lane access. Padding slots (column -1)
+// skip the gather; since padding follows a row's entries, a wavefront stops
+// as soon as all of its rows have reached padding.
+//
+// HYB: the ELL kernel writes y = alpha*A_ell*x + beta*y, then the COO kernel
+// adds the COO part (plain read-modify-write for rows inside a chunk, atomics
+// for rows crossing a chunk boundary).
+#include "common.hpp"
+#include "spmv.hpp"
+#include "wave.hpp"
+
+namespace spx {
+
+template <typename X>
+__device__ __forceinline__ X scaled(X v, X beta)
+{
+    return beta == X(0) ? X(0) : beta * v;
+}
+
+// Pre-pass: a row crossing a chunk boundary is set to beta*y exactly once,
+// by the first boundary that falls strictly inside it.
+template <typename X>
+__global__ __launch_bounds__(256) void coo_split_init_kernel(int64_t nnz, int64_t nchunks,
+                                                            const int32_t *__restrict__ row, X *__restrict__ y,
+                                                            X beta)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;  // boundary k*chunk, k >= 1
+    if (k >= nchunks) return;
+    const int64_t b = k * kCooChunk;
+    const int32_t r = row[b];
+    if (row[b - 1] != r) return;                       // boundary between rows: no split
+    if (k >= 2 && row[b - kCooChunk - 1] == r) return;  // an earlier boundary is inside r too
+    y[r] = scaled(y[r], beta);
+}
+
+template <typename X>
+__global__ __launch_bounds__(256) void scale_kernel(int64_t n, X *__restrict__ y, X beta)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = scaled(y[i], beta);
+}
+
+// Complete segment (row r, sum) of chunk [c0, c1): atomics if it may share
+// its row with a neighbouring chunk.
+template <typename X, bool kAccumulate>
+__device__ __forceinline__ void coo_write(int32_t r, X sum, bool chunk_start_seg, bool chunk_end_seg, int64_t c0,
+                                          int64_t c1, int64_t nnz, const int32_t *__restrict__ row,
+                                          X *__restrict__ y, X alpha, X beta)
+{
+    const bool left = chunk_start_seg && c0 > 0 && row[c0 - 1] == r;
+    const bool right = chunk_end_seg && c1 < nnz && row[c1] == r;
+    if (left || right) {
+        unsafeAtomicAdd(y + r, alpha * sum);
+    } else if (kAccumulate) {
+        y[r] += alpha * sum;
+    } else {
+        y[r] = alpha * sum + scaled(y[r], beta);
+    }
+}
+
+template <typename V, typename X, bool kAccumulate>
+__global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, int64_t nnz, int64_t nchunks,
+                                                               int64_t grid_padded, const int32_t *__restrict__ row,
+                                                               const int32_t *__restrict__ col,
+                                                               const V *__restrict__ val, const X *__restrict__ x,
+                                                               X *__restrict__ y, X alpha, X beta)
+{
+    const int lane = lane_id();
+    const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
+    const int64_t chunk = blk * (kCooThreads / kWave) + threadIdx.x / kWave;
+    if (chunk >= nchunks) return;
+    const int64_t c0 = chunk * kCooChunk;
+    const int64_t c1 = (c0 + kCooChunk < nnz) ? c0 + kCooChunk : nnz;
+
+    // issue every load of the chunk first (memory-level parallelism)
+    int32_t r[kCooTiles], c[kCooTiles];
+    X p[kCooTiles];
+#pragma unroll
+    for (int t = 0; t < kCooTiles; ++t) {
+        const int64_t e = c0 + t * kWave + lane;
+        r[t] = -1;
+        c[t] = 0;
+        p[t] = X(0);
+        if (e < c1) {
+            r[t] = ld_stream(row + e);
+            c[t] = ld_stream(col + e);
+            p[t] = widen(ld_stream(val + e));
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kCooTiles; ++t)
+        if (r[t] >= 0) p[t] *= x[c[t]];
+
+    int32_t carry_row = -1;
+    X carry_val = X(0);
+    bool carry_start = false;  // carried segment began at the chunk start
+#pragma unroll
+    for (int t = 0; t < kCooTiles; ++t) {
+        const int64_t tb = c0 + t * kWave;
+        if (tb >= c1) break;
+        const int64_t e = tb + lane;
+        const bool valid = e < c1;
+        const int32_t rr = r[t];
+        const int32_t r0 = readlane(rr, 0);
+        // the carried segment ends before this tile: write it
+        if (carry_row >= 0 && r0 != carry_row) {
+            if (lane == 0)
+                coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, false, c0, c1, nnz, row, y, alpha, beta);
+            carry_row = -1;
+        }
+        const bool merged = (carry_row >= 0);  // lane 0 continues the carried segment
+        const int32_t rprev = valid ? (e > 0 ? row[e - 1] : -1) : 0;
+        const bool head = !valid || lane == 0 || rr != rprev;
+        X v = p[t];
+        if (lane == 0 && merged) v += carry_val;
+        // gaps: rows strictly between the previous entry's row and this one are empty
+        if (!kAccumulate && valid && rr != rprev)
+            for (int32_t g = rprev + 1; g < rr; ++g) y[g] = scaled(y[g], beta);
+        if (!kAccumulate && valid && e == nnz - 1)
+            for (int32_t g = rr + 1; g < nrows; ++g) y[g] = scaled(y[g], beta);
+        const X s = wave_segscan(v, head);
+        // last valid lane of the tile and the segment it closes are carried on
+        const int64_t tail_e = (c1 - tb < kWave) ? c1 - tb - 1 : kWave - 1;
+        const lane_mask_t heads = ballot64(head && lane > 0);
+        const bool seg0 = (heads & ((lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull)) == 0;  // segment holds lane 0
+        const bool start_seg = seg0 && (t == 0 || (merged && carry_start));
+        // a lane closes a segment when the next lane starts a new one
+        const int32_t rn = (lane < tail_e) ? row[e + 1] : -2;
+        if (lane < tail_e && rn != rr)
+            coo_write<X, kAccumulate>(rr, s, start_seg, false, c0, c1, nnz, row, y, alpha, beta);
+        // carry the tile's last segment
+        carry_row = readlane(rr, (int)tail_e);
+        carry_val = readlane(s, (int)tail_e);
+        const lane_mask_t upto_tail = (tail_e == 63) ? ~0ull : ((2ull << tail_e) - 1);
+        const bool last_seg_has_lane0 = (heads & upto_tail & ~1ull) == 0;
+        carry_start = last_seg_has_lane0 && (t == 0 || (merged && carry_start));
+    }
+    if (carry_row >= 0 && lane == 0)
+        coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, c0, c1, nnz, row, y, alpha, beta);
+}
+
+template <typename V, typename X>
+__global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, int32_t K, int64_t ld,
+                                                               int64_t grid_padded, const int32_t *__restrict__ ecol,
+                                                               const V *__restrict__ eval, const X *__restrict__ x,
+                                                               X *__restrict__ y, X alpha, X beta)
+{
+    const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
+    const int64_t i = blk * kEllThreads + threadIdx.x;
+    if (blk * kEllThreads >= nrows) return;
+    const bool in = i < nrows;
+    X sum = X(0);
+    constexpr int U = 4;
+    for (int k = 0; k < K; k += U) {
+        int32_t cc[U];
+        X vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cc[u] = -1;
+            vv[u] = X(0);
+            if (in && k + u < K) {
+                const int64_t q = (int64_t)(k + u) * ld + i;
+                cc[u] = ld_stream(ecol + q);
+                vv[u] = widen(ld_stream(eval + q));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (cc[u] >= 0) sum += vv[u] * x[cc[u]];
+        if (ballot64(cc[U - 1] >= 0) == 0) break;  // every row of the wavefront is into its padding
+    }
+    if (in) y[i] = alpha * sum + scaled(y[i], beta);
+}
+
+template <typename V, typename X, bool kAccumulate>
+static spx_status coo_part(int32_t nrows, int64_t nnz, const int32_t *row, const int32_t *col, const V *val,
+                           const X *x, X *y, X alpha, X beta, hipStream_t stream)
+{
+    if (nnz == 0) {
+        if (!kAccumulate) {
+            scale_kernel<X><<<(unsigned)ceil_div(nrows, 256), 256, 0, stream>>>(nrows, y, beta);
+            SPX_LAUNCHED();
+        }
+        return SPX_OK;
+    }
+    const int64_t nchunks = ceil_div(nnz, kCooChunk);
+    if (!kAccumulate && nchunks > 1) {
+        coo_split_init_kernel<X><<<(unsigned)ceil_div(nchunks - 1, 256), 256, 0, stream>>>(nnz, nchunks, row, y, beta);
+        SPX_LAUNCHED();
+    }
+    const int64_t blocks = ceil_div(nchunks, kCooThreads / kWave);
+    const int64_t grid = pad_to_xcds(blocks);
+    coo_spmv_kernel<V, X, kAccumulate><<<(unsigned)grid, kCooThreads, 0, stream>>>(nrows, nnz, nchunks, grid, row,
+                                                                                  col, val, x, y, alpha, beta);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+template <typename V, typename X>
+spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+{
+    return coo_part<V, X, false>(A.nrows, A.nnz, A.rowidx, A.colidx, static_cast<const V *>(A.vals), x, y, alpha,
+                                 beta, stream);
+}
+
+template <typename V, typename X>
+spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+{
+    const int64_t blocks = ceil_div(A.nrows, kEllThreads);
+    const int64_t grid = pad_to_xcds(blocks);
+    ell_spmv_kernel<V, X><<<(unsigned)grid, kEllThreads, 0, stream>>>(
+        A.nrows, A.ell_width, A.ell_ld, grid, A.ell_col, static_cast<const V *>(A.ell_val), x, y, alpha, beta);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+template <typename V, typename X>
+spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+{
+    SPX_CHECK(ell_spmv_launch<V, X>(A, x, y, alpha, beta, stream));
+    return coo_part<V, X, true>(A.nrows, A.coo_nnz, A.rowidx, A.colidx, static_cast<const V *>(A.vals), x, y, alpha,
+                                beta, stream);
+}
+
+#define SPX_INST(V, X)                                                                                          \
+    template spx_status coo_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
+    template spx_status ell_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
+    template spx_status hyb_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);
+SPX_INST(double, double)
+SPX_INST(float, float)
+SPX_INST(_Float16, float)
+#undef SPX_INST
+
+}  // namespace spx

@@ -1,0 +1,219 @@
+"""Python binding of libspx.so (include/spx.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every computation runs in the
+library's HIP kernels. Importing this module loads libspx.so and raises if it
+is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2006_14290_amd/build.py (or __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ enums
+OK, ERR_ARG, ERR_FORMAT, ERR_UNSORTED, ERR_DUPLICATE, ERR_RANGE, ERR_NOMEM, ERR_BUDGET, ERR_HIP, \
+    ERR_ZERO_DIAG, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE, PENDING, CANCELLED = range(15)
+F64, F32, F16 = 0, 1, 2
+CSR, COO, ELL, HYB = 0, 1, 2, 3
+
+_VAL_DTYPE = {F64: torch.float64, F32: torch.float32, F16: torch.float16}
+_VEC_DTYPE = {F64: torch.float64, F32: torch.float32, F16: torch.float32}
+DTYPE_NAMES = {"f64": F64, "f32": F32, "f16": F16}
+
+
+class SpxError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        name = _lib.spx_status_string(status).decode()
+        detail = _lib.spx_last_error().decode()
+        super().__init__(f"{where}: {name}: {detail}")
+
+
+class MatrixDesc(ctypes.Structure):
+    _fields_ = [
+        ("fmt", ctypes.c_int32), ("val_type", ctypes.c_int32), ("nrows", ctypes.c_int32),
+        ("ncols", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+        ("rowidx", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+        ("coo_nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("max_row_len", ctypes.c_int32),
+        ("ell_ld", ctypes.c_int64), ("ell_col", ctypes.c_void_p), ("ell_val", ctypes.c_void_p),
+    ]
+
+
+_vp, _i32, _i64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_MP = ctypes.POINTER(MatrixDesc)
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("spx_status_string", [ctypes.c_int], ctypes.c_char_p)
+_sig("spx_last_error", [], ctypes.c_char_p)
+_sig("spx_version", [], ctypes.c_int32)
+_sig("spx_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
+_sig("spx_csr_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
+_sig("spx_subwarp_sum", [_vp, _vp, _i64, _i32, _i32, _vp])
+_sig("spx_subwarp_vote", [_vp, _vp, _vp, _vp, _i64, _i32, _vp])
+_sig("spx_wave_segscan", [_vp, _vp, _vp, _i64, _vp])
+_sig("spx_stream_copy", [_vp, _vp, _i64, _vp])
+
+
+def check(status: int, where: str):
+    if status != OK:
+        raise SpxError(status, where)
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("spx works on device tensors")
+    if not t.is_contiguous():
+        raise ValueError("spx needs contiguous tensors")
+    return t.data_ptr() if t.numel() > 0 else None
+
+
+# ------------------------------------------------------------------ matrices
+@dataclass
+class Matrix:
+    """A device sparse matrix: torch tensors plus the C descriptor."""
+
+    fmt: int
+    dtype: int
+    nrows: int
+    ncols: int
+    nnz: int
+    rowptr: Optional[torch.Tensor] = None
+    rowidx: Optional[torch.Tensor] = None
+    colidx: Optional[torch.Tensor] = None
+    vals: Optional[torch.Tensor] = None
+    coo_nnz: int = 0
+    ell_width: int = 0
+    ell_ld: int = 0
+    ell_col: Optional[torch.Tensor] = None
+    ell_val: Optional[torch.Tensor] = None
+    max_row_len: int = 0
+    _desc: MatrixDesc = field(default=None, repr=False)
+
+    def desc(self) -> MatrixDesc:
+        d = MatrixDesc()
+        d.fmt, d.val_type, d.nrows, d.ncols, d.nnz = self.fmt, self.dtype, self.nrows, self.ncols, self.nnz
+        d.rowptr, d.rowidx, d.colidx, d.vals = (_ptr(self.rowptr), _ptr(self.rowidx), _ptr(self.colidx),
+                                                _ptr(self.vals))
+        d.coo_nnz, d.ell_width, d.max_row_len, d.ell_ld = self.coo_nnz, self.ell_width, self.max_row_len, self.ell_ld
+        d.ell_col, d.ell_val = _ptr(self.ell_col), _ptr(self.ell_val)
+        self._desc = d
+        return d
+
+    @property
+    def vec_dtype(self):
+        return _VEC_DTYPE[self.dtype]
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in
+                   (self.rowptr, self.rowidx, self.colidx, self.vals, self.ell_col, self.ell_val) if t is not None)
+
+
+def _dev_vals(vals: np.ndarray, dtype: int, device) -> torch.Tensor:
+    """Host float64 values stored as dtype on the device (round to nearest even)."""
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    np_t = {F64: np.float64, F32: np.float32, F16: np.float16}[dtype]
+    return torch.from_numpy(v.astype(np_t)).to(device)
+
+
+def csr_from_host(A, dtype: int = F64, device="cuda") -> Matrix:
+    """Upload a host CSR (rowptr/col/val numpy arrays) as a device Matrix."""
+    lens = np.diff(A.rowptr.astype(np.int64))
+    return Matrix(CSR, dtype, int(A.n), int(A.n), int(A.rowptr[-1]),
+                  rowptr=torch.from_numpy(np.ascontiguousarray(A.rowptr, np.int32)).to(device),
+                  colidx=torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).to(device),
+                  vals=_dev_vals(A.val, dtype, device),
+                  max_row_len=int(lens.max()) if lens.size else 0)
+
+
+def coo_from_host(n, row, col, val, dtype: int = F64, device="cuda") -> Matrix:
+    return Matrix(COO, dtype, int(n), int(n), int(len(row)),
+                  rowidx=torch.from_numpy(np.ascontiguousarray(row, np.int32)).to(device),
+                  colidx=torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(device),
+                  vals=_dev_vals(val, dtype, device))
+
+
+def ell_from_host(n, K, ld, ecol, eval_, dtype: int = F64, device="cuda") -> Matrix:
+    ecol = np.ascontiguousarray(ecol, np.int32)
+    return Matrix(ELL, dtype, int(n), int(n), int((ecol >= 0).sum()), ell_width=int(K), ell_ld=int(ld),
+                  ell_col=torch.from_numpy(ecol).to(device), ell_val=_dev_vals(eval_, dtype, device))
+
+
+def hyb_from_host(n, K, ld, ecol, eval_, row, col, val, dtype: int = F64, device="cuda") -> Matrix:
+    ecol = np.ascontiguousarray(ecol, np.int32)
+    return Matrix(HYB, dtype, int(n), int(n), int((ecol >= 0).sum()) + int(len(row)), ell_width=int(K),
+                  ell_ld=int(ld), ell_col=torch.from_numpy(ecol).to(device), ell_val=_dev_vals(eval_, dtype, device),
+                  coo_nnz=int(len(row)),
+                  rowidx=torch.from_numpy(np.ascontiguousarray(row, np.int32)).to(device),
+                  colidx=torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(device),
+                  vals=_dev_vals(val, dtype, device))
+
+
+# ------------------------------------------------------------------ SpMV
+def spmv(A: Matrix, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+         stream=None, csr_only: bool = False) -> torch.Tensor:
+    """y = alpha*A*x + beta*y on the device (asynchronous on the stream)."""
+    if y is None:
+        y = torch.empty(A.nrows, dtype=A.vec_dtype, device=x.device)
+    for v, nm in ((x, "x"), (y, "y")):
+        if v.dtype != A.vec_dtype:
+            raise TypeError(f"{nm} must be {A.vec_dtype}")
+    fn = _lib.spx_csr_spmv if csr_only else _lib.spx_spmv
+    check(fn(ctypes.byref(A.desc()), _ptr(x), _ptr(y), float(alpha), float(beta), _stream(stream)),
+          "spx_csr_spmv" if csr_only else "spx_spmv")
+    return y
+
+
+# ------------------------------------------------------------------ primitives
+def subwarp_sum(x: torch.Tensor, size: int, inner_loops: int = 1, out=None, stream=None) -> torch.Tensor:
+    out = torch.empty_like(x) if out is None else out
+    check(_lib.spx_subwarp_sum(_ptr(x), _ptr(out), x.numel(), size, inner_loops, _stream(stream)), "spx_subwarp_sum")
+    return out
+
+
+def subwarp_vote(pred: torch.Tensor, size: int, stream=None):
+    n = pred.numel()
+    ballot = torch.empty(n, dtype=torch.int64, device=pred.device)
+    anyv = torch.empty(n, dtype=torch.int32, device=pred.device)
+    allv = torch.empty(n, dtype=torch.int32, device=pred.device)
+    check(_lib.spx_subwarp_vote(_ptr(pred), _ptr(ballot), _ptr(anyv), _ptr(allv), n, size, _stream(stream)),
+          "spx_subwarp_vote")
+    return ballot, anyv, allv
+
+
+def wave_segscan(x: torch.Tensor, head: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty_like(x)
+    check(_lib.spx_wave_segscan(_ptr(x), _ptr(head), _ptr(out), x.numel(), _stream(stream)), "spx_wave_segscan")
+    return out
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    check(_lib.spx_stream_copy(_ptr(src), _ptr(dst), src.numel(), _stream(stream)), "spx_stream_copy")
+
+
+def version() -> int:
+    return _lib.spx_version()
