@@ -91,7 +91,7 @@ def main():
     # replicate so that the rotated working set exceeds the Infinity Cache
     fp = csr_bytes(n, nnz, 8, 8)
     R = max(2, int(np.ceil((1 << 30) / fp)))
-    mats = [spx.csr_from_host(A, spx.F64, dev) for _ in range(R)]
+    mats = [spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev)) for _ in range(R)]
     xs = [torch.from_numpy(x_h).to(dev) for _ in range(R)]
     ys = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(R)]
 
@@ -123,8 +123,9 @@ def main():
             "ell_f64": (lambda: spx.ell_from_host(n, E.K, E.ld, E.col, E.val, spx.F64, dev), ell_bytes(n, E.K, 8, 8)),
             "hyb_f64": (lambda: spx.hyb_from_host(n, H.ell.K, H.ell.ld, H.ell.col, H.ell.val, H.row, H.col, H.val,
                                                   spx.F64, dev), hyb_bytes(n, H.ell.K, len(H.row), 8, 8)),
-            "csr_f32": (lambda: spx.csr_from_host(A, spx.F32, dev), csr_bytes(n, nnz, 4, 4)),
-            "csr_f16": (lambda: spx.csr_from_host(A, spx.F16, dev), csr_bytes(n, nnz, 2, 4)),
+            "csr_f32": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F32, dev)), csr_bytes(n, nnz, 4, 4)),
+            "csr_f16": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F16, dev)), csr_bytes(n, nnz, 2, 4)),
+            "csr_f64_nopart": (lambda: spx.csr_from_host(A, spx.F64, dev), csr_bytes(n, nnz, 8, 8)),
         }
         del mats
         torch.cuda.empty_cache()

@@ -85,6 +85,7 @@ typedef struct spx_matrix {
     int64_t ell_ld;
     int32_t *ell_col;
     void *ell_val;
+    const int32_t *csr_part; /* optional CSR partition from spx_csr_analyse (NULL = none) */
 } spx_matrix;
 
 /* Name of a status code (static string). */
@@ -117,6 +118,19 @@ spx_status spx_spmv(const spx_matrix *A, const void *x, void *y, double alpha, d
  * number of rows in the group. */
 spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
                         hipStream_t stream);
+
+/* CSR analysis: the row partition of the load-balanced CSR product.
+ * The nonzeros are cut into tiles of 4096; for every tile boundary the
+ * partition stores (first row starting at or after the boundary, that row's
+ * offset) as two int32. Computing it once per matrix lets every later
+ * product (and every solver iteration) skip the per-tile search of the row
+ * pointer. spx_csr_analysis_bytes gives the size of the device buffer;
+ * spx_csr_analyse fills `buf` (caller-owned device memory, kept alive as long
+ * as A is used) and stores it in A->csr_part. The partition is valid while
+ * A->rowptr is unchanged. Errors: SPX_ERR_ARG (not CSR, buffer too small).
+ * Asynchronous. */
+int64_t spx_csr_analysis_bytes(const spx_matrix *A);
+spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ subwarp primitives
  * The subwarp cooperative-group operations of Section 3.3 on 64-lane

@@ -141,3 +141,24 @@ extern "C" spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, 
     SPX_REQUIRE(x != y || A->nrows == 0, SPX_ERR_ARG, "spx_csr_spmv: x aliases y");
     return spmv_dispatch(*A, x, y, alpha, beta, stream);
 }
+
+extern "C" int64_t spx_csr_analysis_bytes(const spx_matrix *A)
+{
+    if (A == nullptr || A->fmt != SPX_CSR || A->nnz < 0) return 0;
+    return csr_partition_bytes(A->nnz);
+}
+
+extern "C" spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_csr_analyse"));
+    SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "spx_csr_analyse: matrix is not CSR");
+    SPX_REQUIRE(buf != nullptr, SPX_ERR_ARG, "spx_csr_analyse: null buffer");
+    SPX_REQUIRE((int64_t)bytes >= csr_partition_bytes(A->nnz), SPX_ERR_ARG,
+                "spx_csr_analyse: buffer of %zu bytes is smaller than the %lld needed", bytes,
+                (long long)csr_partition_bytes(A->nnz));
+    A->csr_part = nullptr;
+    if (A->nrows > 0) SPX_CHECK(csr_partition_launch(*A, static_cast<int32_t *>(buf), stream));
+    A->csr_part = static_cast<const int32_t *>(buf);
+    return SPX_OK;
+}

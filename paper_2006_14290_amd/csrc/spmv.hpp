@@ -11,7 +11,7 @@ spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alp
                          hipStream_t stream);
 
 constexpr int kCooThreads = 256;
-constexpr int kCooTiles = 8;                      // 64-entry tiles per wavefront chunk
+constexpr int kCooTiles = 4;                      // 64-entry tiles per wavefront chunk
 constexpr int kCooChunk = 64 * kCooTiles;          // entries per wavefront chunk
 constexpr int kEllThreads = 256;
 

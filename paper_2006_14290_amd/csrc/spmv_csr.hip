@@ -25,15 +25,21 @@
 namespace spx {
 
 // First index r in [lo, hi] with rowptr[r] >= key, assuming the answer lies in
-// [lo, hi]. Executed by one whole wavefront; every lane returns the answer.
-__device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t lo, int64_t hi, int64_t key)
+// [lo, hi]; *val receives rowptr[r]. Executed by one whole wavefront (64-ary
+// search: one dependent load per round); every lane returns the answer.
+__device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t lo, int64_t hi, int64_t key,
+                                    int32_t *val)
 {
     const int l = lane_id();
     while (hi - lo >= kWave) {
         const int64_t step = (hi - lo) / kWave;
         const int64_t p = lo + l * step;
-        const lane_mask_t m = ballot64(rowptr[p] >= key);
-        if (m & 1ull) return lo;  // rowptr[lo] >= key and the answer is >= lo
+        const int32_t v = rowptr[p];
+        const lane_mask_t m = ballot64(v >= key);
+        if (m & 1ull) {  // rowptr[lo] >= key and the answer is >= lo
+            *val = readlane(v, 0);
+            return lo;
+        }
         const int j = m ? __builtin_ctzll(m) : kWave;  // first probe at or above key
         const int64_t nlo = lo + (int64_t)(j - 1) * step + 1;
         const int64_t nhi = (j < kWave) ? lo + (int64_t)j * step : hi;
@@ -41,86 +47,138 @@ __device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t 
         hi = nhi;
     }
     const int64_t p = lo + l;
-    const bool pred = (p <= hi) && (rowptr[p] >= key);
-    const lane_mask_t m = ballot64(pred);
-    return m ? lo + __builtin_ctzll(m) : hi;
+    const int32_t v = (p <= hi) ? rowptr[p] : 0;
+    const lane_mask_t m = ballot64((p <= hi) && (v >= key));
+    const int j = m ? __builtin_ctzll(m) : (int)(hi - lo);
+    *val = readlane(v, j);
+    return lo + j;
 }
 
-template <typename V, typename X, bool kEpiDot>
-__global__ __launch_bounds__(kCsrThreads) void csr_spmv_kernel(
+// One work-group per tile of kTile nonzeros (XCD-remapped block id). The
+// group owns the rows that start inside its tile: it reads their bounds from
+// the precomputed partition (or finds them with two wavefront searches),
+// issues every value/column load of the pass before the first gather, stages
+// the products in LDS and reduces each row with an adaptive subwarp. Rows
+// longer than the rest of the pass continue in further passes, carrying their
+// partial sum in LDS.
+template <typename V, typename X, bool kEpiDot, int kThreads, int kTile>
+__global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     int32_t nrows, int64_t nnz, int64_t ntiles, int64_t grid_padded, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y,
-    X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials)
+    X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, const int32_t *__restrict__ part)
 {
     using A = X;  // accumulation type
-    __shared__ A prod[kCsrTile];
-    __shared__ int32_t s_rp[kCsrThreads + 1];
-    __shared__ int64_t s_bounds[2];
+    constexpr int kPer = kTile / kThreads;
+    __shared__ A prod[kTile];
+    __shared__ int32_t s_rp[kThreads + 1];
+    __shared__ int64_t s_b[4];
     __shared__ A s_carry;
-    __shared__ A s_dot[kCsrThreads / kWave];
+    __shared__ A s_dot[kThreads / kWave];
 
     const int64_t k = xcd_remap(blockIdx.x, grid_padded);
     if (k >= ntiles) return;
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
 
-    if (wid == 0) {
-        const int64_t ra = lower_bound_wave(rowptr, 0, nrows, k * kCsrTile);
-        if (lane_id() == 0) s_bounds[0] = ra;
-    } else if (wid == 1) {
-        const int64_t rb = (k == ntiles - 1) ? (int64_t)nrows : lower_bound_wave(rowptr, 0, nrows, (k + 1) * kCsrTile);
-        if (lane_id() == 0) s_bounds[1] = rb;
+    int64_t ra, rb, s, e;
+    if (part != nullptr) {
+        ra = part[2 * k];
+        s = part[2 * k + 1];
+        rb = part[2 * k + 2];
+        e = part[2 * k + 3];
+    } else {
+        if (wid == 0) {
+            int32_t v;
+            const int64_t r0 = lower_bound_wave(rowptr, 0, nrows, k * kTile, &v);
+            if (lane_id() == 0) {
+                s_b[0] = r0;
+                s_b[2] = v;
+            }
+        } else if (wid == 1) {
+            int32_t v = (int32_t)nnz;
+            const int64_t r1 = (k == ntiles - 1) ? (int64_t)nrows : lower_bound_wave(rowptr, 0, nrows, (k + 1) * kTile, &v);
+            if (lane_id() == 0) {
+                s_b[1] = r1;
+                s_b[3] = v;
+            }
+        }
+        __syncthreads();
+        ra = s_b[0];
+        rb = s_b[1];
+        s = s_b[2];
+        e = s_b[3];
     }
     if (tid == 0) s_carry = A(0);
-    __syncthreads();
-    const int64_t ra = s_bounds[0], rb = s_bounds[1];
-    const int64_t s = rowptr[ra], e = rowptr[rb];
 
     A dot_acc = A(0);
     int64_t r = ra;          // first row not yet written
     bool continued = false;  // row r holds a partial sum from an earlier pass
     int64_t w0 = s;
     while (true) {
-        const int64_t w1 = (e - w0 > kCsrTile) ? w0 + kCsrTile : e;
+        const int64_t w1 = (e - w0 > kTile) ? w0 + kTile : e;
         const bool last = (w1 == e);
-        const A carry_in = s_carry;  // written before the previous barrier
-        // stage products of this pass
+        __syncthreads();  // s_carry / prod / s_rp of the previous pass are consumed
+        const A carry_in = s_carry;
+        // every value and column load of the pass goes out before the first
+        // gather; the row pointers of the first row batch are fetched alongside
         const int cnt = (int)(w1 - w0);
-        for (int i = tid; i < cnt; i += kCsrThreads) {
-            const int64_t p = w0 + i;
-            prod[i] = widen(ld_stream(val + p)) * x[ld_stream(col + p)];
+        const int32_t *__restrict__ colw = col + w0;
+        const V *__restrict__ valw = val + w0;
+        int32_t cc[kPer];
+        V vv[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = tid + u * kThreads;
+            cc[u] = 0;
+            vv[u] = V(0);
+            if (i < cnt) {
+                cc[u] = ld_stream(colw + i);
+                vv[u] = ld_stream(valw + i);
+            }
         }
-        // rows of this pass, in batches of up to kCsrThreads rows
+        int64_t row_t = r + tid;
+        int32_t rp_t = 0, rp_t1 = 0;
+        if (row_t < rb) {
+            rp_t = rowptr[row_t];
+            rp_t1 = rowptr[row_t + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = tid + u * kThreads;
+            if (i < cnt) prod[i] = widen(vv[u]) * x[cc[u]];
+        }
+        // rows of this pass, in batches of up to kThreads rows
         bool first_batch = true;
+        bool cont_out = false;
         while (true) {
-            const int64_t row_t = r + tid;
-            int32_t rp_t = 0, rp_t1 = 0;
-            if (row_t < rb) {
-                rp_t = rowptr[row_t];
-                rp_t1 = rowptr[row_t + 1];
+            if (!first_batch) {
+                row_t = r + tid;
+                if (row_t < rb) {
+                    rp_t = rowptr[row_t];
+                    rp_t1 = rowptr[row_t + 1];
+                }
             }
             const bool touch = (row_t < rb) && (last || rp_t < w1);
-            const bool fin = touch && (last || rp_t1 <= w1);
             if (touch) {
                 if (tid == 0) s_rp[0] = rp_t;
                 s_rp[tid + 1] = rp_t1;
             }
             const int nb = __syncthreads_count(touch);
-            const int nfin = __syncthreads_count(fin);
             if (nb == 0) break;
-            // subwarp size: largest power of two with nb * size <= threads, capped at 64
-            int size = kCsrThreads / nb;
+            // every touching row ends inside the pass except possibly the last one
+            const int nfin = (last || s_rp[nb] <= w1) ? nb : nb - 1;
+            int size = kThreads / nb;
             size = size >= 64 ? 64 : (size >= 32 ? 32 : (size >= 16 ? 16 : (size >= 8 ? 8 : (size >= 4 ? 4 : (size >= 2 ? 2 : 1)))));
-            const int groups = kCsrThreads / size;
+            const int groups = kThreads / size;
             const int g = tid / size;
             const int sl = tid % size;
             for (int j0 = 0; j0 < nb; j0 += groups) {
                 const int j = j0 + g;
                 A sum = A(0);
                 if (j < nb) {
-                    const int64_t a = (s_rp[j] > w0 ? s_rp[j] : w0) - w0;
-                    const int64_t b = (s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - w0;
-                    for (int64_t p = a + sl; p < b; p += size) sum += prod[p];
+                    const int a = (int)((s_rp[j] > w0 ? s_rp[j] : w0) - w0);
+                    const int b = (int)((s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - w0);
+                    for (int p = a + sl; p < b; p += size) sum += prod[p];
                 }
                 sum = subwave_sum_dyn(sum, size);
                 if (j < nb && sl == 0) {
@@ -138,13 +196,13 @@ __global__ __launch_bounds__(kCsrThreads) void csr_spmv_kernel(
             }
             r += nfin;
             first_batch = false;
-            __syncthreads();
-            if (nfin < kCsrThreads) break;
+            cont_out = nfin < nb;
+            if (nfin < kThreads) break;
+            __syncthreads();  // s_rp is rewritten by the next batch
         }
-        continued = (r < rb) && (rowptr[r] < w1);
         if (last) break;
+        continued = cont_out;
         w0 = w1;
-        __syncthreads();
     }
     if constexpr (kEpiDot) {
         dot_acc = wave_sum(dot_acc);
@@ -152,10 +210,36 @@ __global__ __launch_bounds__(kCsrThreads) void csr_spmv_kernel(
         __syncthreads();
         if (tid == 0) {
             A t = A(0);
-            for (int w = 0; w < kCsrThreads / kWave; ++w) t += s_dot[w];
+            for (int w = 0; w < kThreads / kWave; ++w) t += s_dot[w];
             dot_partials[k] = t;
         }
     }
+}
+
+// One wavefront per tile boundary k in [0, ntiles]: the first row starting
+// at or after k*kCsrTile (nrows for the final boundary) and its offset.
+__global__ __launch_bounds__(256) void csr_partition_kernel(int32_t nrows, int64_t nnz, int64_t ntiles,
+                                                           const int32_t *__restrict__ rowptr,
+                                                           int32_t *__restrict__ part)
+{
+    const int64_t k = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (k > ntiles) return;
+    int32_t v = (int32_t)nnz;
+    int64_t r = nrows;
+    if (k < ntiles) r = lower_bound_wave(rowptr, 0, nrows, k * kCsrTile, &v);
+    if (lane_id() == 0) {
+        part[2 * k] = (int32_t)r;
+        part[2 * k + 1] = v;
+    }
+}
+
+spx_status csr_partition_launch(const spx_matrix &A, int32_t *part, hipStream_t stream)
+{
+    const int64_t ntiles = csr_tiles(A.nnz);
+    csr_partition_kernel<<<(unsigned)ceil_div(ntiles + 1, 256 / kWave), 256, 0, stream>>>(A.nrows, A.nnz, ntiles,
+                                                                                          A.rowptr, part);
+    SPX_LAUNCHED();
+    return SPX_OK;
 }
 
 template <typename V, typename X>
@@ -166,11 +250,12 @@ spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
     const int64_t grid = pad_to_xcds(ntiles);
     const V *val = static_cast<const V *>(A.vals);
     if (dot_with)
-        csr_spmv_kernel<V, X, true><<<dim3((unsigned)grid), dim3(kCsrThreads), 0, stream>>>(
-            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials);
+        csr_spmv_kernel<V, X, true, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(
+            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials,
+            A.csr_part);
     else
-        csr_spmv_kernel<V, X, false><<<dim3((unsigned)grid), dim3(kCsrThreads), 0, stream>>>(
-            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, nullptr, nullptr);
+        csr_spmv_kernel<V, X, false, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(
+            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, nullptr, nullptr, A.csr_part);
     SPX_LAUNCHED();
     return SPX_OK;
 }

@@ -56,14 +56,14 @@ __global__ __launch_bounds__(256) void scale_kernel(int64_t n, X *__restrict__ y
 }
 
 // Complete segment (row r, sum) of chunk [c0, c1): atomics if it may share
-// its row with a neighbouring chunk.
+// its row with a neighbouring chunk. row_before / row_after are the rows of
+// the entries just outside the chunk (-1 if none).
 template <typename X, bool kAccumulate>
-__device__ __forceinline__ void coo_write(int32_t r, X sum, bool chunk_start_seg, bool chunk_end_seg, int64_t c0,
-                                          int64_t c1, int64_t nnz, const int32_t *__restrict__ row,
-                                          X *__restrict__ y, X alpha, X beta)
+__device__ __forceinline__ void coo_write(int32_t r, X sum, bool chunk_start_seg, bool chunk_end_seg,
+                                          int32_t row_before, int32_t row_after, X *__restrict__ y, X alpha, X beta)
 {
-    const bool left = chunk_start_seg && c0 > 0 && row[c0 - 1] == r;
-    const bool right = chunk_end_seg && c1 < nnz && row[c1] == r;
+    const bool left = chunk_start_seg && row_before == r;
+    const bool right = chunk_end_seg && row_after == r;
     if (left || right) {
         unsafeAtomicAdd(y + r, alpha * sum);
     } else if (kAccumulate) {
@@ -87,21 +87,28 @@ __global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, in
     const int64_t c0 = chunk * kCooChunk;
     const int64_t c1 = (c0 + kCooChunk < nnz) ? c0 + kCooChunk : nnz;
 
-    // issue every load of the chunk first (memory-level parallelism)
+    // issue every load of the chunk first (memory-level parallelism); the
+    // chunk base is wave-uniform so the loads use scalar base + 32-bit offsets
+    const int32_t *__restrict__ rowc = row + c0;
+    const int32_t *__restrict__ colc = col + c0;
+    const V *__restrict__ valc = val + c0;
+    const int cn = (int)(c1 - c0);
     int32_t r[kCooTiles], c[kCooTiles];
     X p[kCooTiles];
 #pragma unroll
     for (int t = 0; t < kCooTiles; ++t) {
-        const int64_t e = c0 + t * kWave + lane;
+        const int o = t * kWave + lane;
         r[t] = -1;
         c[t] = 0;
         p[t] = X(0);
-        if (e < c1) {
-            r[t] = ld_stream(row + e);
-            c[t] = ld_stream(col + e);
-            p[t] = widen(ld_stream(val + e));
+        if (o < cn) {
+            r[t] = ld_stream(rowc + o);
+            c[t] = ld_stream(colc + o);
+            p[t] = widen(ld_stream(valc + o));
         }
     }
+    const int32_t row_before = c0 > 0 ? row[c0 - 1] : -1;
+    const int32_t row_after = c1 < nnz ? row[c1] : -1;
 #pragma unroll
     for (int t = 0; t < kCooTiles; ++t)
         if (r[t] >= 0) p[t] *= x[c[t]];
@@ -120,11 +127,13 @@ __global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, in
         // the carried segment ends before this tile: write it
         if (carry_row >= 0 && r0 != carry_row) {
             if (lane == 0)
-                coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, false, c0, c1, nnz, row, y, alpha, beta);
+                coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, false, row_before, row_after, y, alpha,
+                                          beta);
             carry_row = -1;
         }
         const bool merged = (carry_row >= 0);  // lane 0 continues the carried segment
-        const int32_t rprev = valid ? (e > 0 ? row[e - 1] : -1) : 0;
+        const int32_t first_prev = (t == 0) ? row_before : readlane(r[t > 0 ? t - 1 : 0], kWave - 1);
+        const int32_t rprev = wave_shift_up1(rr, first_prev);
         const bool head = !valid || lane == 0 || rr != rprev;
         X v = p[t];
         if (lane == 0 && merged) v += carry_val;
@@ -134,24 +143,24 @@ __global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, in
         if (!kAccumulate && valid && e == nnz - 1)
             for (int32_t g = rr + 1; g < nrows; ++g) y[g] = scaled(y[g], beta);
         const X s = wave_segscan(v, head);
-        // last valid lane of the tile and the segment it closes are carried on
-        const int64_t tail_e = (c1 - tb < kWave) ? c1 - tb - 1 : kWave - 1;
+        // the last valid lane of the tile and the segment it closes are carried on
+        const int tail_e = (c1 - tb < kWave) ? (int)(c1 - tb - 1) : kWave - 1;
         const lane_mask_t heads = ballot64(head && lane > 0);
-        const bool seg0 = (heads & ((lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull)) == 0;  // segment holds lane 0
+        const lane_mask_t upto_me = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
+        const bool seg0 = (heads & upto_me & ~1ull) == 0;  // my segment holds lane 0
         const bool start_seg = seg0 && (t == 0 || (merged && carry_start));
         // a lane closes a segment when the next lane starts a new one
-        const int32_t rn = (lane < tail_e) ? row[e + 1] : -2;
+        const int32_t rn = wave_shift_down1(rr, -2);
         if (lane < tail_e && rn != rr)
-            coo_write<X, kAccumulate>(rr, s, start_seg, false, c0, c1, nnz, row, y, alpha, beta);
-        // carry the tile's last segment
-        carry_row = readlane(rr, (int)tail_e);
-        carry_val = readlane(s, (int)tail_e);
-        const lane_mask_t upto_tail = (tail_e == 63) ? ~0ull : ((2ull << tail_e) - 1);
+            coo_write<X, kAccumulate>(rr, s, start_seg, false, row_before, row_after, y, alpha, beta);
+        carry_row = readlane(rr, tail_e);
+        carry_val = readlane(s, tail_e);
+        const lane_mask_t upto_tail = (tail_e == kWave - 1) ? ~0ull : ((2ull << tail_e) - 1);
         const bool last_seg_has_lane0 = (heads & upto_tail & ~1ull) == 0;
         carry_start = last_seg_has_lane0 && (t == 0 || (merged && carry_start));
     }
     if (carry_row >= 0 && lane == 0)
-        coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, c0, c1, nnz, row, y, alpha, beta);
+        coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, row_before, row_after, y, alpha, beta);
 }
 
 template <typename V, typename X>

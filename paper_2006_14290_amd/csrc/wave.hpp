@@ -208,6 +208,20 @@ __device__ __forceinline__ T wave_segscan(T v, bool head)
     return v;
 }
 
+// Whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane i
+// receives lane i-1 (resp. i+1); the lane with no source receives `fill`.
+__device__ __forceinline__ int wave_shift_up1(int v, int fill)
+{
+    const int s = __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);
+    return lane_id() == 0 ? fill : s;
+}
+
+__device__ __forceinline__ int wave_shift_down1(int v, int fill)
+{
+    const int s = __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
+    return lane_id() == kWave - 1 ? fill : s;
+}
+
 // Value held by lane src (wave-uniform src) as a scalar broadcast.
 template <typename T>
 __device__ __forceinline__ T readlane(T v, int src);

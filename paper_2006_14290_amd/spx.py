@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspx.so")
+LIB_PATH = os.environ.get("SPX_LIBRARY") or os.path.join(_HERE, "libspx.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2006_14290_amd/build.py (or __graft_entry__.build())")
@@ -47,6 +47,7 @@ class MatrixDesc(ctypes.Structure):
         ("rowidx", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
         ("coo_nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("max_row_len", ctypes.c_int32),
         ("ell_ld", ctypes.c_int64), ("ell_col", ctypes.c_void_p), ("ell_val", ctypes.c_void_p),
+        ("csr_part", ctypes.c_void_p),
     ]
 
 
@@ -66,6 +67,8 @@ _sig("spx_last_error", [], ctypes.c_char_p)
 _sig("spx_version", [], ctypes.c_int32)
 _sig("spx_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
+_sig("spx_csr_analysis_bytes", [_MP], ctypes.c_int64)
+_sig("spx_csr_analyse", [_MP, _vp, ctypes.c_size_t, _vp])
 _sig("spx_subwarp_sum", [_vp, _vp, _i64, _i32, _i32, _vp])
 _sig("spx_subwarp_vote", [_vp, _vp, _vp, _vp, _i64, _i32, _vp])
 _sig("spx_wave_segscan", [_vp, _vp, _vp, _i64, _vp])
@@ -112,6 +115,7 @@ class Matrix:
     ell_col: Optional[torch.Tensor] = None
     ell_val: Optional[torch.Tensor] = None
     max_row_len: int = 0
+    csr_part: Optional[torch.Tensor] = None
     _desc: MatrixDesc = field(default=None, repr=False)
 
     def desc(self) -> MatrixDesc:
@@ -121,6 +125,7 @@ class Matrix:
                                                 _ptr(self.vals))
         d.coo_nnz, d.ell_width, d.max_row_len, d.ell_ld = self.coo_nnz, self.ell_width, self.max_row_len, self.ell_ld
         d.ell_col, d.ell_val = _ptr(self.ell_col), _ptr(self.ell_val)
+        d.csr_part = _ptr(self.csr_part)
         self._desc = d
         return d
 
@@ -171,6 +176,17 @@ def hyb_from_host(n, K, ld, ecol, eval_, row, col, val, dtype: int = F64, device
                   rowidx=torch.from_numpy(np.ascontiguousarray(row, np.int32)).to(device),
                   colidx=torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(device),
                   vals=_dev_vals(val, dtype, device))
+
+
+def csr_analyse(A: Matrix, stream=None) -> Matrix:
+    """Compute the CSR partition once (stored in A.csr_part, reused by every
+    later product on A)."""
+    d = A.desc()
+    nbytes = _lib.spx_csr_analysis_bytes(ctypes.byref(d))
+    buf = torch.empty(max(1, nbytes // 4), dtype=torch.int32, device=A.rowptr.device)
+    check(_lib.spx_csr_analyse(ctypes.byref(d), _ptr(buf), nbytes, _stream(stream)), "spx_csr_analyse")
+    A.csr_part = buf
+    return A
 
 
 # ------------------------------------------------------------------ SpMV

@@ -1,6 +1,8 @@
 """GPU parity of the SpMV kernels (CSR, COO, ELL, HYB; float64, float32,
 binary16 values) against the CPU oracle's Dot2-accurate product, through the
 C ABI."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -101,6 +103,30 @@ def test_spmv_alpha_beta(fmt, dtype):
     assert np.all(np.isfinite(y))
 
 
+@pytest.mark.parametrize("mi", range(len(MATS)), ids=IDS)
+def test_csr_analysed_partition(mi):
+    """The precomputed partition gives the same tiles as the in-kernel search,
+    hence bitwise the same result, and it matches the oracle."""
+    name, make = MATS[mi]
+    A = make()
+    Ad = spx.csr_from_host(A, spx.F64)
+    x = S.uniform_vector(A.n, seed=4)
+    xd = dev(x)
+    y0 = host(spx.spmv(Ad, xd))
+    spx.csr_analyse(Ad)
+    part = host(Ad.csr_part)
+    # partition pins: tile k starts at the first row whose offset is >= 4096*k
+    ntiles = max(1, -(-A.nnz // 4096))
+    rp = A.rowptr.astype(np.int64)
+    for k in range(ntiles + 1):
+        row = A.n if k == ntiles else int(np.searchsorted(rp, 4096 * k, side="left"))
+        assert part[2 * k] == row and part[2 * k + 1] == rp[row], k
+    y1 = host(spx.spmv(Ad, xd))
+    np.testing.assert_array_equal(y0.view(np.uint64), y1.view(np.uint64))
+    yref, absax = O.csr_spmv_dot2(A, x)
+    assert_spmv_f64(y1, yref, absax)
+
+
 def test_csr_bitwise_reproducible():
     A = S.zipf_matrix(30000, seed=8)
     Ad = spx.csr_from_host(A, spx.F64)
@@ -123,13 +149,21 @@ def test_stencil_closed_form_on_gpu():
 
 def test_error_paths():
     A = spx.csr_from_host(S.poisson2d(8))
-    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    x = torch.zeros(A.nrows, dtype=torch.float64, device="cuda")
     with pytest.raises(spx.SpxError, match="aliases"):
         spx.spmv(A, x, x)
     bad = spx.csr_from_host(S.poisson2d(8))
     bad.dtype = 7
-    with pytest.raises(spx.SpxError, match="val_type"):
-        spx.spmv(bad, x.clone().float(), torch.empty(A.n, device="cuda"))
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    st = spx._lib.spx_spmv(ctypes.byref(bad.desc()), x.data_ptr(), y.data_ptr(), 1.0, 0.0, None)
+    assert st == spx.ERR_ARG and b"val_type" in spx._lib.spx_last_error()
+    coo = spx.coo_from_host(4, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.ones(2))
+    coo.rowidx = None
+    st = spx._lib.spx_spmv(ctypes.byref(coo.desc()), x.data_ptr(), y.data_ptr(), 1.0, 0.0, None)
+    assert st == spx.ERR_ARG
+    with pytest.raises(spx.SpxError, match="not CSR"):
+        spx.spmv(spx.coo_from_host(4, np.array([0], np.int32), np.array([0], np.int32), np.ones(1)),
+                 x[:4], y[:4], csr_only=True)
 
 
 # ------------------------------------------------------------------ full size
