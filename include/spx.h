@@ -132,6 +132,113 @@ spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alph
 int64_t spx_csr_analysis_bytes(const spx_matrix *A);
 spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------ format conversion
+ * Conversions between the formats of Section 1 (Csr <-> Coo, Csr -> Ell,
+ * Csr -> Hybrid, Ell -> Csr, Hybrid -> Csr; other pairs go through Csr).
+ * Index arrays are produced exactly and values are copied bit for bit, so
+ * a round trip X -> Csr -> X reproduces the input.
+ *
+ * spx_convert_plan (BLOCKING: synchronizes `stream`) fills the shape fields
+ * of *dst (fmt, val_type, nrows, ncols, nnz, coo_nnz, ell_width, ell_ld;
+ * pointers are set to NULL) and the workspace size. ell_width: -1 chooses it
+ * (Ell: the longest row; Hybrid: the width K that minimises stored bytes
+ * n*K*(sv+4) + (entries beyond K)*(sv+8), smallest K on ties), otherwise the
+ * given width (Ell: SPX_ERR_FORMAT if a row is longer). ell_ld: 0 = nrows.
+ * The caller then allocates dst's arrays (CSR: rowptr[nrows+1], colidx and
+ * vals [nnz]; COO: rowidx/colidx/vals [nnz]; ELL: ell_col/ell_val
+ * [ell_width*ell_ld]; HYB: both, the COO part with coo_nnz entries) and a
+ * workspace of ws_bytes, and calls spx_convert (asynchronous). Ell input
+ * must be in canonical form (entries in ascending column order, padding last).
+ * Errors: SPX_ERR_ARG (unsupported pair, missing arrays, small workspace),
+ * SPX_ERR_FORMAT, SPX_ERR_HIP. */
+spx_status spx_convert_plan(const spx_matrix *src, int32_t dst_fmt, int32_t ell_width, int64_t ell_ld,
+                            spx_matrix *dst, size_t *ws_bytes, hipStream_t stream);
+spx_status spx_convert(const spx_matrix *src, spx_matrix *dst, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Value cast for mixed precision: dst receives src's values (src->val_type
+ * must be SPX_F64) rounded to nearest even into dst->val_type (SPX_F32 or
+ * SPX_F16); dst has the same format and shape as src and its own value
+ * arrays (index arrays may be shared with src). NaN becomes the target's
+ * quiet NaN with the sign kept. BLOCKING. Returns SPX_ERR_RANGE if a finite
+ * value overflowed to infinity (the values are still written). */
+spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hipStream_t stream);
+
+/* ------------------------------------------------------------ Krylov solvers
+ * Solve A x = b to the relative residual ||b - A x||_2 <= tol * ||b||_2
+ * (Section 4 runs CG; Section 1 lists CG, BiCG-type and GMRES solvers with
+ * a block-Jacobi preconditioner, of which the scalar, 1x1-block case is
+ * provided). float64 only (A->val_type == SPX_F64); b and x are device
+ * float64 vectors of nrows entries; x holds the initial guess unless
+ * opts->x0_zero. Any matrix format; CSR uses the fused product+dot kernel.
+ *
+ * Every scalar of the iteration stays on the device; `check_every`
+ * iterations are captured once in a hipGraph and replayed, and the host
+ * reads the solver state only between replays. Convergence of the recursive
+ * residual is confirmed with the true residual b - A x (a miss restarts the
+ * recurrences from it). All solves are BLOCKING: they return when done,
+ * having ordered themselves after earlier work on `stream` and made `stream`
+ * wait for them. info (may not be NULL) receives iterations (CG, BiCGSTAB:
+ * full steps; GMRES: Arnoldi steps), products with A, GMRES restart cycles,
+ * the recursive and true relative residuals and the device time.
+ *
+ * Errors: SPX_ERR_ARG (bad descriptor, dtype, sizes, workspace too small),
+ * SPX_ERR_ZERO_DIAG (Jacobi with a zero/missing/non-finite diagonal entry),
+ * SPX_ERR_BREAKDOWN (CG: p'Ap <= 0; BiCGSTAB: rhat'r = 0, rhat'v = 0, t't = 0
+ * or omega = 0), SPX_ERR_NONFINITE (NaN/Inf in a residual norm),
+ * SPX_ERR_NOT_CONVERGED (maxit reached; x holds the last iterate). */
+typedef enum { SPX_SOLVER_CG = 0, SPX_SOLVER_BICGSTAB = 1, SPX_SOLVER_GMRES = 2 } spx_solver;
+
+typedef struct {
+    double tol;          /* relative residual target (e.g. 1e-10)                 */
+    int32_t maxit;       /* iteration limit (GMRES: Arnoldi steps)                 */
+    int32_t restart;     /* GMRES restart length m (1..62), e.g. 30                */
+    int32_t precond;     /* 0 none, 1 scalar Jacobi M = diag(A)                    */
+    int32_t x0_zero;     /* 1: start from x = 0 (x is write-only)                  */
+    int32_t check_every; /* iterations per graph replay between host checks (0 = 16) */
+    int32_t reserved;
+} spx_solve_opts;
+
+typedef struct {
+    int32_t status, iters, spmv_count, outer_iters;
+    double relres_recursive, relres_true, device_ms;
+} spx_solve_info;
+
+/* Device workspace (bytes) a solve on A with these options needs. */
+spx_status spx_solve_workspace(int32_t solver, const spx_matrix *A, const spx_solve_opts *opts, size_t *bytes);
+
+spx_status spx_cg_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
+                        size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
+
+spx_status spx_bicgstab_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
+                              size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
+
+spx_status spx_gmres_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
+                           size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------ mixed-precision iterative refinement
+ * Solve A x = b to ||b - A x|| <= tol ||b|| in float64 with float32 inner
+ * solves: x = 0; repeat { r = b - A64 x (float64); stop if small; s =
+ * ||r||_inf; d = CG(Alow, fl32(r / s)) to relative residual inner_tol in
+ * float32 (vectors and sums; SPX_F16 values are widened to float32 before
+ * each multiply-add); x += s d }. A64: SPX_F64 values; Alow: the same
+ * pattern with SPX_F32 or SPX_F16 values (see spx_cast_values), same or
+ * different format. info->iters = total inner CG iterations, outer_iters =
+ * refinement steps. BLOCKING; errors as the solvers above, plus
+ * SPX_ERR_NOT_CONVERGED after max_outer steps. */
+typedef struct {
+    double tol;          /* float64 relative residual target, e.g. 1e-10  */
+    double inner_tol;    /* inner CG relative residual, e.g. 1e-3         */
+    int32_t max_outer;   /* refinement steps limit                        */
+    int32_t inner_maxit; /* inner CG iteration limit per step             */
+    int32_t check_every; /* inner iterations per graph replay (0 = 16)    */
+    int32_t reserved;
+} spx_ir_opts;
+
+spx_status spx_ir_workspace(const spx_matrix *A64, const spx_matrix *Alow, size_t *bytes);
+spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const double *b, double *x,
+                        const spx_ir_opts *opts, void *ws, size_t ws_bytes, spx_solve_info *info,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------------ subwarp primitives
  * The subwarp cooperative-group operations of Section 3.3 on 64-lane
  * wavefronts, over n device values (n a multiple of 64):

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "convert.hpp"
 #include "spmv.hpp"
 #include "spmv_csr.hpp"
 
@@ -160,5 +161,56 @@ extern "C" spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hi
     A->csr_part = nullptr;
     if (A->nrows > 0) SPX_CHECK(csr_partition_launch(*A, static_cast<int32_t *>(buf), stream));
     A->csr_part = static_cast<const int32_t *>(buf);
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_convert_plan(const spx_matrix *src, int32_t dst_fmt, int32_t ell_width, int64_t ell_ld,
+                                       spx_matrix *dst, size_t *ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(src, "spx_convert_plan"));
+    SPX_REQUIRE(dst != nullptr && ws_bytes != nullptr, SPX_ERR_ARG, "spx_convert_plan: null output");
+    SPX_REQUIRE(dst_fmt >= SPX_CSR && dst_fmt <= SPX_HYB, SPX_ERR_ARG, "spx_convert_plan: bad format %d", dst_fmt);
+    return convert_plan(*src, dst_fmt, ell_width, ell_ld, dst, ws_bytes, stream);
+}
+
+extern "C" spx_status spx_convert(const spx_matrix *src, spx_matrix *dst, void *ws, size_t ws_bytes,
+                                  hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(src, "spx_convert"));
+    SPX_CHECK(check_matrix(dst, "spx_convert (dst)"));
+    SPX_REQUIRE(src->nrows == dst->nrows && src->ncols == dst->ncols && src->val_type == dst->val_type,
+                SPX_ERR_ARG, "spx_convert: dst shape or dtype differs from src");
+    SPX_REQUIRE(dst->fmt != SPX_COO || dst->nnz == src->nnz, SPX_ERR_ARG, "spx_convert: dst nnz differs from plan");
+    return convert_run(*src, *dst, ws, ws_bytes, stream);
+}
+
+extern "C" spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(src, "spx_cast_values"));
+    SPX_CHECK(check_matrix(dst, "spx_cast_values (dst)"));
+    SPX_REQUIRE(src->val_type == SPX_F64, SPX_ERR_ARG, "spx_cast_values: source must be SPX_F64");
+    SPX_REQUIRE(dst->val_type == SPX_F32 || dst->val_type == SPX_F16, SPX_ERR_ARG,
+                "spx_cast_values: target must be SPX_F32 or SPX_F16");
+    SPX_REQUIRE(src->fmt == dst->fmt && src->nrows == dst->nrows && src->nnz == dst->nnz &&
+                    src->ell_width == dst->ell_width && src->ell_ld == dst->ell_ld && src->coo_nnz == dst->coo_nnz,
+                SPX_ERR_ARG, "spx_cast_values: dst shape differs from src");
+    int64_t ovf = 0, o = 0;
+    if (src->fmt == SPX_CSR || src->fmt == SPX_COO) {
+        SPX_CHECK(cast_values(static_cast<const double *>(src->vals), src->nnz, dst->val_type, dst->vals, &o, stream));
+        ovf += o;
+    } else {
+        SPX_CHECK(cast_values(static_cast<const double *>(src->ell_val), (int64_t)src->ell_width * src->ell_ld,
+                              dst->val_type, dst->ell_val, &o, stream));
+        ovf += o;
+        if (src->fmt == SPX_HYB) {
+            SPX_CHECK(cast_values(static_cast<const double *>(src->vals), src->coo_nnz, dst->val_type, dst->vals, &o,
+                                  stream));
+            ovf += o;
+        }
+    }
+    SPX_REQUIRE(ovf == 0, SPX_ERR_RANGE, "spx_cast_values: %lld finite values overflowed", (long long)ovf);
     return SPX_OK;
 }

@@ -1,0 +1,202 @@
+// krylov.hpp -- device-resident state and deterministic reductions of the
+// Krylov solvers.
+//
+// Every iteration's scalars (rho, alpha, beta, omega, ...) live in a KState
+// in device memory, so an iteration is a fixed sequence of kernel launches
+// with no host round trip and can be captured in a hipGraph. Reductions are
+// two-stage and deterministic: each work-group writes a partial to a fixed
+// slot; the group that arrives last (ticket counter) sums the partials in a
+// fixed order and updates the scalars (one "finish" op per reduction). A
+// flag in the state stops every later kernel of a captured block of
+// iterations as soon as the solve has converged or failed.
+#pragma once
+
+#include "common.hpp"
+#include "wave.hpp"
+
+namespace spx {
+
+enum KFlag : int32_t {
+    kRunning = 0,
+    kConverged = 1,   // recursive residual below tolerance
+    kBreakdown = 2,
+    kNonfinite = 3,
+    kMaxit = 4,
+    kHalfConverged = 5,  // BiCGSTAB: ||s|| below tolerance
+    kZeroRhs = 6,
+    kCycleEnd = 7,       // GMRES: cycle finished (lucky breakdown or estimate converged)
+};
+
+enum KOp : int32_t {
+    kOpNone = 0,
+    kOpCgInit,     // t0 = b.b, t1 = r.z, t2 = r.r
+    kOpCgAlpha,    // t0 = p.q
+    kOpCgRho,      // t0 = r.z, t1 = r.r
+    kOpBiInit,     // t0 = b.b, t1 = r.r
+    kOpBiAlpha,    // t0 = rhat.v
+    kOpBiS,        // t0 = s.s
+    kOpBiOmega,    // t0 = t.s, t1 = t.t
+    kOpBiRho,      // t0 = r.r, t1 = rhat.r
+    kOpNorm2,      // t0 = w.w -> tmp[0]
+    kOpCgRestart,  // t0 = r.z: restart the recurrences from the current r
+    kOpBiRestart,  // t0 = r.r: restart BiCGSTAB with rhat = r
+};
+
+constexpr int kMaxDots = 64;  // GMRES restart length + 2 (multi-dot width)
+
+struct KState {
+    double rho, rho0, alpha, beta, omega, bb, tol2, rr;
+    double tmp[4];
+    int32_t flag, iters, maxit, spmv_count;
+    int32_t restart_j, jend, pad0, pad1;
+    uint32_t ticket[8];
+    double dots[2 * kMaxDots];  // GMRES multi-dot results
+};
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Scalar update of a reduction, run by one thread of the last work-group.
+__device__ inline void finish_op(int op, const double *t, KState *st)
+{
+    switch (op) {
+    case kOpCgInit:
+        st->bb = t[0];
+        st->rho = t[1];
+        st->rr = t[2];
+        if (!finite(t[0]) || !finite(t[2])) st->flag = kNonfinite;
+        else if (t[0] == 0.0) st->flag = kZeroRhs;
+        else if (t[2] <= st->tol2 * t[0]) st->flag = kConverged;
+        break;
+    case kOpCgAlpha:
+        if (!finite(t[0])) st->flag = kNonfinite;
+        else if (t[0] <= 0.0) st->flag = kBreakdown;
+        else st->alpha = st->rho / t[0];
+        break;
+    case kOpCgRho:
+        st->iters += 1;
+        st->spmv_count += 1;
+        st->rr = t[1];
+        if (!finite(t[1]) || !finite(t[0])) {
+            st->flag = kNonfinite;
+        } else if (t[1] <= st->tol2 * st->bb) {
+            st->flag = kConverged;
+        } else {
+            st->beta = t[0] / st->rho;
+            st->rho = t[0];
+            if (st->iters >= st->maxit) st->flag = kMaxit;
+        }
+        break;
+    case kOpBiInit:
+        st->bb = t[0];
+        st->rr = t[1];
+        st->rho = t[1];  // rhat = r, so rhat.r = r.r
+        st->beta = 0.0;  // first direction p = r (p = v = 0 initially)
+        st->omega = 1.0;
+        st->alpha = 1.0;
+        if (!finite(t[0]) || !finite(t[1])) st->flag = kNonfinite;
+        else if (t[0] == 0.0) st->flag = kZeroRhs;
+        else if (t[1] <= st->tol2 * t[0]) st->flag = kConverged;
+        else if (t[1] == 0.0) st->flag = kBreakdown;
+        break;
+    case kOpBiAlpha:
+        st->spmv_count += 1;
+        if (!finite(t[0])) st->flag = kNonfinite;
+        else if (t[0] == 0.0) st->flag = kBreakdown;
+        else st->alpha = st->rho / t[0];
+        break;
+    case kOpBiS:
+        st->rr = t[0];
+        if (!finite(t[0])) st->flag = kNonfinite;
+        else if (t[0] <= st->tol2 * st->bb) {
+            st->flag = kHalfConverged;
+            st->iters += 1;
+        }
+        break;
+    case kOpBiOmega:
+        st->spmv_count += 1;
+        if (!finite(t[1]) || !finite(t[0])) st->flag = kNonfinite;
+        else if (t[1] == 0.0) st->flag = kBreakdown;
+        else st->omega = t[0] / t[1];
+        break;
+    case kOpBiRho:
+        st->iters += 1;
+        st->rr = t[0];
+        if (!finite(t[0]) || !finite(t[1])) {
+            st->flag = kNonfinite;
+        } else if (t[0] <= st->tol2 * st->bb) {
+            st->flag = kConverged;
+        } else if (st->omega == 0.0 || t[1] == 0.0) {
+            st->flag = kBreakdown;
+        } else {
+            st->beta = (t[1] / st->rho) * (st->alpha / st->omega);
+            st->rho0 = st->rho;
+            st->rho = t[1];
+            if (st->iters >= st->maxit) st->flag = kMaxit;
+        }
+        break;
+    case kOpNorm2:
+        st->tmp[0] = t[0];
+        break;
+    case kOpBiRestart:
+        st->rho = t[0];
+        st->rr = t[0];
+        st->beta = 0.0;
+        st->omega = 1.0;
+        st->alpha = 1.0;
+        st->flag = !finite(t[0]) ? kNonfinite : (t[0] == 0.0 ? kBreakdown : kRunning);
+        break;
+    case kOpCgRestart:
+        st->rho = t[0];
+        st->flag = finite(t[0]) ? kRunning : kNonfinite;
+        break;
+    default: break;
+    }
+}
+
+// Work-group sum of v (all threads must call; result valid in thread 0).
+template <typename T, int kThreads>
+__device__ __forceinline__ T block_sum(T v, T *s_red)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0) s_red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    T t = T(0);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w];
+    __syncthreads();
+    return t;
+}
+
+// Two-stage deterministic reduction of NV values per work-group. Each group
+// passes its (already block-reduced, valid in thread 0) values; they are
+// stored in partials[k * nparts + part]. The last group to arrive sums every
+// partial in a fixed order and applies finish_op. Returns nothing; every
+// thread of every group must call it.
+template <typename T, int NV, int kThreads>
+__device__ void reduce_finish(const T (&v)[NV], T *__restrict__ partials, int64_t nparts, int64_t part,
+                              KState *st, int ticket_slot, int op)
+{
+    __shared__ int s_last;
+    __shared__ T s_red[kThreads / kWave];
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) partials[k * nparts + part] = v[k];
+        __threadfence();
+        const uint32_t t = atomicAdd(&st->ticket[ticket_slot], 1u);
+        s_last = (t == (uint32_t)(nparts - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double tot[NV > 3 ? NV : 3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < NV; ++k) {
+        T acc = T(0);
+        for (int64_t i = threadIdx.x; i < nparts; i += kThreads) acc += partials[k * nparts + i];
+        tot[k] = (double)block_sum<T, kThreads>(acc, s_red);
+    }
+    if (threadIdx.x == 0) {
+        finish_op(op, tot, st);
+        st->ticket[ticket_slot] = 0u;
+    }
+}
+
+}  // namespace spx

@@ -19,6 +19,7 @@
 // Bytes moved (the roofline unit): nnz*(sv+4) + (nrows+1)*4 + ncols*sx +
 // nrows*sx (+ nrows*sx when beta != 0).
 #include "common.hpp"
+#include "krylov.hpp"
 #include "spmv_csr.hpp"
 #include "wave.hpp"
 
@@ -61,19 +62,23 @@ __device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t 
 // the products in LDS and reduces each row with an adaptive subwarp. Rows
 // longer than the rest of the pass continue in further passes, carrying their
 // partial sum in LDS.
-template <typename V, typename X, bool kEpiDot, int kThreads, int kTile>
+// kEpi: 0 = plain product; 1 = also sum_i y_i*w_i; 2 = also sum_i y_i*w_i
+// and sum_i y_i*y_i. With a solver state the sums are reduced across tiles
+// (deterministically) and finished by `op`; a set state flag skips the launch.
+template <typename V, typename X, int kEpi, int kThreads, int kTile>
 __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     int32_t nrows, int64_t nnz, int64_t ntiles, int64_t grid_padded, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y,
-    X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, const int32_t *__restrict__ part)
+    X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, const int32_t *__restrict__ part,
+    KState *__restrict__ st, int op, int ticket)
 {
+    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
     using A = X;  // accumulation type
     constexpr int kPer = kTile / kThreads;
     __shared__ A prod[kTile];
     __shared__ int32_t s_rp[kThreads + 1];
     __shared__ int64_t s_b[4];
     __shared__ A s_carry;
-    __shared__ A s_dot[kThreads / kWave];
 
     const int64_t k = xcd_remap(blockIdx.x, grid_padded);
     if (k >= ntiles) return;
@@ -110,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     }
     if (tid == 0) s_carry = A(0);
 
-    A dot_acc = A(0);
+    A dot_acc = A(0), dot_acc2 = A(0);
     int64_t r = ra;          // first row not yet written
     bool continued = false;  // row r holds a partial sum from an earlier pass
     int64_t w0 = s;
@@ -188,7 +193,8 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
                         X out = alpha * sum;
                         if (beta != X(0)) out += beta * y[row];
                         y[row] = out;
-                        if constexpr (kEpiDot) dot_acc += out * dot_with[row];
+                        if constexpr (kEpi >= 1) dot_acc += out * dot_with[row];
+                        if constexpr (kEpi >= 2) dot_acc2 += out * out;
                     } else {
                         s_carry = sum;  // the one row continuing into the next pass
                     }
@@ -204,14 +210,15 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
         continued = cont_out;
         w0 = w1;
     }
-    if constexpr (kEpiDot) {
-        dot_acc = wave_sum(dot_acc);
-        if (lane_id() == 0) s_dot[wid] = dot_acc;
-        __syncthreads();
-        if (tid == 0) {
-            A t = A(0);
-            for (int w = 0; w < kThreads / kWave; ++w) t += s_dot[w];
-            dot_partials[k] = t;
+    if constexpr (kEpi > 0) {
+        __shared__ A s_red[kThreads / kWave];
+        A v[kEpi];
+        v[0] = block_sum<A, kThreads>(dot_acc, s_red);
+        if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<A, kThreads>(dot_acc2, s_red);
+        if (st != nullptr) {
+            reduce_finish<A, kEpi, kThreads>(v, dot_partials, ntiles, k, st, ticket, op);
+        } else if (tid == 0) {
+            for (int q = 0; q < kEpi; ++q) dot_partials[q * ntiles + k] = v[q];
         }
     }
 }
@@ -244,27 +251,28 @@ spx_status csr_partition_launch(const spx_matrix &A, int32_t *part, hipStream_t 
 
 template <typename V, typename X>
 spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, const X *dot_with,
-                           X *dot_partials, hipStream_t stream)
+                           X *dot_partials, hipStream_t stream, int epi, KState *st, int op, int ticket)
 {
     const int64_t ntiles = csr_tiles(A.nnz);
     const int64_t grid = pad_to_xcds(ntiles);
     const V *val = static_cast<const V *>(A.vals);
-    if (dot_with)
-        csr_spmv_kernel<V, X, true, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(
-            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials,
-            A.csr_part);
-    else
-        csr_spmv_kernel<V, X, false, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(
-            A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, nullptr, nullptr, A.csr_part);
+#define SPX_CSR_LAUNCH(E)                                                                                        \
+    csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(                   \
+        A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials, A.csr_part, \
+        st, op, ticket)
+    if (epi == 2) SPX_CSR_LAUNCH(2);
+    else if (epi == 1) SPX_CSR_LAUNCH(1);
+    else SPX_CSR_LAUNCH(0);
+#undef SPX_CSR_LAUNCH
     SPX_LAUNCHED();
     return SPX_OK;
 }
 
 template spx_status csr_spmv_launch<double, double>(const spx_matrix &, const double *, double *, double, double,
-                                                    const double *, double *, hipStream_t);
+                                                    const double *, double *, hipStream_t, int, KState *, int, int);
 template spx_status csr_spmv_launch<float, float>(const spx_matrix &, const float *, float *, float, float,
-                                                  const float *, float *, hipStream_t);
+                                                  const float *, float *, hipStream_t, int, KState *, int, int);
 template spx_status csr_spmv_launch<_Float16, float>(const spx_matrix &, const float *, float *, float, float,
-                                                     const float *, float *, hipStream_t);
+                                                     const float *, float *, hipStream_t, int, KState *, int, int);
 
 }  // namespace spx

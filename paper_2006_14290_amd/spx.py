@@ -69,6 +69,37 @@ _sig("spx_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_analysis_bytes", [_MP], ctypes.c_int64)
 _sig("spx_csr_analyse", [_MP, _vp, ctypes.c_size_t, _vp])
+_sig("spx_convert_plan", [_MP, _i32, _i32, _i64, _MP, ctypes.POINTER(ctypes.c_size_t), _vp])
+_sig("spx_convert", [_MP, _MP, _vp, ctypes.c_size_t, _vp])
+_sig("spx_cast_values", [_MP, _MP, _vp])
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("spmv_count", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("relres_recursive", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IrOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("inner_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_GMRES = 0, 1, 2
+_SOP = ctypes.POINTER(SolveOpts)
+_SIP = ctypes.POINTER(SolveInfo)
+_sig("spx_solve_workspace", [_i32, _MP, _SOP, ctypes.POINTER(ctypes.c_size_t)])
+for _nm in ("spx_cg_solve", "spx_bicgstab_solve", "spx_gmres_solve"):
+    _sig(_nm, [_MP, _vp, _vp, _SOP, _vp, ctypes.c_size_t, _SIP, _vp])
+_sig("spx_ir_workspace", [_MP, _MP, ctypes.POINTER(ctypes.c_size_t)])
+_sig("spx_ir_solve", [_MP, _MP, _vp, _vp, ctypes.POINTER(IrOpts), _vp, ctypes.c_size_t, _SIP, _vp])
 _sig("spx_subwarp_sum", [_vp, _vp, _i64, _i32, _i32, _vp])
 _sig("spx_subwarp_vote", [_vp, _vp, _vp, _vp, _i64, _i32, _vp])
 _sig("spx_wave_segscan", [_vp, _vp, _vp, _i64, _vp])
@@ -189,6 +220,56 @@ def csr_analyse(A: Matrix, stream=None) -> Matrix:
     return A
 
 
+# ------------------------------------------------------------------ conversion
+def convert(A: Matrix, fmt: int, ell_width: int = -1, ell_ld: int = 0, stream=None) -> Matrix:
+    """Convert A to `fmt` on the device (plan: blocking size query; then an
+    asynchronous conversion into freshly allocated tensors)."""
+    src = A.desc()
+    shape = MatrixDesc()
+    ws = ctypes.c_size_t(0)
+    check(_lib.spx_convert_plan(ctypes.byref(src), fmt, ell_width, ell_ld, ctypes.byref(shape), ctypes.byref(ws),
+                                _stream(stream)), "spx_convert_plan")
+    dev = (A.rowptr if A.rowptr is not None else (A.ell_col if A.ell_col is not None else A.colidx)).device
+    vt = _VAL_DTYPE[A.dtype]
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = Matrix(fmt, A.dtype, shape.nrows, shape.ncols, shape.nnz, coo_nnz=shape.coo_nnz,
+                 ell_width=shape.ell_width, ell_ld=shape.ell_ld)
+    if fmt == CSR:
+        out.rowptr = torch.empty(shape.nrows + 1, **i32)
+        out.colidx = torch.empty(shape.nnz, **i32)
+        out.vals = torch.empty(shape.nnz, dtype=vt, device=dev)
+    elif fmt == COO:
+        out.rowidx = torch.empty(shape.nnz, **i32)
+        out.colidx = torch.empty(shape.nnz, **i32)
+        out.vals = torch.empty(shape.nnz, dtype=vt, device=dev)
+    else:
+        out.ell_col = torch.empty(shape.ell_width * shape.ell_ld, **i32)
+        out.ell_val = torch.empty(shape.ell_width * shape.ell_ld, dtype=vt, device=dev)
+        if fmt == HYB:
+            out.rowidx = torch.empty(shape.coo_nnz, **i32)
+            out.colidx = torch.empty(shape.coo_nnz, **i32)
+            out.vals = torch.empty(shape.coo_nnz, dtype=vt, device=dev)
+    wst = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    check(_lib.spx_convert(ctypes.byref(A.desc()), ctypes.byref(out.desc()), _ptr(wst), ws.value, _stream(stream)),
+          "spx_convert")
+    out._ws = wst  # keep the workspace alive until the stream has consumed it
+    return out
+
+
+def cast_values(A: Matrix, dtype: int, stream=None) -> Matrix:
+    """Copy of A (sharing its index arrays) with values rounded to dtype."""
+    out = Matrix(A.fmt, dtype, A.nrows, A.ncols, A.nnz, rowptr=A.rowptr, rowidx=A.rowidx, colidx=A.colidx,
+                 coo_nnz=A.coo_nnz, ell_width=A.ell_width, ell_ld=A.ell_ld, ell_col=A.ell_col,
+                 max_row_len=A.max_row_len, csr_part=A.csr_part)
+    vt = _VAL_DTYPE[dtype]
+    if A.vals is not None:
+        out.vals = torch.empty(A.vals.numel(), dtype=vt, device=A.vals.device)
+    if A.ell_val is not None:
+        out.ell_val = torch.empty(A.ell_val.numel(), dtype=vt, device=A.ell_val.device)
+    check(_lib.spx_cast_values(ctypes.byref(A.desc()), ctypes.byref(out.desc()), _stream(stream)), "spx_cast_values")
+    return out
+
+
 # ------------------------------------------------------------------ SpMV
 def spmv(A: Matrix, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
          stream=None, csr_only: bool = False) -> torch.Tensor:
@@ -202,6 +283,77 @@ def spmv(A: Matrix, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: fl
     check(fn(ctypes.byref(A.desc()), _ptr(x), _ptr(y), float(alpha), float(beta), _stream(stream)),
           "spx_csr_spmv" if csr_only else "spx_spmv")
     return y
+
+
+# ------------------------------------------------------------------ solvers
+_SOLVER_FN = {SOLVER_CG: "spx_cg_solve", SOLVER_BICGSTAB: "spx_bicgstab_solve", SOLVER_GMRES: "spx_gmres_solve"}
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """A reusable device workspace of at least nbytes (grown on demand)."""
+    key = str(device)
+    t = _ws_cache.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = t
+    return t
+
+
+def solve(solver: int, A: Matrix, b: torch.Tensor, x: Optional[torch.Tensor] = None, tol: float = 1e-10,
+          maxit: int = 10000, precond: int = 0, restart: int = 30, check_every: int = 0, stream=None):
+    """Solve A x = b on the device (blocking). Returns (x, info dict); raises
+    SpxError on failure unless the failure is NOT_CONVERGED/BREAKDOWN, which
+    are reported in info['status'] with x holding the last iterate."""
+    opts = SolveOpts(tol, maxit, restart, precond, 1 if x is None else 0, check_every, 0)
+    if x is None:
+        x = torch.empty_like(b)
+    d = A.desc()
+    nbytes = ctypes.c_size_t(0)
+    check(_lib.spx_solve_workspace(solver, ctypes.byref(d), ctypes.byref(opts), ctypes.byref(nbytes)),
+          "spx_solve_workspace")
+    ws = _workspace(nbytes.value, b.device)
+    info = SolveInfo()
+    st = getattr(_lib, _SOLVER_FN[solver])(ctypes.byref(d), _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                                             ws.numel(), ctypes.byref(info), _stream(stream))
+    if st not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE):
+        check(st, _SOLVER_FN[solver])
+    out = info.as_dict()
+    out["status"] = st
+    out["error"] = _lib.spx_last_error().decode() if st != OK else ""
+    return x, out
+
+
+def cg_solve(A, b, x=None, **kw):
+    return solve(SOLVER_CG, A, b, x, **kw)
+
+
+def bicgstab_solve(A, b, x=None, **kw):
+    return solve(SOLVER_BICGSTAB, A, b, x, **kw)
+
+
+def gmres_solve(A, b, x=None, **kw):
+    return solve(SOLVER_GMRES, A, b, x, **kw)
+
+
+def ir_solve(A64: Matrix, Alow: Matrix, b: torch.Tensor, tol: float = 1e-10, inner_tol: float = 1e-3,
+             max_outer: int = 50, inner_maxit: int = 20000, check_every: int = 0, stream=None):
+    """Mixed-precision iterative refinement (blocking). Returns (x, info)."""
+    x = torch.empty_like(b)
+    opts = IrOpts(tol, inner_tol, max_outer, inner_maxit, check_every, 0)
+    d64, dlo = A64.desc(), Alow.desc()
+    nbytes = ctypes.c_size_t(0)
+    check(_lib.spx_ir_workspace(ctypes.byref(d64), ctypes.byref(dlo), ctypes.byref(nbytes)), "spx_ir_workspace")
+    ws = _workspace(nbytes.value, b.device)
+    info = SolveInfo()
+    st = _lib.spx_ir_solve(ctypes.byref(d64), ctypes.byref(dlo), _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                           ws.numel(), ctypes.byref(info), _stream(stream))
+    if st not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE):
+        check(st, "spx_ir_solve")
+    out = info.as_dict()
+    out["status"] = st
+    out["error"] = _lib.spx_last_error().decode() if st != OK else ""
+    return x, out
 
 
 # ------------------------------------------------------------------ primitives

@@ -1,0 +1,250 @@
+"""GPU Krylov solvers (CG, BiCGSTAB, GMRES(m), mixed-precision IR) against the
+oracle: the true relative residual is recomputed on the host with the
+oracle's Dot2 residual, the solution error is bounded through the
+condition number, iteration counts are compared with the oracle's, and the
+status codes are forced by input."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2006_14290_amd import synth as S
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+spx = pytest.importorskip("paper_2006_14290_amd.spx")
+
+
+def _problem(A, seed=0):
+    xs = S.uniform_vector(A.n, seed=seed, purpose="xstar")
+    b, _ = O.csr_spmv_dot2(A, xs)
+    return xs, b
+
+
+def _true_relres(A, b, x):
+    _, rn = O.residual(A, b, x)
+    return rn / np.linalg.norm(b)
+
+
+def _fmt(A, fmt):
+    Ad = spx.csr_from_host(A)
+    return Ad if fmt == "csr" else spx.convert(Ad, {"coo": spx.COO, "ell": spx.ELL, "hyb": spx.HYB}[fmt])
+
+
+def _kappa_poisson(N, c):
+    j = np.arange(1, N + 1)
+    lam = 2 * (1 - np.cos(np.pi * j / (N + 1)))
+    return sum(ci * lam.max() for ci in c) / sum(ci * lam.min() for ci in c)
+
+
+# ------------------------------------------------------------------ CG
+@pytest.mark.parametrize("fmt", ["csr", "coo", "ell", "hyb"])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_cg_poisson64(fmt, precond):
+    """2D 5-point 64x64 (n = 4096, nnz = 20,224), tol 1e-10."""
+    A = S.poisson2d(64)
+    xs, b = _problem(A)
+    xo, io = O.cg(A, b, tol=1e-10, precond=precond)
+    x, info = spx.cg_solve(_fmt(A, fmt), dev(b), tol=1e-10, precond=precond, check_every=8)
+    x = host(x)
+    assert info["status"] == spx.OK, info
+    rr = _true_relres(A, b, x)
+    assert rr <= 1e-10, rr
+    assert abs(info["relres_true"] - rr) <= 1e-3 * rr + 1e-15
+    # rounding-dependent count: within 10% (+5) of the oracle's
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+    kappa = _kappa_poisson(64, (1, 1))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+
+
+def test_cg_jacobi_nonconstant_diag_and_x0():
+    A = S.spd_diag_dominant(20000, seed=2)
+    xs, b = _problem(A, 3)
+    x0 = S.uniform_vector(A.n, seed=9)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), x=dev(x0), tol=1e-10, precond=1)
+    assert info["status"] == spx.OK
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    xo, io = O.cg(A, b, tol=1e-10, precond=1, x0=x0)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
+
+
+def test_cg_bitwise_reproducible():
+    A = S.poisson3d_7pt(20, 1, 1, 0.01)
+    xs, b = _problem(A)
+    Ad = spx.csr_from_host(A)
+    x1, i1 = spx.cg_solve(Ad, dev(b), tol=1e-10, precond=1)
+    x2, i2 = spx.cg_solve(Ad, dev(b), tol=1e-10, precond=1)
+    assert i1["iters"] == i2["iters"]
+    np.testing.assert_array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
+
+
+def test_cg_status_codes():
+    # indefinite: p'Ap <= 0
+    A = S.from_dense(np.diag([1.0, -1.0, 2.0]))
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(np.array([1.0, 1.0, 0.0])), tol=1e-12)
+    assert info["status"] == spx.ERR_BREAKDOWN
+    P = S.poisson2d(16)
+    xs, b = _problem(P)
+    x, info = spx.cg_solve(spx.csr_from_host(P), dev(b), tol=1e-10, maxit=3)
+    assert info["status"] == spx.ERR_NOT_CONVERGED and info["iters"] == 3
+    bn = b.copy()
+    bn[5] = np.nan
+    x, info = spx.cg_solve(spx.csr_from_host(P), dev(bn), tol=1e-10)
+    assert info["status"] == spx.ERR_NONFINITE
+    Z = S.from_dense(np.diag([1.0, 0.0, 2.0]), keep_zeros=True)
+    with pytest.raises(spx.SpxError, match="ZERO_DIAG"):
+        spx.cg_solve(spx.csr_from_host(Z), dev(np.ones(3)), precond=1)
+    x, info = spx.cg_solve(spx.csr_from_host(P), dev(np.zeros(P.n)), tol=1e-10)
+    assert info["status"] == spx.OK and info["iters"] == 0 and np.all(host(x) == 0)
+    I = S.from_dense(np.eye(50))
+    bi = S.uniform_vector(50, seed=1)
+    x, info = spx.cg_solve(spx.csr_from_host(I), dev(bi), tol=1e-12)
+    assert info["status"] == spx.OK and info["iters"] == 1
+    np.testing.assert_array_equal(host(x), bi)
+
+
+@pytest.mark.timeout(600)
+def test_cg_full_aniso_128():
+    """Anisotropic 7-point 128^3 (coefficients 1/1/0.01, n = 2,097,152), CG +
+    Jacobi to 1e-10; checked through the oracle's true residual and the
+    condition-number bound on the error."""
+    print("case cg aniso 128^3", flush=True)
+    N = 128
+    A = S.poisson3d_7pt(N, 1, 1, 0.01)
+    assert A.n == 2097152 and A.nnz == 14581760
+    xs, b = _problem(A)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), tol=1e-10, precond=1, maxit=5000)
+    x = host(x)
+    assert info["status"] == spx.OK, info
+    rr = _true_relres(A, b, x)
+    assert rr <= 1e-10
+    kappa = _kappa_poisson(N, (1, 1, 0.01))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+    bound = int(np.ceil(np.sqrt(kappa) / 2 * np.log(2 / 1e-10)))
+    assert info["iters"] <= bound
+    print("cg aniso 128^3:", info, flush=True)
+
+
+# ------------------------------------------------------------------ BiCGSTAB
+@pytest.mark.parametrize("fmt", ["csr", "coo", "hyb"])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_bicgstab_convdiff(fmt, precond):
+    A = S.convdiff3d_upwind(24)
+    xs, b = _problem(A)
+    x, info = spx.bicgstab_solve(_fmt(A, fmt), dev(b), tol=1e-10, precond=precond)
+    x = host(x)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, x) <= 1e-10
+    xo, io = O.bicgstab(A, b, tol=1e-10, precond=precond)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+
+
+def test_bicgstab_identity_and_status():
+    I = S.from_dense(np.eye(40))
+    bi = S.uniform_vector(40, seed=2)
+    x, info = spx.bicgstab_solve(spx.csr_from_host(I), dev(bi), tol=1e-12)
+    assert info["status"] == spx.OK and info["iters"] == 1 and info["spmv_count"] == 1
+    np.testing.assert_array_equal(host(x), bi)
+    A = S.convdiff3d_upwind(10)
+    xs, b = _problem(A)
+    x, info = spx.bicgstab_solve(spx.csr_from_host(A), dev(b), tol=1e-10, maxit=2)
+    assert info["status"] == spx.ERR_NOT_CONVERGED
+
+
+@pytest.mark.timeout(600)
+def test_bicgstab_full_convdiff_128():
+    print("case bicgstab convdiff 128^3", flush=True)
+    A = S.convdiff3d_upwind(128)
+    xs, b = _problem(A)
+    x, info = spx.bicgstab_solve(spx.csr_from_host(A), dev(b), tol=1e-10, precond=1, maxit=5000)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    print("bicgstab convdiff 128^3:", info, flush=True)
+
+
+# ------------------------------------------------------------------ GMRES
+@pytest.mark.parametrize("fmt", ["csr", "ell"])
+@pytest.mark.parametrize("precond", [0, 1])
+@pytest.mark.parametrize("m", [30, 5])
+def test_gmres_convdiff(fmt, precond, m):
+    A = S.convdiff3d_upwind(16)
+    xs, b = _problem(A)
+    x, info = spx.gmres_solve(_fmt(A, fmt), dev(b), tol=1e-10, precond=precond, restart=m)
+    x = host(x)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, x) <= 1e-10
+    xo, io = O.gmres(A, b, tol=1e-10, precond=precond, restart=m)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+
+
+def test_gmres_full_space_and_identity():
+    rng = np.random.default_rng(4)
+    n = 20
+    Ad = rng.standard_normal((n, n)) + 8 * np.eye(n)
+    A = S.from_dense(Ad)
+    b = rng.standard_normal(n)
+    x, info = spx.gmres_solve(spx.csr_from_host(A), dev(b), tol=1e-12, restart=n)
+    assert info["status"] == spx.OK and info["iters"] <= n
+    xd = np.linalg.solve(Ad, b)
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= np.linalg.cond(Ad) * 1e-12 * 4
+    I = S.from_dense(np.eye(30))
+    x, info = spx.gmres_solve(spx.csr_from_host(I), dev(b[:20].repeat(2)[:30]), tol=1e-12)
+    assert info["status"] == spx.OK and info["iters"] == 1
+
+
+@pytest.mark.timeout(600)
+def test_gmres_full_convdiff_128():
+    print("case gmres convdiff 128^3", flush=True)
+    A = S.convdiff3d_upwind(128)
+    xs, b = _problem(A)
+    x, info = spx.gmres_solve(spx.csr_from_host(A), dev(b), tol=1e-10, precond=1, restart=30, maxit=5000)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    print("gmres convdiff 128^3:", info, flush=True)
+
+
+# ------------------------------------------------------------------ IR
+@pytest.mark.parametrize("low", ["f32", "f16"])
+@pytest.mark.parametrize("fmt", ["csr", "ell"])
+def test_ir_poisson(low, fmt):
+    N = 24
+    A = S.poisson3d_7pt(N)
+    xs, b = _problem(A)
+    A64 = _fmt(A, fmt)
+    Alow = spx.cast_values(A64, spx.DTYPE_NAMES[low])
+    x, info = spx.ir_solve(A64, Alow, dev(b), tol=1e-10, inner_tol=1e-3)
+    x = host(x)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, x) <= 1e-10
+    lv, _ = O.cast_values(A.val, low)
+    xo, io = O.ir(A, lv.astype(np.float32), b, tol=1e-10, inner_tol=1e-3)
+    kappa = _kappa_poisson(N, (1, 1, 1))
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+    assert abs(info["outer_iters"] - io["outer_iters"]) <= 2
+
+
+@pytest.mark.timeout(900)
+def test_ir_full_192_vs_fp64_cg():
+    """7-point Poisson 192^3 (n = 7,077,888): FP32 and FP16-value IR reach a
+    float64 true residual of 1e-10 and agree with plain float64 CG."""
+    print("case ir 192^3", flush=True)
+    N = 192
+    A = S.poisson3d_7pt(N)
+    xs, b = _problem(A)
+    A64 = spx.csr_from_host(A)
+    bd = dev(b)
+    x64, i64 = spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
+    assert i64["status"] == spx.OK
+    x64 = host(x64)
+    assert _true_relres(A, b, x64) <= 1e-10
+    kappa = _kappa_poisson(N, (1, 1, 1))
+    for low in (spx.F32, spx.F16):
+        Alow = spx.cast_values(A64, low)
+        x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
+        x = host(x)
+        assert info["status"] == spx.OK, info
+        assert _true_relres(A, b, x) <= 1e-10
+        assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 2 * kappa * 1e-10
+        print("ir 192^3", low, info, "fp64 cg", i64, flush=True)
