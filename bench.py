@@ -60,6 +60,90 @@ def time_launches(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps
 
 
+def cg_iter_bytes(n, nnz, sv, precond):
+    """Algorithmic bytes of one CG iteration: the CSR product plus 9 (no
+    preconditioner) or 11 (Jacobi) vector passes of n values."""
+    return csr_bytes(n, nnz, sv, sv) + (11 if precond else 9) * n * sv
+
+
+def bench_cg_small(spx, S, O, torch, dev, nsolves):
+    """2D 5-point 64x64 (n = 4096, nnz = 20,224), unpreconditioned CG to 1e-10
+    relative residual, solved `nsolves` times back to back (blocking calls);
+    latency is the host wall clock of each call."""
+    A = S.poisson2d(64)
+    xs = S.uniform_vector(A.n, seed=0, purpose="xstar")
+    b, _ = O.csr_spmv_dot2(A, xs)
+    Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    bd = torch.from_numpy(b).to(dev)
+    for _ in range(3):
+        spx.cg_solve(Ad, bd, tol=1e-10)
+    torch.cuda.synchronize()
+    lat, iters = [], 0
+    t0 = time.perf_counter()
+    for _ in range(nsolves):
+        t1 = time.perf_counter()
+        x, info = spx.cg_solve(Ad, bd, tol=1e-10)
+        lat.append(time.perf_counter() - t1)
+        iters = info["iters"]
+        assert info["status"] == 0 and info["relres_true"] <= 1e-10, info
+    tot = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    return {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
+            "relres_true": info["relres_true"]}
+
+
+def bench_solvers(spx, S, O, torch, dev):
+    """Krylov solvers at full size: CG+Jacobi on the anisotropic 7-point 128^3
+    grid, BiCGSTAB and GMRES(30) + Jacobi on the upwind convection-diffusion
+    128^3 grid, and mixed-precision IR (float32 / binary16 values) against
+    plain float64 CG on the 7-point 192^3 grid; all to 1e-10."""
+    out = {}
+
+    def prob(A):
+        xs = S.uniform_vector(A.n, seed=0, purpose="xstar")
+        b, _ = O.csr_spmv_dot2(A, xs)
+        return torch.from_numpy(b).to(dev)
+
+    A = S.poisson3d_7pt(128, 1, 1, 0.01)
+    bd = prob(A)
+    Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+    x, info = spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+    it_us = 1e3 * info["device_ms"] / max(info["iters"], 1)
+    out["cg_jacobi_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
+                                 "us_per_iter": round(it_us, 2),
+                                 "GBs": round(cg_iter_bytes(A.n, A.nnz, 8, True) / it_us / 1e3, 1),
+                                 "relres_true": info["relres_true"]}
+    del Ad, A
+    A = S.convdiff3d_upwind(128)
+    bd = prob(A)
+    Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    for nm, fn in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve), ("gmres30_jacobi_convdiff128", spx.gmres_solve)):
+        fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+        x, info = fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+        out[nm] = {"ms": round(info["device_ms"], 2), "iters": info["iters"], "spmv": info["spmv_count"],
+                   "relres_true": info["relres_true"]}
+    del Ad, A
+    A = S.poisson3d_7pt(192)
+    bd = prob(A)
+    A64 = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
+    x, info = spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
+    t64 = info["device_ms"]
+    out["cg_fp64_poisson192"] = {"ms": round(t64, 2), "iters": info["iters"], "relres_true": info["relres_true"]}
+    x64 = x.clone()
+    for nm, low in (("ir_fp32_poisson192", spx.F32), ("ir_fp16v_poisson192", spx.F16)):
+        Alow = spx.cast_values(A64, low)
+        spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
+        x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
+        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+        out[nm] = {"ms": round(info["device_ms"], 2), "inner_iters": info["iters"], "outer": info["outer_iters"],
+                   "speedup_vs_fp64": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
+                   "rel_err_vs_fp64_cg": err}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +152,8 @@ def main():
     ap.add_argument("--grid", type=int, default=100, help="27-point grid edge (100 -> n = 1e6)")
     ap.add_argument("--sweep", action="store_true", help="also time COO/ELL/HYB and float32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="time only this kernel (for profiling runs)")
+    ap.add_argument("--solvers", action="store_true", help="also time the full-size Krylov solvers")
+    ap.add_argument("--cg-solves", type=int, default=50, help="solves of the 64x64 CG latency run (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -141,6 +226,11 @@ def main():
             del Ms, Xs, Ys
             torch.cuda.empty_cache()
 
+    import oracle as O  # inputs (b = A x*) and the CPU baseline only
+
+    cg_small = bench_cg_small(spx, S, O, torch, dev, args.cg_solves) if args.cg_solves > 0 else None
+    solvers = bench_solvers(spx, S, O, torch, dev) if args.solvers else None
+
     cpu = None
     if not args.no_cpu:
         import oracle as O
@@ -180,6 +270,8 @@ def main():
                      "frac": round(r["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "csr_spmv_kernel<double,double,false>", "bytes_per_launch": b},
         "sweep": {k: {"GBs": round(v["GBs"], 2), "ms": round(v["ms"], 5)} for k, v in results.items()},
+        "cg_poisson64": cg_small,
+        "solvers": solvers,
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
     }

@@ -239,6 +239,88 @@ spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const dou
                         const spx_ir_opts *opts, void *ws, size_t ws_bytes, spx_solve_info *info,
                         hipStream_t stream);
 
+/* ------------------------------------------------------------ batched CG and the solve server
+ * Many independent float64 CSR systems advanced by ONE persistent kernel:
+ * each resident work-group takes a system from an atomic counter and runs
+ * CG on it by itself (product, updates and fixed-order reductions inside the
+ * group), so a system's iterates are bitwise the same alone or in any batch.
+ * Unpreconditioned CG from x = 0 to ||b - A x|| <= tol ||b|| (true residual
+ * confirmed). */
+typedef struct {
+    int32_t n;              /* rows (square system)                        */
+    int32_t reserved0;
+    int64_t nnz;
+    const int32_t *rowptr;  /* DEVICE CSR, float64 values                  */
+    const int32_t *colidx;
+    const double *vals;
+    const double *b;        /* DEVICE right-hand side                      */
+    double *x;              /* DEVICE solution (written)                   */
+    double tol;
+    int32_t maxit;
+    int32_t status;         /* out: spx_status of this system              */
+    int32_t iters;          /* out                                         */
+    int32_t spmv_count;     /* out                                         */
+    double relres_true;     /* out                                         */
+} spx_batch_system;
+
+/* Workspace for spx_cg_batch (3 vectors per system + the slot table). */
+spx_status spx_cg_batch_workspace(const spx_batch_system *sys, int32_t count, size_t *bytes);
+
+/* Solve sys[0..count) (host array of descriptors; outputs written back).
+ * BLOCKING. Returns SPX_OK if every system converged, else the first failing
+ * system's status (each sys[i].status tells). */
+spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Continuous-batching server. Requests carry HOST arrays (kept alive by the
+ * caller until the ticket completes); the server copies them into its HBM
+ * pool (one allocation of hbm_budget_bytes, made at creation) when a slot and
+ * memory are free, keeps each system and its CG state resident, and advances
+ * all admitted systems together, tick after tick, in the persistent batched
+ * kernel captured in a hipGraph; admission and retirement happen between
+ * ticks. A finished request's solution is copied to x_out. */
+typedef struct spx_server spx_server;
+
+typedef struct {
+    int32_t device;          /* HIP device of the server                        */
+    int32_t max_slots;       /* concurrently resident systems                   */
+    size_t hbm_budget_bytes; /* device memory for matrices and Krylov vectors   */
+    int32_t iters_per_tick;  /* CG iterations per system per tick (0 = adaptive) */
+    int32_t tick_us;         /* adaptive budget: target tick length (0 = 2000)  */
+} spx_server_config;
+
+typedef struct {
+    int32_t n;
+    int32_t solver;          /* SPX_SOLVER_CG                                   */
+    int64_t nnz;
+    const int32_t *rowptr;   /* HOST CSR, float64, canonical                    */
+    const int32_t *colidx;
+    const double *vals;
+    const double *b;         /* HOST                                           */
+    double *x_out;           /* HOST, written on completion (may be NULL)       */
+    double tol;              /* e.g. 1e-8                                       */
+    int32_t maxit;           /* 0 = no limit                                    */
+    int32_t reserved;
+} spx_request;
+
+typedef struct {
+    int64_t submitted, completed, queued, active, rejected, ticks;
+    size_t pool_bytes_total, pool_bytes_in_use, pool_bytes_peak;
+} spx_server_stats;
+
+spx_status spx_server_create(const spx_server_config *cfg, spx_server **out);
+/* Queues a request. SPX_ERR_BUDGET if it can never fit the HBM budget. */
+spx_status spx_serve_submit(spx_server *server, const spx_request *req, uint64_t *ticket);
+/* SPX_PENDING while queued or running; afterwards the request's status, and
+ * *info (if not NULL) with iterations, residuals and device_ms = submit-to-done
+ * latency in milliseconds. */
+spx_status spx_serve_poll(spx_server *server, uint64_t ticket, spx_solve_info *info);
+spx_status spx_serve_wait(spx_server *server, uint64_t ticket, double timeout_s, spx_solve_info *info);
+/* Cancels a queued or running request (its status becomes SPX_CANCELLED). */
+spx_status spx_serve_cancel(spx_server *server, uint64_t ticket);
+spx_status spx_server_get_stats(spx_server *server, spx_server_stats *stats);
+/* Stops the worker (queued requests are cancelled) and frees everything. */
+spx_status spx_server_destroy(spx_server *server);
+
 /* ------------------------------------------------------------ subwarp primitives
  * The subwarp cooperative-group operations of Section 3.3 on 64-lane
  * wavefronts, over n device values (n a multiple of 64):

@@ -5,10 +5,10 @@
 // in device memory, so an iteration is a fixed sequence of kernel launches
 // with no host round trip and can be captured in a hipGraph. Reductions are
 // two-stage and deterministic: each work-group writes a partial to a fixed
-// slot; the group that arrives last (ticket counter) sums the partials in a
-// fixed order and updates the scalars (one "finish" op per reduction). A
-// flag in the state stops every later kernel of a captured block of
-// iterations as soon as the solve has converged or failed.
+// slot; a one-work-group finish kernel sums the partials in a fixed order and
+// updates the scalars (one "finish" op per reduction). A flag in the state
+// stops every later kernel of a captured block of iterations as soon as the
+// solve has converged or failed.
 #pragma once
 
 #include "common.hpp"
@@ -167,36 +167,51 @@ __device__ __forceinline__ T block_sum(T v, T *s_red)
     return t;
 }
 
-// Two-stage deterministic reduction of NV values per work-group. Each group
-// passes its (already block-reduced, valid in thread 0) values; they are
-// stored in partials[k * nparts + part]. The last group to arrive sums every
-// partial in a fixed order and applies finish_op. Returns nothing; every
-// thread of every group must call it.
-template <typename T, int NV, int kThreads>
-__device__ void reduce_finish(const T (&v)[NV], T *__restrict__ partials, int64_t nparts, int64_t part,
-                              KState *st, int ticket_slot, int op)
+// Two-stage deterministic reduction, stage 1: each work-group stores its NV
+// block sums (valid in thread 0) to partials[k * nparts + part]. No fence:
+// stage 2 (finish_kernel) is a separate launch, and the kernel boundary
+// makes the partials visible across XCDs. (A last-arriving-group finish
+// would need a device-scope release per work-group, which on gfx950 is an
+// L2 write-back plus invalidate for every group.)
+template <typename T, int NV>
+__device__ __forceinline__ void write_partials(const T (&v)[NV], T *__restrict__ partials, int64_t nparts,
+                                               int64_t part)
 {
-    __shared__ int s_last;
-    __shared__ T s_red[kThreads / kWave];
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         for (int k = 0; k < NV; ++k) partials[k * nparts + part] = v[k];
-        __threadfence();
-        const uint32_t t = atomicAdd(&st->ticket[ticket_slot], 1u);
-        s_last = (t == (uint32_t)(nparts - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    double tot[NV > 3 ? NV : 3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < NV; ++k) {
+}
+
+// Ops that belong to an iteration are skipped once the solve has stopped
+// (their producing kernels skipped too); setup ops always run.
+__device__ __forceinline__ bool op_runs_when_stopped(int op)
+{
+    return op == kOpCgInit || op == kOpBiInit || op == kOpNorm2 || op == kOpCgRestart || op == kOpBiRestart;
+}
+
+constexpr int kFinThreads = 256;
+
+// Stage 2: one work-group sums nv rows of partials in a fixed order and
+// applies the scalar update `op`.
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void finish_kernel(const T *__restrict__ partials, int64_t nparts, int nv,
+                                                            KState *st, int op)
+{
+    if (st->flag != kRunning && !op_runs_when_stopped(op)) return;
+    __shared__ T s_red[kFinThreads / kWave];
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nv; ++k) {
         T acc = T(0);
-        for (int64_t i = threadIdx.x; i < nparts; i += kThreads) acc += partials[k * nparts + i];
-        tot[k] = (double)block_sum<T, kThreads>(acc, s_red);
+        for (int64_t i = threadIdx.x; i < nparts; i += kFinThreads) acc += partials[k * nparts + i];
+        tot[k] = (double)block_sum<T, kFinThreads>(acc, s_red);
     }
-    if (threadIdx.x == 0) {
-        finish_op(op, tot, st);
-        st->ticket[ticket_slot] = 0u;
-    }
+    if (threadIdx.x == 0) finish_op(op, tot, st);
+}
+
+template <typename T>
+inline spx_status launch_finish(const T *partials, int64_t nparts, int nv, KState *st, int op, hipStream_t stream)
+{
+    finish_kernel<T><<<1, kFinThreads, 0, stream>>>(partials, nparts, nv, st, op);
+    return hipGetLastError() == hipSuccess ? SPX_OK : SPX_ERR_HIP;
 }
 
 }  // namespace spx

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_init_kernel(int64_t n, const X
     __shared__ X s_red[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X bb = X(0), rr = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_init_kernel(int64_t n, const X
         }
     }
     X vals[2] = {block_sum<X, kVecThreads>(bb, s_red), block_sum<X, kVecThreads>(rr, s_red)};
-    reduce_finish<X, 2, kVecThreads>(vals, partials, gridDim.x, blockIdx.x, st, 4, kOpBiInit);
+    write_partials<X, 2>(vals, partials, gridDim.x, blockIdx.x);
 }
 
 // restart from the current (true) residual r: rhat = r, p = v = 0
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_restart_kernel(int64_t n, cons
     __shared__ X s_red[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X rr = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_restart_kernel(int64_t n, cons
         }
     }
     X vals[1] = {block_sum<X, kVecThreads>(rr, s_red)};
-    reduce_finish<X, 1, kVecThreads>(vals, partials, gridDim.x, blockIdx.x, st, 4, kOpBiRestart);
+    write_partials<X, 1>(vals, partials, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kVecThreads) void bi_p_kernel(int64_t n, const X *__restrict__ r, const X *__restrict__ v,
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_p_kernel(int64_t n, const X *_
     if (st->flag != kRunning) return;
     const X be = st->beta, om = st->omega;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_s_kernel(int64_t n, const X *_
     const X a = st->alpha;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X ss = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_s_kernel(int64_t n, const X *_
         }
     }
     X vals[1] = {block_sum<X, kVecThreads>(ss, s_red)};
-    reduce_finish<X, 1, kVecThreads>(vals, partials, gridDim.x, blockIdx.x, st, 1, kOpBiS);
+    write_partials<X, 1>(vals, partials, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kVecThreads) void bi_x_kernel(int64_t n, X *__restrict__ x, const X *__restrict__ ph,
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_x_kernel(int64_t n, X *__restr
     const X a = st->alpha, om = st->omega;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X rr = X(0), rhr = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kVecThreads) void bi_x_kernel(int64_t n, X *__restr
         }
     }
     X vals[2] = {block_sum<X, kVecThreads>(rr, s_red), block_sum<X, kVecThreads>(rhr, s_red)};
-    reduce_finish<X, 2, kVecThreads>(vals, partials, gridDim.x, blockIdx.x, st, 3, kOpBiRho);
+    write_partials<X, 2>(vals, partials, gridDim.x, blockIdx.x);
 }
 
 // half-step exit: x += alpha p^
@@ -226,6 +226,7 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
         bi_init_kernel<<<gv, kVecThreads, 0, s>>>(n, b, w.q, w.r, w.rh, w.p, w.v, w.partials, w.st);
     }
     SPX_LAUNCHED();
+    SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpBiInit, s));
     SPX_CHECK(read_state(env, w.st, &hs));
 
     GraphGuard graph;
@@ -235,9 +236,11 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
             bi_p_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.v, w.p, w.ph, w.dinv, w.st);
             SPX_CHECK((spmv_dot<double, double>(A, w.ph, w.v, w.rh, w.partials, w.st, kOpBiAlpha, 0, s)));
             bi_s_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.v, w.s, w.sh, w.dinv, w.partials, w.st);
+            SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpBiS, s));
             SPX_CHECK((spmv_dot2<double, double>(A, w.sh, w.t, w.s, w.partials, w.st, kOpBiOmega, 2, s)));
             bi_x_kernel<<<gv, kVecThreads, 0, s>>>(n, x, w.ph, w.sh, w.s, w.t, w.r, w.rh, w.partials, w.st);
             SPX_LAUNCHED();
+            SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpBiRho, s));
         }
         return SPX_OK;
     };
@@ -274,6 +277,7 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
             }
             bi_restart_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.rh, w.p, w.v, w.partials, w.st);
             SPX_LAUNCHED();
+            SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpBiRestart, s));
             SPX_CHECK(read_state(env, w.st, &hs));
             have_true = false;
             continue;

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_init_kernel(int64_t n, const X
     __shared__ X s_red[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X bb = X(0), rz = X(0), rr = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_init_kernel(int64_t n, const X
     }
     X v[3] = {block_sum<X, kVecThreads>(bb, s_red), block_sum<X, kVecThreads>(rz, s_red),
               block_sum<X, kVecThreads>(rr, s_red)};
-    reduce_finish<X, 3, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, 2, kOpCgInit);
+    write_partials<X, 3>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename X>
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_update_kernel(int64_t n, X *__
     const X a = (X)st->alpha;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X rz = X(0), rr = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_update_kernel(int64_t n, X *__
         }
     }
     X v[2] = {block_sum<X, kVecThreads>(rz, s_red), block_sum<X, kVecThreads>(rr, s_red)};
-    reduce_finish<X, 2, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, 1, kOpCgRho);
+    write_partials<X, 2>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename X>
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_p_kernel(int64_t n, const X *_
     if (st->flag != kRunning) return;
     const X be = (X)st->beta;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) p[i] = z[i] + be * p[i];
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_restart_kernel(int64_t n, cons
     __shared__ X s_red[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     X rz = X(0);
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kVecThreads) void cg_restart_kernel(int64_t n, cons
         }
     }
     X v[1] = {block_sum<X, kVecThreads>(rz, s_red)};
-    reduce_finish<X, 1, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, 2, kOpCgRestart);
+    write_partials<X, 1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename X>
@@ -197,6 +197,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
         cg_init_kernel<X><<<gv, kVecThreads, 0, s>>>(n, b, w.q, w.dinv, w.r, w.z, w.p, w.partials, w.st);
     }
     SPX_LAUNCHED();
+    SPX_CHECK(launch_finish<X>(w.partials, gv, 3, w.st, kOpCgInit, s));
     SPX_CHECK(read_state(env, w.st, &hs));
 
     GraphGuard graph;
@@ -206,6 +207,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
             SPX_CHECK((spmv_dot<V, X>(A, w.p, w.q, w.p, w.partials, w.st, kOpCgAlpha, 0, s)));
             cg_update_kernel<X><<<gv, kVecThreads, 0, s>>>(n, x, w.p, w.q, w.r, sp.precond ? w.z : nullptr,
                                                           w.dinv, w.partials, w.st);
+            SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpCgRho, s));
             cg_p_kernel<X><<<gv, kVecThreads, 0, s>>>(n, w.z, w.p, w.st);
             SPX_LAUNCHED();
         }
@@ -244,6 +246,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
             // restart the recurrences from the true residual (already in r)
             cg_restart_kernel<X><<<gv, kVecThreads, 0, s>>>(n, w.r, w.dinv, w.z, w.p, w.partials, w.st);
             SPX_LAUNCHED();
+            SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpCgRestart, s));
             SPX_CHECK(read_state(env, w.st, &hs));
             have_true = false;
             continue;

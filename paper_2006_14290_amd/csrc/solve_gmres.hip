@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kVecThreads) void gm_prep_kernel(int64_t n, X *__re
     if (st->flag != kRunning) return;
     const double inv = normalise ? 1.0 / st->tmp[1] : 1.0;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) {
@@ -67,15 +67,14 @@ __global__ __launch_bounds__(kVecThreads) void gm_prep_kernel(int64_t n, X *__re
     }
 }
 
-// h_i = v_i . w for i < nv, into st->dots[off + i] (deterministic)
+// h_i = v_i . w for i < nv: per-group partial sums (stage 1; the group keeps
+// its chunk of w in registers and sweeps the basis vectors)
 __global__ __launch_bounds__(kVecThreads) void gm_multidot_kernel(int64_t n, const X *__restrict__ V,
                                                                  const X *__restrict__ w, int nv,
-                                                                 X *__restrict__ partials, KState *st, int off,
-                                                                 int ticket)
+                                                                 X *__restrict__ partials, const KState *st)
 {
     if (st->flag != kRunning) return;
     __shared__ X s_red[kVecThreads / kWave];
-    __shared__ int s_last;
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     const int64_t nb = gridDim.x;
     X wl[kVecItems];
@@ -95,37 +94,34 @@ __global__ __launch_bounds__(kVecThreads) void gm_multidot_kernel(int64_t n, con
         const X t = block_sum<X, kVecThreads>(acc, s_red);
         if (threadIdx.x == 0) partials[(int64_t)k * nb + blockIdx.x] = t;
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = (atomicAdd(&st->ticket[ticket], 1u) == (uint32_t)(nb - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// stage 2: st->dots[off + k] = sum of row k of the partials, fixed order
+__global__ __launch_bounds__(kFinThreads) void gm_multidot_finish(const X *__restrict__ partials, int64_t nb, int nv,
+                                                                 KState *st, int off)
+{
+    if (st->flag != kRunning) return;
+    __shared__ X s_red[kFinThreads / kWave];
     for (int k = 0; k < nv; ++k) {
         X acc = X(0);
-        for (int64_t b = threadIdx.x; b < nb; b += kVecThreads) acc += partials[(int64_t)k * nb + b];
-        const X t = block_sum<X, kVecThreads>(acc, s_red);
+        for (int64_t b = threadIdx.x; b < nb; b += kFinThreads) acc += partials[(int64_t)k * nb + b];
+        const X t = block_sum<X, kFinThreads>(acc, s_red);
         if (threadIdx.x == 0) st->dots[off + k] = t;
     }
-    if (threadIdx.x == 0) st->ticket[ticket] = 0u;
 }
 
 // w -= sum_i h_i v_i with h = st->dots[off..off+nv); optionally ||w||^2 and
 // the Arnoldi step finish (Hessenberg column, Givens, cycle-end test).
 __global__ __launch_bounds__(kVecThreads) void gm_update_kernel(int64_t n, const X *__restrict__ V, X *__restrict__ w,
-                                                               int nv, int off, int final_pass, int j,
-                                                               X *__restrict__ partials, KState *st, GmState gs,
-                                                               int ticket)
+                                                               int nv, int off, int final_pass,
+                                                               X *__restrict__ partials, const KState *st)
 {
     if (st->flag != kRunning) return;
     __shared__ X s_red[kVecThreads / kWave];
-    __shared__ int s_last;
     __shared__ double s_h[kMaxDots];
     if (threadIdx.x < nv) s_h[threadIdx.x] = st->dots[off + threadIdx.x];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
-    const int64_t nb = gridDim.x;
     X wl[kVecItems];
 #pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
@@ -152,19 +148,20 @@ __global__ __launch_bounds__(kVecThreads) void gm_update_kernel(int64_t n, const
     }
     if (!final_pass) return;
     const X t = block_sum<X, kVecThreads>(ww, s_red);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = t;
-        __threadfence();
-        s_last = (atomicAdd(&st->ticket[ticket], 1u) == (uint32_t)(nb - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Arnoldi step finish: ||w||, Hessenberg column j, Givens rotations, the
+// residual estimate and the cycle-end test (one work-group, fixed order).
+__global__ __launch_bounds__(kFinThreads) void gm_step_finish(const X *__restrict__ partials, int64_t nb, int j,
+                                                             KState *st, GmState gs)
+{
+    if (st->flag != kRunning) return;
+    __shared__ X s_red[kFinThreads / kWave];
     X acc = X(0);
-    for (int64_t b = threadIdx.x; b < nb; b += kVecThreads) acc += partials[b];
-    const X w2 = block_sum<X, kVecThreads>(acc, s_red);
+    for (int64_t b = threadIdx.x; b < nb; b += kFinThreads) acc += partials[b];
+    const X w2 = block_sum<X, kFinThreads>(acc, s_red);
     if (threadIdx.x != 0) return;
-    st->ticket[ticket] = 0u;
     const int m = gs.m;
     double *hj = gs.H + (int64_t)j * (m + 1);
     for (int i = 0; i <= j; ++i) hj[i] = st->dots[i] + st->dots[kMaxDots + i];
@@ -251,7 +248,7 @@ __global__ __launch_bounds__(kVecThreads) void gm_bnorm_kernel(int64_t n, const 
         if (i < n) acc += b[i] * b[i];
     }
     X v[1] = {block_sum<X, kVecThreads>(acc, s_red)};
-    reduce_finish<X, 1, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, 6, kOpNorm2);
+    write_partials<X, 1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 __global__ void gm_set_bb_kernel(KState *st)
@@ -333,6 +330,8 @@ spx_status gmres_run(const spx_matrix &A_in, const double *b, double *x, const S
     const unsigned ge = (unsigned)ceil_div(n, kVecThreads);
     if (sp.x0_zero) gm_zero_vec<<<ge, kVecThreads, 0, s>>>(n, x);
     gm_bnorm_kernel<<<gv, kVecThreads, 0, s>>>(n, b, w.partials, w.st);
+    SPX_LAUNCHED();
+    SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpNorm2, s));
     gm_set_bb_kernel<<<1, 64, 0, s>>>(w.st);
     SPX_LAUNCHED();
 
@@ -344,10 +343,13 @@ spx_status gmres_run(const spx_matrix &A_in, const double *b, double *x, const S
             if (j > 0 || w.dinv) gm_prep_kernel<<<gv, kVecThreads, 0, s>>>(n, vj, w.dinv, w.z, j > 0 ? 1 : 0, w.st);
             const X *src = w.dinv ? w.z : vj;
             SPX_CHECK(spmv_dispatch(A, src, wv, 1.0, 0.0, s));
-            gm_multidot_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, w.partials, w.st, 0, 0);
-            gm_update_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, 0, 0, j, w.partials, w.st, gs, 1);
-            gm_multidot_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, w.partials, w.st, kMaxDots, 2);
-            gm_update_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, kMaxDots, 1, j, w.partials, w.st, gs, 3);
+            gm_multidot_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, w.partials, w.st);
+            gm_multidot_finish<<<1, kFinThreads, 0, s>>>(w.partials, gv, j + 1, w.st, 0);
+            gm_update_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, 0, 0, w.partials, w.st);
+            gm_multidot_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, w.partials, w.st);
+            gm_multidot_finish<<<1, kFinThreads, 0, s>>>(w.partials, gv, j + 1, w.st, kMaxDots);
+            gm_update_kernel<<<gv, kVecThreads, 0, s>>>(n, w.V, wv, j + 1, kMaxDots, 1, w.partials, w.st);
+            gm_step_finish<<<1, kFinThreads, 0, s>>>(w.partials, gv, j, w.st, gs);
             SPX_LAUNCHED();
         }
         return SPX_OK;

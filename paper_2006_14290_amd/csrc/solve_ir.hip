@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kVecThreads) void ir_amax_kernel(int64_t n, const d
     // max |r_i| as the bit pattern of a non-negative double (monotone in value)
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     double m = 0.0;
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < kVecItems; ++u) {
         const int64_t i = base + threadIdx.x + u * kVecThreads;
         if (i < n) m = fmax(m, fabs(r[i]));

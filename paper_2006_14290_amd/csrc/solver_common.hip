@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kVecThreads) void dot_kernel(int64_t n, const X *__
         if (i < n) acc += a[i] * b[i];
     }
     X v[1] = {block_sum<X, kVecThreads>(acc, s_red)};
-    reduce_finish<X, 1, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, ticket, op);
+    write_partials<X, 1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename X>
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kVecThreads) void dot2_kernel(int64_t n, const X *_
         }
     }
     X v[2] = {block_sum<X, kVecThreads>(aw, s_red), block_sum<X, kVecThreads>(aa, s_red)};
-    reduce_finish<X, 2, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, ticket, op);
+    write_partials<X, 2>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename X>
@@ -223,29 +223,35 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, const 
         }
     }
     X v[1] = {block_sum<X, kVecThreads>(acc, s_red)};
-    reduce_finish<X, 1, kVecThreads>(v, partials, gridDim.x, blockIdx.x, st, ticket, kOpNorm2);
+    write_partials<X, 1>(v, partials, gridDim.x, blockIdx.x);
 }
 
 template <typename V, typename X>
 spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partials, KState *st, int op, int ticket,
                     hipStream_t stream)
 {
-    if (A.fmt == SPX_CSR) return csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op, ticket);
+    if (A.fmt == SPX_CSR) {
+        SPX_CHECK((csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op, ticket)));
+        return launch_finish<X>(partials, csr_tiles(A.nnz), 1, st, op, stream);
+    }
     SPX_CHECK(spmv_dispatch(A, p, q, 1.0, 0.0, stream));
     dot_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, w, q, partials, st, op, ticket);
     SPX_LAUNCHED();
-    return SPX_OK;
+    return launch_finish<X>(partials, vec_blocks(A.nrows), 1, st, op, stream);
 }
 
 template <typename V, typename X>
 spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *partials, KState *st, int op, int ticket,
                      hipStream_t stream)
 {
-    if (A.fmt == SPX_CSR) return csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op, ticket);
+    if (A.fmt == SPX_CSR) {
+        SPX_CHECK((csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op, ticket)));
+        return launch_finish<X>(partials, csr_tiles(A.nnz), 2, st, op, stream);
+    }
     SPX_CHECK(spmv_dispatch(A, sv, t, 1.0, 0.0, stream));
     dot2_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, t, w, partials, st, op, ticket);
     SPX_LAUNCHED();
-    return SPX_OK;
+    return launch_finish<X>(partials, vec_blocks(A.nrows), 2, st, op, stream);
 }
 
 template <typename X>
@@ -254,7 +260,7 @@ spx_status residual_norm(int64_t n, const X *b, const X *q, X *r, X *partials, K
 {
     residual_kernel<X><<<(unsigned)vec_blocks(n), kVecThreads, 0, stream>>>(n, b, q, r, partials, st, ticket);
     SPX_LAUNCHED();
-    return SPX_OK;
+    return launch_finish<X>(partials, vec_blocks(n), 1, st, kOpNorm2, stream);
 }
 
 template spx_status jacobi_setup<double, double>(const spx_matrix &, double *, double *, KState *, hipStream_t);

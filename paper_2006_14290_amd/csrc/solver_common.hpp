@@ -11,7 +11,7 @@
 namespace spx {
 
 constexpr int kVecThreads = 256;
-constexpr int kVecItems = 16;                          // elements per thread
+constexpr int kVecItems = 4;                           // elements per thread
 constexpr int kVecChunk = kVecThreads * kVecItems;     // elements per work-group
 
 inline int64_t vec_blocks(int64_t n) { return n > 0 ? ceil_div(n, kVecChunk) : 1; }

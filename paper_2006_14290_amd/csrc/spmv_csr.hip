@@ -215,11 +215,7 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
         A v[kEpi];
         v[0] = block_sum<A, kThreads>(dot_acc, s_red);
         if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<A, kThreads>(dot_acc2, s_red);
-        if (st != nullptr) {
-            reduce_finish<A, kEpi, kThreads>(v, dot_partials, ntiles, k, st, ticket, op);
-        } else if (tid == 0) {
-            for (int q = 0; q < kEpi; ++q) dot_partials[q * ntiles + k] = v[q];
-        }
+        write_partials<A, kEpi>(v, dot_partials, ntiles, k);
     }
 }
 

@@ -15,8 +15,8 @@ struct KState;
 // y = alpha*A*x + beta*y for a CSR matrix with stored value type V and vector
 // type X. epi = 1: also sum_i y_i*dot_with_i; epi = 2: that and sum_i y_i^2,
 // one partial per tile in dot_partials[epi][csr_tiles(nnz)] (fixed order).
-// With a solver state st, the partials are reduced by the last tile and
-// finished by `op` (ticket slot `ticket`), and a set st->flag skips the work.
+// With a solver state st, a set st->flag skips the work (the caller reduces
+// the partials with finish_kernel).
 // Writes the tile partition (2 * (csr_tiles(nnz) + 1) int32) of A.
 spx_status csr_partition_launch(const spx_matrix &A, int32_t *part, hipStream_t stream);
 inline int64_t csr_partition_bytes(int64_t nnz) { return 2 * (csr_tiles(nnz) + 1) * (int64_t)sizeof(int32_t); }

@@ -101,8 +101,9 @@ def test_cg_status_codes():
     I = S.from_dense(np.eye(50))
     bi = S.uniform_vector(50, seed=1)
     x, info = spx.cg_solve(spx.csr_from_host(I), dev(bi), tol=1e-12)
-    assert info["status"] == spx.OK and info["iters"] == 1
-    np.testing.assert_array_equal(host(x), bi)
+    assert info["status"] == spx.OK and info["iters"] == 1, info
+    # alpha = r.r / p.q is 1 up to the rounding of two differently ordered sums
+    np.testing.assert_allclose(host(x), bi, rtol=4e-16, atol=0)
 
 
 @pytest.mark.timeout(600)
