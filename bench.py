@@ -66,15 +66,22 @@ def cg_iter_bytes(n, nnz, sv, precond):
     return csr_bytes(n, nnz, sv, sv) + (11 if precond else 9) * n * sv
 
 
-def bench_cg_small(spx, S, O, torch, dev, nsolves):
+def rhs(spx, S, torch, Ad, seed=0):
+    """b = A x* on the device, x* i.i.d. uniform[-1, 1) (the product is the
+    library's own)."""
+    xs = torch.from_numpy(S.uniform_vector(Ad.nrows, seed=seed, purpose="xstar")).to(Ad.vals.device)
+    return spx.spmv(Ad, xs)
+
+
+def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
     """2D 5-point 64x64 (n = 4096, nnz = 20,224), unpreconditioned CG to 1e-10
-    relative residual, solved `nsolves` times back to back (blocking calls);
-    latency is the host wall clock of each call."""
+    relative residual. (1) One system at a time: `nsolves` blocking solves back
+    to back, latency = host wall clock per call. (2) Batched: `nbatch`
+    independent right-hand sides solved by one launch of the batched kernel
+    (one work-group per system)."""
     A = S.poisson2d(64)
-    xs = S.uniform_vector(A.n, seed=0, purpose="xstar")
-    b, _ = O.csr_spmv_dot2(A, xs)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
-    bd = torch.from_numpy(b).to(dev)
+    bd = rhs(spx, S, torch, Ad)
     for _ in range(3):
         spx.cg_solve(Ad, bd, tol=1e-10)
     torch.cuda.synchronize()
@@ -88,26 +95,36 @@ def bench_cg_small(spx, S, O, torch, dev, nsolves):
         assert info["status"] == 0 and info["relres_true"] <= 1e-10, info
     tot = time.perf_counter() - t0
     lat = np.array(lat) * 1e3
-    return {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
-            "relres_true": info["relres_true"]}
+    out = {"single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
+                      "relres_true": info["relres_true"]}}
+    if nbatch > 0:
+        bs = [rhs(spx, S, torch, Ad, seed=s) for s in range(nbatch)]
+        spx.cg_batch([Ad] * nbatch, bs, tol=1e-10)
+        torch.cuda.synchronize()
+        reps, lat = 5, []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            xs, infos = spx.cg_batch([Ad] * nbatch, bs, tol=1e-10)
+            lat.append(time.perf_counter() - t1)
+            assert all(i["status"] == 0 and i["relres_true"] <= 1e-10 for i in infos)
+        lat = np.array(lat)
+        out["batched"] = {"systems": nbatch, "solves_per_s": round(nbatch / float(np.median(lat)), 1),
+                          "batch_ms_p50": round(1e3 * float(np.median(lat)), 3),
+                          "batch_ms_max": round(1e3 * float(lat.max()), 3), "iters": infos[0]["iters"]}
+    return out
 
 
-def bench_solvers(spx, S, O, torch, dev):
+def bench_solvers(spx, S, torch, dev):
     """Krylov solvers at full size: CG+Jacobi on the anisotropic 7-point 128^3
     grid, BiCGSTAB and GMRES(30) + Jacobi on the upwind convection-diffusion
     128^3 grid, and mixed-precision IR (float32 / binary16 values) against
     plain float64 CG on the 7-point 192^3 grid; all to 1e-10."""
     out = {}
 
-    def prob(A):
-        xs = S.uniform_vector(A.n, seed=0, purpose="xstar")
-        b, _ = O.csr_spmv_dot2(A, xs)
-        return torch.from_numpy(b).to(dev)
-
     A = S.poisson3d_7pt(128, 1, 1, 0.01)
-    bd = prob(A)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    bd = rhs(spx, S, torch, Ad)
     spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
     x, info = spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
     it_us = 1e3 * info["device_ms"] / max(info["iters"], 1)
@@ -117,8 +134,8 @@ def bench_solvers(spx, S, O, torch, dev):
                                  "relres_true": info["relres_true"]}
     del Ad, A
     A = S.convdiff3d_upwind(128)
-    bd = prob(A)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    bd = rhs(spx, S, torch, Ad)
     for nm, fn in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve), ("gmres30_jacobi_convdiff128", spx.gmres_solve)):
         fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
         x, info = fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
@@ -126,8 +143,8 @@ def bench_solvers(spx, S, O, torch, dev):
                    "relres_true": info["relres_true"]}
     del Ad, A
     A = S.poisson3d_7pt(192)
-    bd = prob(A)
     A64 = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
+    bd = rhs(spx, S, torch, A64)
     spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
     x, info = spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
     t64 = info["device_ms"]
@@ -144,6 +161,85 @@ def bench_solvers(spx, S, O, torch, dev):
     return out
 
 
+def serve_workload(S, nreq, seed):
+    """Request mix of the serving workload: half 2D 5-point Poisson systems on
+    N x N grids with N ~ U{32..512}, half random symmetric diagonally dominant
+    SPD systems with n log-uniform in [1e3, 1e6] and 5..30 entries per row.
+    Distinct matrices are drawn from a fixed menu (Poisson N rounded to a
+    multiple of 16, SPD sizes on 24 log-spaced values) so that the host builds
+    each matrix once; every request is solved independently."""
+    r = S.rng(seed, "sizes")
+    kinds = r.random(nreq) < 0.5
+    pN = np.clip(np.round(r.integers(32, 513, nreq) / 16) * 16, 32, 512).astype(int)
+    spd_menu = np.unique(np.round(np.logspace(3, 6, 24)).astype(int))
+    sn = spd_menu[np.clip(np.searchsorted(spd_menu, np.exp(r.uniform(np.log(1e3), np.log(1e6), nreq))), 0,
+                          len(spd_menu) - 1)]
+    return [("poisson", int(pN[i])) if kinds[i] else ("spd", int(sn[i])) for i in range(nreq)]
+
+
+def bench_serve(spx, S, torch, dev, nreq, seed):
+    """Serving: (1) all `nreq` requests submitted at once (capacity, solves/s);
+    (2) an open-loop Poisson arrival stream at 0.7 x that capacity (latency =
+    completion - scheduled arrival, p50/p99); (3) the same requests solved one
+    by one with the blocking float64 CG (spx_cg_solve) on a sample, for
+    comparison. Tolerance 1e-8."""
+    reqs = serve_workload(S, nreq, seed)
+    mats = {}
+    t0 = time.time()
+    for kind, size in sorted(set(reqs)):
+        A = S.poisson2d(size) if kind == "poisson" else S.spd_diag_dominant(size, seed=size)
+        Ad = spx.csr_from_host(A, spx.F64, dev)
+        b = rhs(spx, S, torch, Ad, seed=size).cpu().numpy()
+        mats[(kind, size)] = (A, b)
+        del Ad
+    gen_s = time.time() - t0
+    srv = spx.Server(max_slots=2048, hbm_budget_bytes=32 << 30)
+
+    def run(arrivals):
+        tickets, t_sched = [], []
+        start = time.perf_counter()
+        for i, (kind, size) in enumerate(reqs):
+            if arrivals is not None:
+                while time.perf_counter() - start < arrivals[i]:
+                    time.sleep(0.0002)
+            A, b = mats[(kind, size)]
+            tickets.append(srv.submit(A, b, tol=1e-8))
+            t_sched.append(start + (arrivals[i] if arrivals is not None else 0.0))
+        lat, iters, worst = [], [], 0.0
+        for t, ts in zip(tickets, t_sched):
+            x, info = srv.wait(t, timeout_s=600)
+            assert info["status"] == 0, info
+            done = time.perf_counter()
+            lat.append(done - ts)
+            iters.append(info["iters"])
+            worst = max(worst, info["relres_true"])
+        total = time.perf_counter() - start
+        lat = np.array(lat) * 1e3
+        return {"requests": nreq, "solves_per_s": round(nreq / total, 2), "wall_s": round(total, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "mean_iters": round(float(np.mean(iters)), 1), "max_relres_true": worst}
+
+    burst = run(None)
+    rate = 0.7 * burst["solves_per_s"]
+    arr = S.poisson_arrivals(nreq, rate, seed=seed)
+    stream = run(arr)
+    stream["rate_per_s"] = round(rate, 2)
+    st = srv.stats()
+    srv.close()
+    # sequential blocking float64 CG on a sample of the same requests
+    sample = reqs[: min(nreq, 100)]
+    t1 = time.perf_counter()
+    for kind, size in sample:
+        A, b = mats[(kind, size)]
+        Ad = spx.csr_from_host(A, spx.F64, dev)
+        x, info = spx.cg_solve(Ad, torch.from_numpy(b).to(dev), tol=1e-8, maxit=100000)
+        assert info["status"] == 0
+    seq = len(sample) / (time.perf_counter() - t1)
+    return {"burst": burst, "open_loop": stream, "sequential_cg_solves_per_s": round(seq, 2),
+            "sequential_sample": len(sample), "server": {k: st[k] for k in ("ticks", "pool_bytes_peak")},
+            "distinct_matrices": len(mats), "gen_s": round(gen_s, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +250,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solvers", action="store_true", help="also time the full-size Krylov solvers")
     ap.add_argument("--cg-solves", type=int, default=50, help="solves of the 64x64 CG latency run (0 = skip)")
+    ap.add_argument("--cg-batch", type=int, default=1024, help="systems in the batched 64x64 CG run (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving run (0 = skip)")
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -198,16 +297,14 @@ def main():
     del src, dst
 
     if args.sweep:
-        import oracle as O  # host-side format conversion for the inputs only
-
-        E = O.csr_to_ell(A)
-        H = O.csr_to_hyb(A)
-        crow = O.csr_to_coo_rows(A)
+        base = spx.csr_from_host(A, spx.F64, dev)
+        Kh = spx.convert(base, spx.HYB)
+        hybK, hybC = Kh.ell_width, Kh.coo_nnz
+        del Kh
         variants = {
-            "coo_f64": (lambda: spx.coo_from_host(n, crow, A.col, A.val, spx.F64, dev), coo_bytes(n, nnz, 8, 8)),
-            "ell_f64": (lambda: spx.ell_from_host(n, E.K, E.ld, E.col, E.val, spx.F64, dev), ell_bytes(n, E.K, 8, 8)),
-            "hyb_f64": (lambda: spx.hyb_from_host(n, H.ell.K, H.ell.ld, H.ell.col, H.ell.val, H.row, H.col, H.val,
-                                                  spx.F64, dev), hyb_bytes(n, H.ell.K, len(H.row), 8, 8)),
+            "coo_f64": (lambda: spx.convert(base, spx.COO), coo_bytes(n, nnz, 8, 8)),
+            "ell_f64": (lambda: spx.convert(base, spx.ELL), ell_bytes(n, int(A.row_lengths().max()), 8, 8)),
+            "hyb_f64": (lambda: spx.convert(base, spx.HYB), hyb_bytes(n, hybK, hybC, 8, 8)),
             "csr_f32": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F32, dev)), csr_bytes(n, nnz, 4, 4)),
             "csr_f16": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F16, dev)), csr_bytes(n, nnz, 2, 4)),
             "csr_f64_nopart": (lambda: spx.csr_from_host(A, spx.F64, dev), csr_bytes(n, nnz, 8, 8)),
@@ -226,10 +323,9 @@ def main():
             del Ms, Xs, Ys
             torch.cuda.empty_cache()
 
-    import oracle as O  # inputs (b = A x*) and the CPU baseline only
-
-    cg_small = bench_cg_small(spx, S, O, torch, dev, args.cg_solves) if args.cg_solves > 0 else None
-    solvers = bench_solvers(spx, S, O, torch, dev) if args.solvers else None
+    cg_small = bench_cg_small(spx, S, torch, dev, args.cg_solves, args.cg_batch) if args.cg_solves > 0 else None
+    solvers = bench_solvers(spx, S, torch, dev) if args.solvers else None
+    serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed) if args.serve_requests > 0 else None
 
     cpu = None
     if not args.no_cpu:
@@ -272,6 +368,7 @@ def main():
         "sweep": {k: {"GBs": round(v["GBs"], 2), "ms": round(v["ms"], 5)} for k, v in results.items()},
         "cg_poisson64": cg_small,
         "solvers": solvers,
+        "serve": serve,
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
     }

@@ -100,6 +100,45 @@ for _nm in ("spx_cg_solve", "spx_bicgstab_solve", "spx_gmres_solve"):
     _sig(_nm, [_MP, _vp, _vp, _SOP, _vp, ctypes.c_size_t, _SIP, _vp])
 _sig("spx_ir_workspace", [_MP, _MP, ctypes.POINTER(ctypes.c_size_t)])
 _sig("spx_ir_solve", [_MP, _MP, _vp, _vp, ctypes.POINTER(IrOpts), _vp, ctypes.c_size_t, _SIP, _vp])
+class BatchSystem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("spmv_count", ctypes.c_int32), ("relres_true", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("iters_per_tick", ctypes.c_int32), ("tick_us", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("solver", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("x_out", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("pool_bytes_total", ctypes.c_size_t), ("pool_bytes_in_use", ctypes.c_size_t),
+                ("pool_bytes_peak", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_sig("spx_cg_batch_workspace", [ctypes.POINTER(BatchSystem), _i32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("spx_cg_batch", [ctypes.POINTER(BatchSystem), _i32, _vp, ctypes.c_size_t, _vp])
+_sig("spx_server_create", [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)])
+_sig("spx_serve_submit", [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
+_sig("spx_serve_poll", [_vp, ctypes.c_uint64, _SIP])
+_sig("spx_serve_wait", [_vp, ctypes.c_uint64, ctypes.c_double, _SIP])
+_sig("spx_serve_cancel", [_vp, ctypes.c_uint64])
+_sig("spx_server_get_stats", [_vp, ctypes.POINTER(ServerStats)])
+_sig("spx_server_destroy", [_vp])
 _sig("spx_subwarp_sum", [_vp, _vp, _i64, _i32, _i32, _vp])
 _sig("spx_subwarp_vote", [_vp, _vp, _vp, _vp, _i64, _i32, _vp])
 _sig("spx_wave_segscan", [_vp, _vp, _vp, _i64, _vp])
@@ -354,6 +393,94 @@ def ir_solve(A64: Matrix, Alow: Matrix, b: torch.Tensor, tol: float = 1e-10, inn
     out["status"] = st
     out["error"] = _lib.spx_last_error().decode() if st != OK else ""
     return x, out
+
+
+# ------------------------------------------------------------------ batched CG and serving
+def cg_batch(mats, bs, tol=1e-8, maxit=100000, stream=None):
+    """Solve independent CSR systems (device Matrix objects, float64) with one
+    persistent launch, one work-group per system. Returns (xs, infos)."""
+    count = len(mats)
+    arr = (BatchSystem * count)()
+    xs = []
+    for i, (A, b) in enumerate(zip(mats, bs)):
+        x = torch.empty_like(b)
+        xs.append(x)
+        arr[i] = BatchSystem(A.nrows, 0, A.nnz, _ptr(A.rowptr), _ptr(A.colidx), _ptr(A.vals), _ptr(b), _ptr(x),
+                             tol, maxit, 0, 0, 0, 0.0)
+    nbytes = ctypes.c_size_t(0)
+    check(_lib.spx_cg_batch_workspace(arr, count, ctypes.byref(nbytes)), "spx_cg_batch_workspace")
+    ws = _workspace(nbytes.value, bs[0].device)
+    st = _lib.spx_cg_batch(arr, count, _ptr(ws), ws.numel(), _stream(stream))
+    if st not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE):
+        check(st, "spx_cg_batch")
+    infos = [{"status": arr[i].status, "iters": arr[i].iters, "spmv_count": arr[i].spmv_count,
+              "relres_true": arr[i].relres_true} for i in range(count)]
+    return xs, infos
+
+
+class Server:
+    """Continuous-batching CG server (host requests, results copied back)."""
+
+    def __init__(self, device: int = 0, max_slots: int = 1024, hbm_budget_bytes: int = 32 << 30,
+                 iters_per_tick: int = 0, tick_us: int = 0):
+        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us)
+        h = ctypes.c_void_p()
+        check(_lib.spx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "spx_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> host arrays kept alive until completion
+
+    def submit(self, A, b: np.ndarray, tol: float = 1e-8, maxit: int = 0, x_out: Optional[np.ndarray] = None):
+        """A: host CSR (rowptr/col/val numpy); returns the ticket."""
+        rp = np.ascontiguousarray(A.rowptr, np.int32)
+        ci = np.ascontiguousarray(A.col, np.int32)
+        va = np.ascontiguousarray(A.val, np.float64)
+        bb = np.ascontiguousarray(b, np.float64)
+        x = np.empty(A.n, np.float64) if x_out is None else x_out
+        req = Request(int(A.n), SOLVER_CG, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                      bb.ctypes.data, x.ctypes.data, tol, maxit, 0)
+        t = ctypes.c_uint64(0)
+        check(_lib.spx_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "spx_serve_submit")
+        self._keep[t.value] = (rp, ci, va, bb, x)
+        return t.value
+
+    def _result(self, ticket, st, info):
+        out = info.as_dict()
+        out["status"] = st
+        x = self._keep.pop(ticket)[4] if st != PENDING else None
+        return x, out
+
+    def poll(self, ticket):
+        info = SolveInfo()
+        st = _lib.spx_serve_poll(self._h, ticket, ctypes.byref(info))
+        if st == ERR_ARG:
+            check(st, "spx_serve_poll")
+        return self._result(ticket, st, info)
+
+    def wait(self, ticket, timeout_s: float = -1.0):
+        info = SolveInfo()
+        st = _lib.spx_serve_wait(self._h, ticket, timeout_s, ctypes.byref(info))
+        if st == ERR_ARG:
+            check(st, "spx_serve_wait")
+        return self._result(ticket, st, info)
+
+    def cancel(self, ticket):
+        check(_lib.spx_serve_cancel(self._h, ticket), "spx_serve_cancel")
+
+    def stats(self):
+        s = ServerStats()
+        check(_lib.spx_server_get_stats(self._h, ctypes.byref(s)), "spx_server_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if self._h:
+            _lib.spx_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ primitives

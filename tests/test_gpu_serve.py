@@ -1,0 +1,169 @@
+"""Batched CG (one work-group per system) and the continuous-batching server:
+every result meets the tolerance through the oracle's true residual, and a
+system's solution is bitwise the same alone, in a batch, and in the served
+mix (however its iterations are split across ticks). Admission, budget,
+queueing, slot reuse and cancellation are exercised."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2006_14290_amd import synth as S
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+spx = pytest.importorskip("paper_2006_14290_amd.spx")
+
+
+def _system(kind, size, seed):
+    A = S.poisson2d(size) if kind == "poisson" else S.spd_diag_dominant(size, seed=seed)
+    xs = S.uniform_vector(A.n, seed=seed, purpose="xstar")
+    b, _ = O.csr_spmv_dot2(A, xs)
+    return A, b
+
+
+MIX = [("poisson", 32, 1), ("spd", 1000, 2), ("poisson", 47, 3), ("spd", 5000, 4), ("poisson", 64, 5),
+       ("spd", 20000, 6), ("poisson", 90, 7), ("spd", 1500, 8), ("poisson", 33, 9), ("spd", 12345, 10)]
+
+
+def _relres(A, b, x):
+    _, rn = O.residual(A, b, x)
+    return rn / np.linalg.norm(b)
+
+
+def _alone(A, b, tol):
+    Ad = spx.csr_from_host(A)
+    xs, infos = spx.cg_batch([Ad], [dev(b)], tol=tol)
+    return host(xs[0]), infos[0]
+
+
+def test_cg_batch_mix_and_alone_bitwise():
+    systems = [_system(*m) for m in MIX]
+    mats = [spx.csr_from_host(A) for A, _ in systems]
+    bs = [dev(b) for _, b in systems]
+    xs, infos = spx.cg_batch(mats, bs, tol=1e-8)
+    for (A, b), x, info in zip(systems, xs, infos):
+        x = host(x)
+        assert info["status"] == spx.OK, info
+        assert _relres(A, b, x) <= 1e-8
+        xa, ia = _alone(A, b, 1e-8)
+        assert ia["iters"] == info["iters"]
+        np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+
+
+def test_cg_batch_matches_oracle_iterations():
+    A, b = _system("poisson", 64, 0)
+    x, info = _alone(A, b, 1e-10)
+    assert info["status"] == spx.OK
+    assert _relres(A, b, x) <= 1e-10
+    xo, io = O.cg(A, b, tol=1e-10)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
+
+
+def test_cg_batch_many_identical_systems():
+    """The 64x64 Poisson system 512 times over with different right-hand sides."""
+    A = S.poisson2d(64)
+    Ad = spx.csr_from_host(A)
+    bs = []
+    for s in range(512):
+        xs = S.uniform_vector(A.n, seed=s, purpose="xstar")
+        bs.append(O.csr_spmv_dot2(A, xs)[0])
+    xs, infos = spx.cg_batch([Ad] * 512, [dev(b) for b in bs], tol=1e-10)
+    for i in (0, 1, 255, 511):
+        assert infos[i]["status"] == spx.OK
+        assert _relres(A, bs[i], host(xs[i])) <= 1e-10
+    assert all(inf["status"] == spx.OK for inf in infos)
+
+
+def test_server_mix_alone_bitwise_and_stats():
+    srv = spx.Server(max_slots=4, hbm_budget_bytes=256 << 20, tick_us=300)
+    try:
+        systems = [_system(*m) for m in MIX]
+        tickets = [srv.submit(A, b, tol=1e-8) for A, b in systems]
+        for t, (A, b) in zip(tickets, systems):
+            x, info = srv.wait(t, timeout_s=120)
+            assert info["status"] == spx.OK, info
+            assert _relres(A, b, x) <= 1e-8
+            xa, ia = _alone(A, b, 1e-8)
+            assert ia["iters"] == info["iters"]
+            np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+            assert info["device_ms"] > 0
+        st = srv.stats()
+        assert st["submitted"] == st["completed"] == len(MIX)
+        assert st["active"] == 0 and st["queued"] == 0
+        assert st["pool_bytes_peak"] <= st["pool_bytes_total"]
+        assert st["ticks"] >= 1
+    finally:
+        srv.close()
+
+
+def test_server_one_iteration_per_tick_same_bits():
+    A, b = _system("poisson", 40, 11)
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20, iters_per_tick=1)
+    try:
+        x, info = srv.wait(srv.submit(A, b, tol=1e-8), timeout_s=120)
+        assert info["status"] == spx.OK
+        xa, _ = _alone(A, b, 1e-8)
+        np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+        assert srv.stats()["ticks"] >= info["iters"]
+    finally:
+        srv.close()
+
+
+def test_server_budget_queueing_and_cancel():
+    big = S.poisson2d(128)
+    xs = S.uniform_vector(big.n, seed=1, purpose="xstar")
+    bbig = O.csr_spmv_dot2(big, xs)[0]
+    small, bsmall = _system("poisson", 32, 2)
+    # a budget that holds one 128x128 system at a time
+    one = 5 * 16384 * 8 + 16385 * 4 + big.nnz * 12 + 8 * 256
+    srv = spx.Server(max_slots=8, hbm_budget_bytes=int(one * 1.5), iters_per_tick=5)
+    try:
+        with pytest.raises(spx.SpxError, match="BUDGET"):
+            huge = S.poisson2d(300)
+            srv.submit(huge, np.ones(huge.n))
+        tickets = [srv.submit(big, bbig, tol=1e-8) for _ in range(4)]
+        victim = srv.submit(small, bsmall, tol=1e-8)
+        srv.cancel(victim)
+        x, info = srv.wait(victim, timeout_s=60)
+        assert info["status"] in (spx.CANCELLED, spx.OK)
+        saw_queue = False
+        for t in tickets:
+            saw_queue |= srv.stats()["queued"] > 0
+            x, info = srv.wait(t, timeout_s=120)
+            assert info["status"] == spx.OK
+            assert _relres(big, bbig, x) <= 1e-8
+        st = srv.stats()
+        assert st["pool_bytes_peak"] <= st["pool_bytes_total"]
+        assert st["rejected"] == 1
+        assert st["completed"] == st["submitted"] == 5
+    finally:
+        srv.close()
+
+
+def test_server_poll_and_slot_reuse():
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20)
+    try:
+        systems = [_system("spd", 2000 + 100 * i, i) for i in range(10)]
+        tickets = [srv.submit(A, b, tol=1e-8) for A, b in systems]
+        pending = set(tickets)
+        t0 = time.time()
+        results = {}
+        while pending and time.time() - t0 < 120:
+            for t in list(pending):
+                x, info = srv.poll(t)
+                if info["status"] != spx.PENDING:
+                    results[t] = (x, info)
+                    pending.discard(t)
+            time.sleep(0.001)
+        assert not pending
+        for t, (A, b) in zip(tickets, systems):
+            x, info = results[t]
+            assert info["status"] == spx.OK
+            assert _relres(A, b, x) <= 1e-8
+    finally:
+        srv.close()
