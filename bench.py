@@ -66,6 +66,33 @@ def cg_iter_bytes(n, nnz, sv, precond):
     return csr_bytes(n, nnz, sv, sv) + (11 if precond else 9) * n * sv
 
 
+def profile_traffic(name, algo_bytes):
+    """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter runs
+    summarised in profiles/<name>.md, or None when the kernel sources listed
+    there have changed since (their hash differs) or the launch moved a
+    different number of algorithmic bytes."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ": " in line and not line.startswith(("|", "#", " ")):
+            k, v = line.strip().split(": ", 1)
+            kv[k] = v
+    try:
+        h = hashlib.sha256()
+        for f in sorted(kv["kernel_sources"].split(",")):
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != kv["kernel_source_sha256_16"] or int(kv["algorithmic_bytes_per_launch"]) != algo_bytes:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def rhs(spx, S, torch, Ad, seed=0):
     """b = A x* on the device, x* i.i.d. uniform[-1, 1) (the product is the
     library's own)."""
@@ -364,7 +391,7 @@ def main():
         "pct_of_copy": round(100 * r["GBs"] / copy_gbs, 2),
         "roofline": {"bound": "hbm", "achieved": round(r["GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "csr_spmv_kernel<double,double,false>", "bytes_per_launch": b},
+                     "kernel": "csr_spmv_kernel<double,double,0,512,4096>", "bytes_per_launch": b},
         "sweep": {k: {"GBs": round(v["GBs"], 2), "ms": round(v["ms"], 5)} for k, v in results.items()},
         "cg_poisson64": cg_small,
         "solvers": solvers,
@@ -372,6 +399,10 @@ def main():
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
     }
+    traffic = profile_traffic(f"csr_spmv_f64_27pt{args.grid}", b)
+    if traffic is not None:
+        line["roofline"]["traffic"] = traffic
+        line["roofline"]["traffic_over_algorithmic"] = round(traffic / b, 4)
     print(json.dumps(line), flush=True)
 
 
