@@ -55,7 +55,7 @@ struct KState {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
-// Scalar update of a reduction, run by one thread of the last work-group.
+// Scalar update after a reduction, run by one thread of the finisher kernel.
 __device__ inline void finish_op(int op, const double *t, KState *st)
 {
     switch (op) {

@@ -7,8 +7,8 @@
 // "twice is enough": Giraud, Langou, Rozloznik 2005): two passes of
 //   h = V^T w (one multi-dot kernel: each work-group keeps its chunk of w in
 //   registers and sweeps every basis vector), w -= V h,
-// the second update fused with ||w||^2. The last work-group of that reduction
-// builds the Hessenberg column, applies the previous Givens rotations, forms
+// the second update fused with ||w||^2. A one-work-group finisher kernel that
+// sums the partials of that reduction builds the Hessenberg column, applies the previous Givens rotations, forms
 // the new one, updates the residual estimate |g_{j+1}| and decides whether the
 // cycle ends (estimate below tolerance, lucky breakdown, or maxit). All of
 // this stays on the device; one restart cycle (m Arnoldi steps) is a single
