@@ -240,15 +240,24 @@ spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const dou
                         hipStream_t stream);
 
 /* ------------------------------------------------------------ batched CG and the solve server
- * Many independent float64 CSR systems advanced by ONE persistent kernel:
- * each resident work-group takes a system from an atomic counter and runs
- * CG on it by itself (product, updates and fixed-order reductions inside the
- * group), so a system's iterates are bitwise the same alone or in any batch.
- * Unpreconditioned CG from x = 0 to ||b - A x|| <= tol ||b|| (true residual
- * confirmed). */
+ * Many independent float64 CSR systems solved together by unpreconditioned CG
+ * (the solver of Section 4) from x = 0 to ||b - A x|| <= tol ||b||, the true
+ * residual confirming convergence. Two paths, chosen per system by its size:
+ *  - one work-group per system: a persistent kernel whose resident
+ *    work-groups take systems from an atomic counter and run all of a
+ *    system's CG iterations by themselves (product, updates and fixed-order
+ *    reductions inside the group);
+ *  - wide systems (n >= 16384 by default): several work-groups per system,
+ *    one CG iteration as four grid-wide launches over every wide system at
+ *    once, each system cut into fixed blocks of 1024 rows whose partial sums
+ *    are added in a fixed order.
+ * Neither path lets one system's arithmetic depend on another's, so a
+ * system's iterates are bitwise the same alone or in any batch or mix. */
+typedef enum { SPX_BATCH_AUTO = 0, SPX_BATCH_ONE_GROUP = 1, SPX_BATCH_WIDE = 2 } spx_batch_path;
+
 typedef struct {
     int32_t n;              /* rows (square system)                        */
-    int32_t reserved0;
+    int32_t path;           /* spx_batch_path (AUTO: wide iff n >= 16384)  */
     int64_t nnz;
     const int32_t *rowptr;  /* DEVICE CSR, float64 values                  */
     const int32_t *colidx;
@@ -275,9 +284,12 @@ spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t w
  * caller until the ticket completes); the server copies them into its HBM
  * pool (one allocation of hbm_budget_bytes, made at creation) when a slot and
  * memory are free, keeps each system and its CG state resident, and advances
- * all admitted systems together, tick after tick, in the persistent batched
- * kernel captured in a hipGraph; admission and retirement happen between
- * ticks. A finished request's solution is copied to x_out. */
+ * all admitted systems together, tick after tick: the small ones in the
+ * persistent one-work-group-per-system kernel, the wide ones in blocks of
+ * wide iterations, each captured in a hipGraph and run concurrently on two
+ * streams. Admission and retirement happen between ticks. A finished
+ * request's solution is copied to x_out; it is bitwise the solution that
+ * spx_cg_batch gives for the same system alone with the same path. */
 typedef struct spx_server spx_server;
 
 typedef struct {
@@ -286,6 +298,9 @@ typedef struct {
     size_t hbm_budget_bytes; /* device memory for matrices and Krylov vectors   */
     int32_t iters_per_tick;  /* CG iterations per system per tick (0 = adaptive) */
     int32_t tick_us;         /* adaptive budget: target tick length (0 = 2000)  */
+    int32_t wide_min_rows;   /* systems with n >= this take the wide path
+                                (0 = 16384, as SPX_BATCH_AUTO; < 0 = never)      */
+    int32_t reserved;
 } spx_server_config;
 
 typedef struct {

@@ -42,6 +42,56 @@ inline int32_t batch_sub_for(int64_t n, int64_t nnz)
     return s;
 }
 
+// ---------------------------------------------------------------- wide systems
+// Systems too large for one work-group are advanced together by a sequence of
+// grid-wide phases. Each wide system is cut into virtual blocks of kWideRows
+// rows; every phase launches a fixed grid that strides over the virtual
+// blocks of all wide systems (vb_slot maps a virtual block to its system).
+// A system's partition, partial sums and their fixed summation order depend
+// only on its own n, so its iterates are bitwise the same alone or in any mix.
+constexpr int kWideThreads = 256;
+constexpr int kWideRows = 1024;
+
+enum WideMode : int32_t {
+    kWideInit = 0,   // r = b (x0 = 0), p = r, bb = ||b||^2
+    kWideRun = 1,    // one CG iteration per phase sequence
+    kWideCheck = 2,  // true residual b - A x
+    kWideDone = 3,
+};
+
+// Written by the host when the system is admitted.
+struct WideSlot {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *b;
+    double *x, *r, *p, *q;
+    double *part;  // 2 * nvb partial sums
+    int32_t n, nvb, sub, maxit;
+    double tol2;
+};
+
+// Written by the device (the commit phase) and once at admission.
+struct WideState {
+    int32_t mode, status, iters, spmv;  // status: SlotStatus
+    double rho, bb, rr, relres_true;
+};
+
+// Header of the virtual-block map, device memory: {total virtual blocks,
+// number of listed systems}; list[] holds the slot index of each listed system.
+struct WideMap {
+    int32_t total_vb;
+    int32_t nlisted;
+};
+
+inline int32_t wide_nvb(int64_t n) { return (int32_t)((n + kWideRows - 1) / kWideRows); }
+
+// One iteration (four launches: product, update, direction, commit) for all
+// listed wide systems. grid: physical blocks of the three vector phases.
+spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
+                                 const int32_t *vb_slot, const int32_t *vb_local, int grid, int commit_grid,
+                                 hipStream_t stream);
+
 // Advance slots[0..nslots) by at most slot.budget CG iterations each (or to
 // convergence); work-groups take slots from *counter, which must be 0 at
 // launch (batch_reset does that). grid: number of resident work-groups.

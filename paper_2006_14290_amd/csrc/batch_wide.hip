@@ -1,0 +1,270 @@
+// batch_wide.hip -- CG on many large systems at once, several work-groups per
+// system, no synchronisation between work-groups inside a launch.
+//
+// Unpreconditioned CG (Hestenes & Stiefel), x0 = 0, one iteration as four
+// grid-wide phases over every listed system (a launch boundary is the only
+// global synchronisation):
+//   A  q = A p (or q = A x in the true-residual mode), partial sums of p.q;
+//   B  alpha = rho / p.q from the partials; x += alpha p, r -= alpha q,
+//      partial sums of r.r (true-residual mode: r = b - q; init: r = b);
+//   C  beta = r.r / rho from the partials; p = r + beta p (or p = r on a
+//      restart or at init) -- skipped once r.r passes the tolerance;
+//   D  commit: one work-group per system re-forms the same sums and updates
+//      the scalar state (rho, iteration count, mode, status).
+// Every work-group that needs a sum forms it from the same partials in the
+// same order, so all of them take the same decisions. A system's virtual
+// blocks, partials and summation order depend only on its own size; its
+// arithmetic is therefore independent of the other systems in the launch.
+#include "batch_cg.hpp"
+#include "wave.hpp"
+
+namespace spx {
+
+constexpr int kWideWaves = kWideThreads / kWave;
+
+// Work-group sum in a fixed order (result in every thread).
+__device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
+{
+    v = wave_sum(v);
+    __syncthreads();  // s_red may still be read by a previous call
+    if (lane_id() == 0) s_red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWideWaves; ++w) t += s_red[w];
+    return t;
+}
+
+// Sum of part[0..cnt): thread t takes t, t + 256, ... in order, then the
+// fixed work-group reduction.
+__device__ __forceinline__ double wide_part_sum(const double *part, int32_t cnt, double *s_red)
+{
+    double t = 0.0;
+    for (int32_t i = threadIdx.x; i < cnt; i += kWideThreads) t += part[i];
+    return wide_wg_sum(t, s_red);
+}
+
+// q[rows] = A v[rows]; returns the work-group sum of v_i q_i over the rows if dot.
+__device__ __forceinline__ double wide_rows_spmv(const WideSlot &S, int32_t r0, int32_t r1, const double *__restrict__ v,
+                                                 double *__restrict__ q, bool dot, double *s_red)
+{
+    const int sub = S.sub;
+    const int g = threadIdx.x / sub, sl = threadIdx.x % sub;
+    const int G = kWideThreads / sub;
+    double acc = 0.0;
+    for (int32_t row0 = r0; row0 < r1; row0 += G) {  // uniform trip count: whole subwaves reduce together
+        const int32_t row = row0 + g;
+        double sum = 0.0;
+        if (row < r1) {
+            const int32_t a = S.rowptr[row], b = S.rowptr[row + 1];
+            for (int32_t k = a + sl; k < b; k += sub) sum += S.val[k] * v[S.col[k]];
+        }
+        sum = subwave_sum_dyn(sum, sub);
+        if (row < r1 && sl == 0) {
+            q[row] = sum;
+            if (dot) acc += sum * v[row];
+        }
+    }
+    return dot ? wide_wg_sum(acc, s_red) : 0.0;
+}
+
+__global__ __launch_bounds__(kWideThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
+                                                              const WideState *__restrict__ st,
+                                                              const WideMap *__restrict__ map,
+                                                              const int32_t *__restrict__ vb_slot,
+                                                              const int32_t *__restrict__ vb_local)
+{
+    __shared__ double s_red[kWideWaves];
+    const int32_t total = map->total_vb;
+    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
+        const int32_t s = vb_slot[v], lv = vb_local[v];
+        const int32_t mode = st[s].mode;
+        if (mode != kWideRun && mode != kWideCheck) continue;
+        const WideSlot S = slots[s];
+        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
+        if (mode == kWideRun) {
+            const double pq = wide_rows_spmv(S, r0, r1, S.p, S.q, true, s_red);
+            if (threadIdx.x == 0) S.part[lv] = pq;
+        } else {
+            wide_rows_spmv(S, r0, r1, S.x, S.q, false, s_red);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWideThreads) void wide_b_kernel(const WideSlot *__restrict__ slots,
+                                                              const WideState *__restrict__ st,
+                                                              const WideMap *__restrict__ map,
+                                                              const int32_t *__restrict__ vb_slot,
+                                                              const int32_t *__restrict__ vb_local)
+{
+    __shared__ double s_red[kWideWaves];
+    const int32_t total = map->total_vb;
+    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
+        const int32_t s = vb_slot[v], lv = vb_local[v];
+        const int32_t mode = st[s].mode;
+        if (mode == kWideDone) continue;
+        const WideSlot S = slots[s];
+        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
+        double t = 0.0;
+        if (mode == kWideRun) {
+            const double pq = wide_part_sum(S.part, S.nvb, s_red);
+            if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;  // the commit phase records the breakdown
+            const double alpha = st[s].rho / pq;
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                S.x[i] += alpha * S.p[i];
+                const double ri = S.r[i] - alpha * S.q[i];
+                S.r[i] = ri;
+                t += ri * ri;
+            }
+        } else if (mode == kWideCheck) {
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                const double ri = S.b[i] - S.q[i];
+                S.r[i] = ri;
+                t += ri * ri;
+            }
+        } else {  // init: x = 0 was written at admission
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                const double bi = S.b[i];
+                S.r[i] = bi;
+                t += bi * bi;
+            }
+        }
+        t = wide_wg_sum(t, s_red);
+        if (threadIdx.x == 0) S.part[S.nvb + lv] = t;
+    }
+}
+
+__global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__restrict__ slots,
+                                                              const WideState *__restrict__ st,
+                                                              const WideMap *__restrict__ map,
+                                                              const int32_t *__restrict__ vb_slot,
+                                                              const int32_t *__restrict__ vb_local)
+{
+    __shared__ double s_red[kWideWaves];
+    const int32_t total = map->total_vb;
+    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
+        const int32_t s = vb_slot[v], lv = vb_local[v];
+        const int32_t mode = st[s].mode;
+        if (mode == kWideDone) continue;
+        const WideSlot S = slots[s];
+        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
+        const double bb = st[s].bb;
+        if (mode == kWideRun) {
+            const double pq = wide_part_sum(S.part, S.nvb, s_red);
+            if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;
+            const double rr = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+            if (!__builtin_isfinite(rr) || rr <= S.tol2 * bb) continue;  // stop or check next
+            const double beta = rr / st[s].rho;
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i] + beta * S.p[i];
+        } else if (mode == kWideCheck) {
+            const double tr = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+            if (tr <= S.tol2 * bb) continue;
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];  // restart
+        } else {
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];
+        }
+    }
+}
+
+// Scalar state update of one system from the two partial sums of this
+// iteration (s1: p.q, s2: r.r or the true residual or b.b).
+__device__ void commit(WideState &W, const WideSlot &S, double s1, double s2)
+{
+    if (W.mode == kWideRun) {
+        W.spmv += 1;
+        if (!__builtin_isfinite(s1)) {
+            W.status = kSlotNonfinite;
+            W.mode = kWideDone;
+        } else if (!(s1 > 0.0)) {
+            W.status = kSlotBreakdown;
+            W.mode = kWideDone;
+        } else {
+            W.iters += 1;
+            W.rr = s2;
+            if (!__builtin_isfinite(s2)) {
+                W.status = kSlotNonfinite;
+                W.mode = kWideDone;
+            } else if (s2 <= S.tol2 * W.bb) {
+                W.mode = kWideCheck;
+            } else {
+                W.rho = s2;
+                if (W.iters >= S.maxit) {
+                    W.status = kSlotMaxit;
+                    W.mode = kWideDone;
+                }
+            }
+        }
+    } else if (W.mode == kWideCheck) {
+        W.spmv += 1;
+        W.rr = s2;
+        if (s2 <= S.tol2 * W.bb) {
+            W.status = kSlotConverged;
+            W.relres_true = sqrt(s2 / W.bb);
+            W.mode = kWideDone;
+        } else if (!__builtin_isfinite(s2)) {
+            W.status = kSlotNonfinite;
+            W.mode = kWideDone;
+        } else {
+            W.rho = s2;
+            W.mode = kWideRun;
+            if (W.iters >= S.maxit) {
+                W.status = kSlotMaxit;
+                W.mode = kWideDone;
+            }
+        }
+    } else {  // init
+        W.bb = s2;
+        W.rho = s2;
+        W.rr = s2;
+        if (!__builtin_isfinite(s2)) {
+            W.status = kSlotNonfinite;
+            W.mode = kWideDone;
+        } else if (s2 == 0.0) {
+            W.status = kSlotConverged;
+            W.relres_true = 0.0;
+            W.mode = kWideDone;
+        } else {
+            W.mode = kWideRun;
+        }
+    }
+    if (W.mode == kWideDone && W.status != kSlotConverged) W.relres_true = W.bb > 0 ? sqrt(W.rr / W.bb) : 0.0;
+}
+
+// Commit: one work-group per listed system.
+__global__ __launch_bounds__(kWideThreads) void wide_d_kernel(const WideSlot *__restrict__ slots,
+                                                              WideState *__restrict__ st,
+                                                              const WideMap *__restrict__ map,
+                                                              const int32_t *__restrict__ list)
+{
+    __shared__ double s_red[kWideWaves];
+    const int32_t nl = map->nlisted;
+    for (int32_t k = blockIdx.x; k < nl; k += gridDim.x) {
+        const int32_t s = list[k];
+        WideState W = st[s];
+        if (W.mode == kWideDone) continue;
+        const WideSlot S = slots[s];
+        const double s1 = wide_part_sum(S.part, S.nvb, s_red);
+        const double s2 = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+        if (threadIdx.x == 0) {
+            commit(W, S, s1, s2);
+            st[s] = W;
+        }
+    }
+}
+
+spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
+                                 const int32_t *vb_slot, const int32_t *vb_local, int grid, int commit_grid,
+                                 hipStream_t stream)
+{
+    wide_a_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
+    SPX_LAUNCHED();
+    wide_b_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
+    SPX_LAUNCHED();
+    wide_c_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
+    SPX_LAUNCHED();
+    wide_d_kernel<<<commit_grid, kWideThreads, 0, stream>>>(slots, st, map, list);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+}  // namespace spx

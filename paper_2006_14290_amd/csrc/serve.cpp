@@ -8,14 +8,16 @@
 // hbm_budget_bytes made at creation, carved first-fit) can hold the matrix and
 // its Krylov vectors, looking past a request that does not fit at most
 // kBackfill places. Admitted requests are copied to the device on a copy
-// stream while the current tick runs. A tick is one captured hipGraph (reset
-// the work counter, run the persistent batched-CG kernel over the slot table)
-// that advances every active slot by its iteration budget; between ticks the
-// worker reads the slot table back, copies the solutions of finished slots to
-// the callers' buffers, frees their memory and slots, and admits more. The
-// per-slot budget keeps a tick around tick_us of work so that new requests
-// join within a few milliseconds (continuous batching). Matrices and Krylov
-// state stay resident in HBM between ticks.
+// stream while the current tick runs. A tick runs two captured hipGraphs on
+// two streams at once: the narrow graph (reset the work counter, run the
+// persistent one-group-per-system kernel over the slot table) advances every
+// small system by its iteration budget; the wide graph (kWideIters iterations
+// of the four wide phases) advances every large system, launched as many
+// times as fits the tick. Between ticks the worker reads the state back,
+// copies the solutions of finished systems to the callers' buffers, frees
+// their memory and slots, and admits more: new requests join within a few
+// milliseconds (continuous batching). Matrices and Krylov state stay resident
+// in HBM between ticks.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -40,11 +42,23 @@ constexpr int kBackfill = 8;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Device bytes of one system: CSR arrays + b, x, r, p, q.
-size_t system_bytes(int64_t n, int64_t nnz)
+constexpr int kWideIters = 8;                    // wide iterations per graph launch
+constexpr int kWideGrids[3] = {256, 1024, 4096};  // physical grids of the wide graphs
+constexpr int kWideCommitGrid = 128;
+constexpr int32_t kWideDefaultRows = 16384;
+
+// Device bytes of one system: CSR arrays + b, x, r, p, q (+ the partial sums
+// of the wide path).
+size_t system_bytes(int64_t n, int64_t nnz, bool wide)
 {
     return align256((size_t)(n + 1) * 4) + align256((size_t)nnz * 4) + align256((size_t)nnz * 8) +
-           5 * align256((size_t)n * 8);
+           5 * align256((size_t)n * 8) + (wide ? align256((size_t)wide_nvb(n) * 16) : 0);
+}
+
+bool is_wide(int32_t wide_min_rows, int64_t n)
+{
+    const int64_t t = wide_min_rows == 0 ? kWideDefaultRows : wide_min_rows;
+    return wide_min_rows >= 0 && n >= t;
 }
 
 struct Pool {
@@ -97,6 +111,7 @@ struct Pending {
     spx_request req;
     Clock::time_point t_submit;
     size_t bytes;
+    bool wide;
 };
 
 struct Active {
@@ -108,7 +123,9 @@ struct Active {
     Clock::time_point t_submit;
     bool cancel = false;
     bool live = false;
-    bool staged = false;  // descriptor waiting in spx_server::staged
+    bool staged = false;  // descriptor waiting in spx_server::staged / wstaged
+    bool wide = false;
+    bool in_map = false;  // listed in the wide map uploaded for the current tick
 };
 
 struct Result {
@@ -133,14 +150,27 @@ spx_status slot_status_to_spx(int32_t s)
 struct spx_server {
     spx_server_config cfg{};
     int device = 0;
-    hipStream_t s_compute = nullptr, s_copy = nullptr;
+    hipStream_t s_compute = nullptr, s_copy = nullptr, s_wide = nullptr;
     char *pool_base = nullptr;
     Pool pool;
     BatchSlot *slots_dev = nullptr;
     BatchSlot *slots_host = nullptr;  // pinned mirror
     std::vector<BatchSlot> staged;    // descriptors of slots admitted since the last table upload
     int32_t *counter = nullptr;
-    hipGraphExec_t tick = nullptr;
+    hipGraphExec_t tick = nullptr;       // narrow tick, full persistent grid
+    hipGraphExec_t tick_half = nullptr;  // narrow tick, half grid (wide work running beside it)
+    // wide path: descriptor table, device state, map (header, list, virtual blocks)
+    WideSlot *wslots_dev = nullptr, *wslots_host = nullptr;
+    WideState *wstate_dev = nullptr, *wstate_host = nullptr, *winit_host = nullptr;
+    WideMap *wmap_dev = nullptr, *wmap_host = nullptr;
+    int32_t *wlist_dev = nullptr, *wlist_host = nullptr;
+    int32_t *vb_dev = nullptr, *vb_host = nullptr;  // [2 * vb_cap]: slot, then local index
+    int64_t vb_cap = 0;
+    std::vector<WideSlot> wstaged;
+    hipGraphExec_t wide_tick[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
+    bool wide_dirty = false;
+    int wide_launches = 1;  // wide graph launches per tick (adapted to tick_us)
     std::vector<Active> active;
     std::deque<Pending> queue;
     std::unordered_map<uint64_t, Result> results;
@@ -234,6 +264,7 @@ int admit(spx_server &S)
         double *r = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *pp = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *q = reinterpret_cast<double *>(carve((size_t)n * 8));
+        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 16)) : nullptr;
         (void)hipMemcpyAsync(rp, p.req.rowptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, S.s_copy);
         if (nnz > 0) {
             (void)hipMemcpyAsync(ci, p.req.colidx, (size_t)nnz * 4, hipMemcpyHostToDevice, S.s_copy);
@@ -241,6 +272,40 @@ int admit(spx_server &S)
         }
         (void)hipMemcpyAsync(b, p.req.b, (size_t)n * 8, hipMemcpyHostToDevice, S.s_copy);
         (void)hipMemsetAsync(x, 0, (size_t)n * 8, S.s_copy);
+        a.wide = p.wide;
+        a.in_map = false;
+        if (p.wide) {
+            WideSlot &w = S.wstaged[si];
+            std::memset(&w, 0, sizeof(w));
+            w.rowptr = rp;
+            w.col = ci;
+            w.val = va;
+            w.b = b;
+            w.x = x;
+            w.r = r;
+            w.p = pp;
+            w.q = q;
+            w.part = part;
+            w.n = (int32_t)n;
+            w.nvb = wide_nvb(n);
+            w.sub = batch_sub_for(n, nnz);
+            w.maxit = p.req.maxit > 0 ? p.req.maxit : 100000;
+            w.tol2 = p.req.tol * p.req.tol;
+            WideState &ws = S.winit_host[si];
+            std::memset(&ws, 0, sizeof(ws));
+            ws.mode = kWideInit;
+            (void)hipMemcpyAsync(S.wstate_dev + si, &ws, sizeof(WideState), hipMemcpyHostToDevice, S.s_copy);
+            a.ticket = p.ticket;
+            a.x_dev = x;
+            a.x_out = p.req.x_out;
+            a.n = n;
+            a.nnz = nnz;
+            a.t_submit = p.t_submit;
+            a.cancel = false;
+            a.live = true;
+            a.staged = true;
+            continue;
+        }
         BatchSlot &d = S.staged[si];
         std::memset(&d, 0, sizeof(d));
         d.rowptr = rp;
@@ -277,33 +342,92 @@ void apply_staged(spx_server &S)
 {
     for (int i = 0; i < (int)S.active.size(); ++i)
         if (S.active[i].staged) {
-            S.slots_host[i] = S.staged[i];
+            if (S.active[i].wide) {
+                S.wslots_host[i] = S.wstaged[i];
+                S.wstate_host[i] = S.winit_host[i];
+                S.wide_dirty = true;
+            } else {
+                S.slots_host[i] = S.staged[i];
+            }
             S.active[i].staged = false;
         }
+}
+
+// List every live, uncancelled wide system and map the virtual blocks onto
+// them; upload the tables on the wide stream (called between ticks only).
+bool rebuild_wide_map(spx_server &S)
+{
+    int32_t nl = 0;
+    int64_t tot = 0;
+    for (int i = 0; i < (int)S.active.size(); ++i) {
+        Active &a = S.active[i];
+        a.in_map = false;
+        if (!a.live || !a.wide || a.staged || a.cancel) continue;
+        const int32_t nvb = S.wslots_host[i].nvb;
+        if (tot + nvb > S.vb_cap) return false;
+        S.wlist_host[nl++] = i;
+        for (int32_t k = 0; k < nvb; ++k) {
+            S.vb_host[tot + k] = i;
+            S.vb_host[S.vb_cap + tot + k] = k;
+        }
+        tot += nvb;
+        a.in_map = true;
+    }
+    S.wmap_host->total_vb = (int32_t)tot;
+    S.wmap_host->nlisted = nl;
+    const size_t tb = sizeof(WideSlot) * S.active.size();
+    hipError_t e = hipMemcpyAsync(S.wslots_dev, S.wslots_host, tb, hipMemcpyHostToDevice, S.s_wide);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.wmap_dev, S.wmap_host, sizeof(WideMap), hipMemcpyHostToDevice, S.s_wide);
+    if (e == hipSuccess && nl > 0)
+        e = hipMemcpyAsync(S.wlist_dev, S.wlist_host, sizeof(int32_t) * nl, hipMemcpyHostToDevice, S.s_wide);
+    if (e == hipSuccess && tot > 0) {
+        e = hipMemcpyAsync(S.vb_dev, S.vb_host, sizeof(int32_t) * tot, hipMemcpyHostToDevice, S.s_wide);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.vb_dev + S.vb_cap, S.vb_host + S.vb_cap, sizeof(int32_t) * tot,
+                               hipMemcpyHostToDevice, S.s_wide);
+    }
+    S.wide_dirty = false;
+    return e == hipSuccess;
 }
 
 void retire(spx_server &S)
 {
     for (int i = 0; i < (int)S.active.size(); ++i) {
         Active &a = S.active[i];
-        if (!a.live) continue;
-        BatchSlot &d = S.slots_host[i];
-        if (d.status == kSlotRunning && !a.cancel) continue;
+        if (!a.live || a.staged) continue;
         spx_solve_info info{};
-        spx_status st = a.cancel ? SPX_CANCELLED : slot_status_to_spx(d.status);
+        spx_status st;
+        if (a.wide) {
+            // the host copy of the state is current only for systems that were
+            // listed in this tick's launches
+            const WideState &w = S.wstate_host[i];
+            const bool done = a.in_map && w.mode == kWideDone;
+            if (!done && !a.cancel) continue;
+            st = a.cancel ? SPX_CANCELLED : slot_status_to_spx(w.status);
+            info.iters = w.iters;
+            info.spmv_count = w.spmv;
+            info.relres_recursive = w.bb > 0 ? sqrt(w.rr / w.bb) : 0.0;
+            info.relres_true = w.relres_true;
+            S.wide_dirty = true;
+        } else {
+            BatchSlot &d = S.slots_host[i];
+            if (d.status == kSlotRunning && !a.cancel) continue;
+            st = a.cancel ? SPX_CANCELLED : slot_status_to_spx(d.status);
+            info.iters = d.iters;
+            info.spmv_count = d.spmv;
+            info.relres_recursive = d.bb > 0 ? sqrt(d.rr / d.bb) : 0.0;
+            info.relres_true = d.relres_true;
+            d.status = kSlotEmpty;
+        }
         if (!a.cancel && a.x_out) (void)hipMemcpy(a.x_out, a.x_dev, (size_t)a.n * 8, hipMemcpyDeviceToHost);
         info.status = st;
-        info.iters = d.iters;
-        info.spmv_count = d.spmv;
-        info.relres_recursive = d.bb > 0 ? sqrt(d.rr / d.bb) : 0.0;
-        info.relres_true = d.relres_true;
         info.device_ms = std::chrono::duration<double, std::milli>(Clock::now() - a.t_submit).count();
         {
             std::lock_guard<std::mutex> lk(S.mu);
             S.pool.release(a.off, a.bytes);
         }
-        d.status = kSlotEmpty;
         a.live = false;
+        a.in_map = false;
         finish_ticket(S, a.ticket, st, info);
     }
 }
@@ -313,7 +437,7 @@ void worker_main(spx_server *Sp)
     spx_server &S = *Sp;
     (void)hipSetDevice(S.device);
     while (!S.stop.load()) {
-        int admitted = admit(S);
+        admit(S);
         bool any = false;
         for (auto &a : S.active) any |= a.live;
         if (!any) {
@@ -321,43 +445,72 @@ void worker_main(spx_server *Sp)
             if (S.queue.empty() && !S.stop.load()) S.cv_work.wait_for(lk, std::chrono::milliseconds(1));
             continue;
         }
-        (void)admitted;
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
             S.fatal = "admission copy failed";
             break;
         }
         apply_staged(S);
+        if (S.wide_dirty && !rebuild_wide_map(S)) {
+            S.fatal = "wide map upload failed";
+            break;
+        }
+        const int32_t nwide = S.wmap_host->nlisted;
+        bool narrow = false;
         for (int i = 0; i < (int)S.active.size(); ++i) {
-            if (!S.active[i].live) continue;
+            if (!S.active[i].live || S.active[i].wide) continue;
             BatchSlot &d = S.slots_host[i];
             if (S.active[i].cancel) {
                 d.budget = 0;
                 continue;
             }
             d.budget = budget_for(S, S.active[i].n, S.active[i].nnz, std::max(1, d.maxit - d.iters));
+            narrow = true;
         }
-        const size_t tb = sizeof(BatchSlot) * S.active.size();
-        hipError_t e = hipMemcpyAsync(S.slots_dev, S.slots_host, tb, hipMemcpyHostToDevice, S.s_compute);
-        if (e == hipSuccess) e = hipGraphLaunch(S.tick, S.s_compute);
-        if (e == hipSuccess) e = hipMemcpyAsync(S.slots_host, S.slots_dev, tb, hipMemcpyDeviceToHost, S.s_compute);
+        hipError_t e = hipSuccess;
+        if (narrow) {
+            const size_t tb = sizeof(BatchSlot) * S.active.size();
+            e = hipMemcpyAsync(S.slots_dev, S.slots_host, tb, hipMemcpyHostToDevice, S.s_compute);
+            if (e == hipSuccess) e = hipGraphLaunch(nwide > 0 ? S.tick_half : S.tick, S.s_compute);
+            if (e == hipSuccess) e = hipMemcpyAsync(S.slots_host, S.slots_dev, tb, hipMemcpyDeviceToHost, S.s_compute);
+        }
+        if (nwide > 0 && e == hipSuccess) {
+            const int32_t tot = S.wmap_host->total_vb;
+            const int gi = tot <= kWideGrids[0] ? 0 : (tot <= kWideGrids[1] ? 1 : 2);
+            e = hipEventRecord(S.ev_w0, S.s_wide);
+            for (int l = 0; l < S.wide_launches && e == hipSuccess; ++l) e = hipGraphLaunch(S.wide_tick[gi], S.s_wide);
+            if (e == hipSuccess) e = hipEventRecord(S.ev_w1, S.s_wide);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(S.wstate_host, S.wstate_dev, sizeof(WideState) * S.active.size(),
+                                   hipMemcpyDeviceToHost, S.s_wide);
+        }
         // admit more while the tick runs (descriptors stay staged until the
-        // read-back of the table has landed)
+        // read-back of the tables has landed)
         admit(S);
         if (e == hipSuccess) e = hipStreamSynchronize(S.s_compute);
+        if (e == hipSuccess) e = hipStreamSynchronize(S.s_wide);
         if (e != hipSuccess) {
             S.fatal = hipGetErrorString(e);
             break;
+        }
+        if (nwide > 0) {
+            // size the next tick's wide work to about tick_us
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, S.ev_w0, S.ev_w1) == hipSuccess && ms > 0.f) {
+                const double tick_ms = (S.cfg.tick_us > 0 ? S.cfg.tick_us : 2000) * 1e-3;
+                const double per = ms / S.wide_launches;
+                S.wide_launches = (int)std::max(1.0, std::min(64.0, tick_ms / per));
+            }
         }
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
             S.fatal = "admission copy failed";
             break;
         }
-        apply_staged(S);
         {
             std::lock_guard<std::mutex> lk(S.mu);
             S.stats.ticks += 1;
         }
-        retire(S);
+        retire(S);  // before apply_staged: newly admitted systems have no state to read yet
+        apply_staged(S);
     }
     // fail whatever is left
     std::lock_guard<std::mutex> lk(S.mu);
@@ -372,6 +525,59 @@ void worker_main(spx_server *Sp)
 
 }  // namespace
 
+namespace {
+
+void server_free(spx_server *S)
+{
+    if (S->tick) (void)hipGraphExecDestroy(S->tick);
+    if (S->tick_half) (void)hipGraphExecDestroy(S->tick_half);
+    for (auto &g : S->wide_tick)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (S->ev_w0) (void)hipEventDestroy(S->ev_w0);
+    if (S->ev_w1) (void)hipEventDestroy(S->ev_w1);
+    for (void *p : {(void *)S->pool_base, (void *)S->slots_dev, (void *)S->counter, (void *)S->wslots_dev,
+                    (void *)S->wstate_dev, (void *)S->wmap_dev, (void *)S->wlist_dev, (void *)S->vb_dev})
+        if (p) (void)hipFree(p);
+    for (void *p : {(void *)S->slots_host, (void *)S->wslots_host, (void *)S->wstate_host, (void *)S->winit_host,
+                    (void *)S->wmap_host, (void *)S->wlist_host, (void *)S->vb_host})
+        if (p) (void)hipHostFree(p);
+    if (S->s_compute) (void)hipStreamDestroy(S->s_compute);
+    if (S->s_copy) (void)hipStreamDestroy(S->s_copy);
+    if (S->s_wide) (void)hipStreamDestroy(S->s_wide);
+    delete S;
+}
+
+// Capture `launch(stream)` into an executable graph.
+template <typename F>
+hipError_t capture(hipStream_t stream, F launch, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const spx_status st = launch(stream);
+    e = hipStreamEndCapture(stream, &g);
+    if (e == hipSuccess && st != SPX_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+}
+
+template <typename T>
+hipError_t host_alloc(T **p, size_t count)
+{
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), sizeof(T) * count, hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(*p, 0, sizeof(T) * count);
+    return e;
+}
+
+}  // namespace
+
 extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server **out)
 {
     clear_error();
@@ -381,46 +587,71 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     auto *S = new spx_server();
     S->cfg = *cfg;
     S->device = cfg->device;
-    auto fail = [&](const char *what, hipError_t e) {
+    const size_t ms = (size_t)cfg->max_slots;
+    // every wide row costs at least 44 pool bytes (row pointer + five vectors)
+    S->vb_cap = (int64_t)(cfg->hbm_budget_bytes / (44 * (size_t)kWideRows)) + (int64_t)ms + 1;
+    hipError_t e;
+    auto fail = [&](const char *what) {
         set_error("spx_server_create: %s: %s", what, hipGetErrorString(e));
-        if (S->tick) (void)hipGraphExecDestroy(S->tick);
-        if (S->pool_base) (void)hipFree(S->pool_base);
-        if (S->slots_dev) (void)hipFree(S->slots_dev);
-        if (S->counter) (void)hipFree(S->counter);
-        if (S->slots_host) (void)hipHostFree(S->slots_host);
-        if (S->s_compute) (void)hipStreamDestroy(S->s_compute);
-        if (S->s_copy) (void)hipStreamDestroy(S->s_copy);
-        delete S;
+        server_free(S);
         return e == hipErrorOutOfMemory ? SPX_ERR_NOMEM : SPX_ERR_HIP;
     };
-    hipError_t e;
-    if ((e = hipSetDevice(S->device)) != hipSuccess) return fail("hipSetDevice", e);
-    if ((e = hipStreamCreateWithFlags(&S->s_compute, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
-    if ((e = hipStreamCreateWithFlags(&S->s_copy, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
-    if ((e = hipMalloc(reinterpret_cast<void **>(&S->pool_base), cfg->hbm_budget_bytes)) != hipSuccess)
-        return fail("pool", e);
+    if ((e = hipSetDevice(S->device)) != hipSuccess) return fail("hipSetDevice");
+    if ((e = hipStreamCreateWithFlags(&S->s_compute, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
+    if ((e = hipStreamCreateWithFlags(&S->s_copy, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
+    if ((e = hipStreamCreateWithFlags(&S->s_wide, hipStreamNonBlocking)) != hipSuccess) return fail("stream");
+    if ((e = hipEventCreate(&S->ev_w0)) != hipSuccess || (e = hipEventCreate(&S->ev_w1)) != hipSuccess)
+        return fail("event");
+    if ((e = dev_alloc(&S->pool_base, cfg->hbm_budget_bytes)) != hipSuccess) return fail("pool");
     S->pool.init(cfg->hbm_budget_bytes);
-    const size_t tb = sizeof(BatchSlot) * (size_t)cfg->max_slots;
-    if ((e = hipMalloc(reinterpret_cast<void **>(&S->slots_dev), tb)) != hipSuccess) return fail("slots", e);
-    if ((e = hipHostMalloc(reinterpret_cast<void **>(&S->slots_host), tb, hipHostMallocDefault)) != hipSuccess)
-        return fail("pinned slots", e);
-    std::memset(S->slots_host, 0, tb);
-    for (int i = 0; i < cfg->max_slots; ++i) S->slots_host[i].status = kSlotEmpty;
-    if ((e = hipMalloc(reinterpret_cast<void **>(&S->counter), sizeof(int32_t))) != hipSuccess)
-        return fail("counter", e);
-    // the tick: reset the counter, then the persistent batched kernel
-    hipGraph_t g = nullptr;
-    if ((e = hipStreamBeginCapture(S->s_compute, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-        return fail("capture", e);
-    spx_status s1 = batch_reset_launch(S->counter, S->s_compute);
-    spx_status s2 = batch_cg_launch(S->slots_dev, cfg->max_slots, S->counter, batch_resident_groups(), S->s_compute);
-    e = hipStreamEndCapture(S->s_compute, &g);
-    if (s1 != SPX_OK || s2 != SPX_OK || e != hipSuccess) return fail("capture", e != hipSuccess ? e : hipErrorUnknown);
-    e = hipGraphInstantiate(&S->tick, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail("instantiate", e);
-    S->active.resize(cfg->max_slots);
-    S->staged.resize(cfg->max_slots);
+    if ((e = dev_alloc(&S->slots_dev, ms)) != hipSuccess || (e = host_alloc(&S->slots_host, ms)) != hipSuccess ||
+        (e = dev_alloc(&S->counter, 1)) != hipSuccess || (e = dev_alloc(&S->wslots_dev, ms)) != hipSuccess ||
+        (e = host_alloc(&S->wslots_host, ms)) != hipSuccess || (e = dev_alloc(&S->wstate_dev, ms)) != hipSuccess ||
+        (e = host_alloc(&S->wstate_host, ms)) != hipSuccess || (e = host_alloc(&S->winit_host, ms)) != hipSuccess ||
+        (e = dev_alloc(&S->wmap_dev, 1)) != hipSuccess || (e = host_alloc(&S->wmap_host, 1)) != hipSuccess ||
+        (e = dev_alloc(&S->wlist_dev, ms)) != hipSuccess || (e = host_alloc(&S->wlist_host, ms)) != hipSuccess ||
+        (e = dev_alloc(&S->vb_dev, 2 * (size_t)S->vb_cap)) != hipSuccess ||
+        (e = host_alloc(&S->vb_host, 2 * (size_t)S->vb_cap)) != hipSuccess)
+        return fail("tables");
+    for (size_t i = 0; i < ms; ++i) {
+        S->slots_host[i].status = kSlotEmpty;
+        S->wstate_host[i].mode = kWideDone;
+    }
+    if ((e = hipMemcpy(S->wmap_dev, S->wmap_host, sizeof(WideMap), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail("map");
+    // narrow ticks: reset the counter, then the persistent kernel (full grid,
+    // and half the grid for ticks that run wide work beside it)
+    const int64_t groups = batch_resident_groups();
+    for (int half = 0; half < 2; ++half) {
+        const int64_t grid = half ? std::max<int64_t>(1, groups / 2) : groups;
+        e = capture(
+            S->s_compute,
+            [&](hipStream_t st) {
+                spx_status s1 = batch_reset_launch(S->counter, st);
+                return s1 != SPX_OK ? s1 : batch_cg_launch(S->slots_dev, cfg->max_slots, S->counter, grid, st);
+            },
+            half ? &S->tick_half : &S->tick);
+        if (e != hipSuccess) return fail("narrow tick capture");
+    }
+    // wide ticks: kWideIters iterations over the map, one graph per grid size
+    for (int gi = 0; gi < 3; ++gi) {
+        e = capture(
+            S->s_wide,
+            [&](hipStream_t st) {
+                for (int it = 0; it < kWideIters; ++it) {
+                    spx_status s1 = wide_iteration_launch(S->wslots_dev, S->wstate_dev, S->wmap_dev, S->wlist_dev,
+                                                          S->vb_dev, S->vb_dev + S->vb_cap, kWideGrids[gi],
+                                                          kWideCommitGrid, st);
+                    if (s1 != SPX_OK) return s1;
+                }
+                return SPX_OK;
+            },
+            &S->wide_tick[gi]);
+        if (e != hipSuccess) return fail("wide tick capture");
+    }
+    S->active.resize(ms);
+    S->staged.resize(ms);
+    S->wstaged.resize(ms);
     S->stats.pool_bytes_total = cfg->hbm_budget_bytes;
     S->worker = std::thread(worker_main, S);
     *out = S;
@@ -435,7 +666,8 @@ extern "C" spx_status spx_serve_submit(spx_server *S, const spx_request *req, ui
                 SPX_ERR_ARG, "spx_serve_submit: bad request");
     SPX_REQUIRE(req->solver == SPX_SOLVER_CG, SPX_ERR_ARG, "spx_serve_submit: only CG is served");
     SPX_REQUIRE(req->tol >= 0.0, SPX_ERR_ARG, "spx_serve_submit: negative tolerance");
-    const size_t bytes = system_bytes(req->n, req->nnz);
+    const bool wide = is_wide(S->cfg.wide_min_rows, req->n);
+    const size_t bytes = system_bytes(req->n, req->nnz, wide);
     std::lock_guard<std::mutex> lk(S->mu);
     SPX_REQUIRE(S->fatal.empty(), SPX_ERR_HIP, "spx_serve_submit: server failed: %s", S->fatal.c_str());
     if (bytes > S->cfg.hbm_budget_bytes) {
@@ -444,7 +676,7 @@ extern "C" spx_status spx_serve_submit(spx_server *S, const spx_request *req, ui
         return SPX_ERR_BUDGET;
     }
     const uint64_t t = S->next_ticket++;
-    S->queue.push_back(Pending{t, *req, Clock::now(), bytes});
+    S->queue.push_back(Pending{t, *req, Clock::now(), bytes, wide});
     S->results[t] = Result{};
     S->stats.submitted += 1;
     S->stats.queued = (int64_t)S->queue.size();
@@ -529,31 +761,68 @@ extern "C" spx_status spx_server_destroy(spx_server *S)
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
     (void)hipStreamSynchronize(S->s_compute);
+    (void)hipStreamSynchronize(S->s_wide);
     (void)hipStreamSynchronize(S->s_copy);
-    if (S->tick) (void)hipGraphExecDestroy(S->tick);
-    (void)hipFree(S->pool_base);
-    (void)hipFree(S->slots_dev);
-    (void)hipFree(S->counter);
-    (void)hipHostFree(S->slots_host);
-    (void)hipStreamDestroy(S->s_compute);
-    (void)hipStreamDestroy(S->s_copy);
-    delete S;
+    server_free(S);
     return SPX_OK;
 }
 
 // ------------------------------------------------------------------ spx_cg_batch
-static size_t batch_ws_bytes(const spx_batch_system *sys, int32_t count)
+namespace {
+
+bool batch_is_wide(const spx_batch_system &s)
 {
-    size_t b = align256(sizeof(BatchSlot) * (size_t)count) + 256;
-    for (int32_t i = 0; i < count; ++i) b += 3 * align256((size_t)sys[i].n * 8);
-    return b;
+    if (s.path == SPX_BATCH_WIDE) return true;
+    if (s.path == SPX_BATCH_ONE_GROUP) return false;
+    return s.n >= kWideDefaultRows;
 }
+
+// Workspace: narrow slot table, counter, wide tables, then per system r, p, q
+// (+ 2 * nvb partial sums for wide systems).
+struct BatchLayout {
+    size_t slots, counter, wslots, wstate, wmap, wlist, vb, vectors, total;
+    int64_t nwide, total_vb;
+};
+
+BatchLayout batch_layout(const spx_batch_system *sys, int32_t count)
+{
+    BatchLayout L{};
+    for (int32_t i = 0; i < count; ++i)
+        if (batch_is_wide(sys[i])) {
+            L.nwide += 1;
+            L.total_vb += wide_nvb(sys[i].n);
+        }
+    size_t off = 0;
+    L.slots = off;
+    off += align256(sizeof(BatchSlot) * (size_t)count);
+    L.counter = off;
+    off += 256;
+    L.wslots = off;
+    off += align256(sizeof(WideSlot) * (size_t)L.nwide);
+    L.wstate = off;
+    off += align256(sizeof(WideState) * (size_t)L.nwide);
+    L.wmap = off;
+    off += 256;
+    L.wlist = off;
+    off += align256(sizeof(int32_t) * (size_t)L.nwide);
+    L.vb = off;
+    off += align256(sizeof(int32_t) * 2 * (size_t)L.total_vb);
+    L.vectors = off;
+    for (int32_t i = 0; i < count; ++i) {
+        off += 3 * align256((size_t)sys[i].n * 8);
+        if (batch_is_wide(sys[i])) off += align256((size_t)wide_nvb(sys[i].n) * 16);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
 
 extern "C" spx_status spx_cg_batch_workspace(const spx_batch_system *sys, int32_t count, size_t *bytes)
 {
     clear_error();
     SPX_REQUIRE(sys && bytes && count >= 0, SPX_ERR_ARG, "spx_cg_batch_workspace: bad argument");
-    *bytes = batch_ws_bytes(sys, count);
+    *bytes = batch_layout(sys, count).total;
     return SPX_OK;
 }
 
@@ -563,49 +832,134 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
     clear_error();
     SPX_REQUIRE(sys && count >= 0, SPX_ERR_ARG, "spx_cg_batch: bad argument");
     if (count == 0) return SPX_OK;
-    SPX_REQUIRE(ws && ws_bytes >= batch_ws_bytes(sys, count), SPX_ERR_ARG, "spx_cg_batch: workspace too small");
-    for (int32_t i = 0; i < count; ++i)
+    for (int32_t i = 0; i < count; ++i) {
         SPX_REQUIRE(sys[i].n >= 1 && sys[i].rowptr && sys[i].b && sys[i].x && (sys[i].nnz == 0 || (sys[i].colidx && sys[i].vals)),
                     SPX_ERR_ARG, "spx_cg_batch: bad system %d", i);
+        SPX_REQUIRE(sys[i].path >= SPX_BATCH_AUTO && sys[i].path <= SPX_BATCH_WIDE, SPX_ERR_ARG,
+                    "spx_cg_batch: bad path of system %d", i);
+    }
+    const BatchLayout L = batch_layout(sys, count);
+    SPX_REQUIRE(ws && ws_bytes >= L.total, SPX_ERR_ARG, "spx_cg_batch: workspace too small");
     char *base = static_cast<char *>(ws);
-    BatchSlot *slots_dev = reinterpret_cast<BatchSlot *>(base);
-    size_t off = align256(sizeof(BatchSlot) * (size_t)count);
-    int32_t *counter = reinterpret_cast<int32_t *>(base + off);
-    off += 256;
+    BatchSlot *slots_dev = reinterpret_cast<BatchSlot *>(base + L.slots);
+    int32_t *counter = reinterpret_cast<int32_t *>(base + L.counter);
+    WideSlot *wslots_dev = reinterpret_cast<WideSlot *>(base + L.wslots);
+    WideState *wstate_dev = reinterpret_cast<WideState *>(base + L.wstate);
+    WideMap *wmap_dev = reinterpret_cast<WideMap *>(base + L.wmap);
+    int32_t *wlist_dev = reinterpret_cast<int32_t *>(base + L.wlist);
+    int32_t *vb_dev = reinterpret_cast<int32_t *>(base + L.vb);
+    size_t off = L.vectors;
     std::vector<BatchSlot> host((size_t)count);
+    std::vector<WideSlot> whost;
+    std::vector<WideState> wstate;
+    std::vector<int32_t> wlist, vb((size_t)(2 * L.total_vb)), widx((size_t)count, -1);
+    int64_t tot = 0;
+    int32_t maxit_max = 1;
     for (int32_t i = 0; i < count; ++i) {
+        const size_t vb_bytes = align256((size_t)sys[i].n * 8);
+        double *r = reinterpret_cast<double *>(base + off);
+        double *p = reinterpret_cast<double *>(base + off + vb_bytes);
+        double *q = reinterpret_cast<double *>(base + off + 2 * vb_bytes);
+        off += 3 * vb_bytes;
+        const int32_t maxit = sys[i].maxit > 0 ? sys[i].maxit : 100000;
+        maxit_max = std::max(maxit_max, maxit);
         BatchSlot &d = host[i];
         std::memset(&d, 0, sizeof(d));
-        const size_t vb = align256((size_t)sys[i].n * 8);
-        d.rowptr = sys[i].rowptr;
-        d.col = sys[i].colidx;
-        d.val = sys[i].vals;
-        d.b = sys[i].b;
-        d.x = sys[i].x;
-        d.r = reinterpret_cast<double *>(base + off);
-        d.p = reinterpret_cast<double *>(base + off + vb);
-        d.q = reinterpret_cast<double *>(base + off + 2 * vb);
-        off += 3 * vb;
-        d.n = sys[i].n;
-        d.sub = batch_sub_for(sys[i].n, sys[i].nnz);
-        d.status = kSlotRunning;
-        d.tol2 = sys[i].tol * sys[i].tol;
-        d.maxit = sys[i].maxit > 0 ? sys[i].maxit : 100000;
-        d.budget = d.maxit;
+        if (batch_is_wide(sys[i])) {
+            WideSlot w{};
+            w.rowptr = sys[i].rowptr;
+            w.col = sys[i].colidx;
+            w.val = sys[i].vals;
+            w.b = sys[i].b;
+            w.x = sys[i].x;
+            w.r = r;
+            w.p = p;
+            w.q = q;
+            w.part = reinterpret_cast<double *>(base + off);
+            off += align256((size_t)wide_nvb(sys[i].n) * 16);
+            w.n = sys[i].n;
+            w.nvb = wide_nvb(sys[i].n);
+            w.sub = batch_sub_for(sys[i].n, sys[i].nnz);
+            w.maxit = maxit;
+            w.tol2 = sys[i].tol * sys[i].tol;
+            const int32_t k = (int32_t)whost.size();
+            widx[i] = k;
+            for (int32_t v = 0; v < w.nvb; ++v) {
+                vb[tot + v] = k;
+                vb[L.total_vb + tot + v] = v;
+            }
+            tot += w.nvb;
+            whost.push_back(w);
+            WideState s0{};
+            s0.mode = kWideInit;
+            wstate.push_back(s0);
+            wlist.push_back(k);
+            d.status = kSlotEmpty;  // the one-group kernel skips it
+        } else {
+            d.rowptr = sys[i].rowptr;
+            d.col = sys[i].colidx;
+            d.val = sys[i].vals;
+            d.b = sys[i].b;
+            d.x = sys[i].x;
+            d.r = r;
+            d.p = p;
+            d.q = q;
+            d.n = sys[i].n;
+            d.sub = batch_sub_for(sys[i].n, sys[i].nnz);
+            d.status = kSlotRunning;
+            d.tol2 = sys[i].tol * sys[i].tol;
+            d.maxit = maxit;
+            d.budget = d.maxit;
+        }
         SPX_HIP(hipMemsetAsync(sys[i].x, 0, (size_t)sys[i].n * 8, stream));
     }
-    SPX_HIP(hipMemcpyAsync(slots_dev, host.data(), sizeof(BatchSlot) * (size_t)count, hipMemcpyHostToDevice, stream));
-    SPX_CHECK(batch_reset_launch(counter, stream));
-    SPX_CHECK(batch_cg_launch(slots_dev, count, counter, batch_resident_groups(), stream));
-    SPX_HIP(hipMemcpyAsync(host.data(), slots_dev, sizeof(BatchSlot) * (size_t)count, hipMemcpyDeviceToHost, stream));
+    const int64_t nnarrow = count - L.nwide;
+    if (nnarrow > 0) {
+        SPX_HIP(hipMemcpyAsync(slots_dev, host.data(), sizeof(BatchSlot) * (size_t)count, hipMemcpyHostToDevice, stream));
+        SPX_CHECK(batch_reset_launch(counter, stream));
+        SPX_CHECK(batch_cg_launch(slots_dev, count, counter, batch_resident_groups(), stream));
+        SPX_HIP(hipMemcpyAsync(host.data(), slots_dev, sizeof(BatchSlot) * (size_t)count, hipMemcpyDeviceToHost, stream));
+    }
+    if (L.nwide > 0) {
+        const WideMap m{(int32_t)L.total_vb, (int32_t)L.nwide};
+        SPX_HIP(hipMemcpyAsync(wslots_dev, whost.data(), sizeof(WideSlot) * whost.size(), hipMemcpyHostToDevice, stream));
+        SPX_HIP(hipMemcpyAsync(wstate_dev, wstate.data(), sizeof(WideState) * wstate.size(), hipMemcpyHostToDevice, stream));
+        SPX_HIP(hipMemcpyAsync(wmap_dev, &m, sizeof(m), hipMemcpyHostToDevice, stream));
+        SPX_HIP(hipMemcpyAsync(wlist_dev, wlist.data(), sizeof(int32_t) * wlist.size(), hipMemcpyHostToDevice, stream));
+        SPX_HIP(hipMemcpyAsync(vb_dev, vb.data(), sizeof(int32_t) * vb.size(), hipMemcpyHostToDevice, stream));
+        const int grid = (int)std::min<int64_t>(L.total_vb, 4096);
+        // every iteration either counts a CG step or is a true-residual check
+        // followed by one, so 2 * maxit + 4 iterations finish every system
+        const int64_t limit = 2 * (int64_t)maxit_max + 4;
+        for (int64_t done = 0; done < limit;) {
+            for (int k = 0; k < 16; ++k, ++done)
+                SPX_CHECK(wide_iteration_launch(wslots_dev, wstate_dev, wmap_dev, wlist_dev, vb_dev,
+                                                vb_dev + L.total_vb, grid, kWideCommitGrid, stream));
+            SPX_HIP(hipMemcpyAsync(wstate.data(), wstate_dev, sizeof(WideState) * wstate.size(), hipMemcpyDeviceToHost,
+                                   stream));
+            SPX_HIP(hipStreamSynchronize(stream));
+            bool all = true;
+            for (auto &w : wstate) all &= (w.mode == kWideDone);
+            if (all) break;
+        }
+    }
     SPX_HIP(hipStreamSynchronize(stream));
     spx_status first = SPX_OK;
     for (int32_t i = 0; i < count; ++i) {
-        const BatchSlot &d = host[i];
-        sys[i].status = d.status == kSlotConverged ? SPX_OK : slot_status_to_spx(d.status);
-        sys[i].iters = d.iters;
-        sys[i].spmv_count = d.spmv;
-        sys[i].relres_true = d.relres_true;
+        if (widx[i] >= 0) {
+            const WideState &w = wstate[(size_t)widx[i]];
+            sys[i].status = w.mode != kWideDone ? SPX_ERR_NOT_CONVERGED
+                                                : (w.status == kSlotConverged ? SPX_OK : slot_status_to_spx(w.status));
+            sys[i].iters = w.iters;
+            sys[i].spmv_count = w.spmv;
+            sys[i].relres_true = w.relres_true;
+        } else {
+            const BatchSlot &d = host[i];
+            sys[i].status = d.status == kSlotConverged ? SPX_OK : slot_status_to_spx(d.status);
+            sys[i].iters = d.iters;
+            sys[i].spmv_count = d.spmv;
+            sys[i].relres_true = d.relres_true;
+        }
         if (first == SPX_OK && sys[i].status != SPX_OK) first = (spx_status)sys[i].status;
     }
     if (first != SPX_OK) set_error("spx_cg_batch: at least one system did not converge");

@@ -101,7 +101,7 @@ for _nm in ("spx_cg_solve", "spx_bicgstab_solve", "spx_gmres_solve"):
 _sig("spx_ir_workspace", [_MP, _MP, ctypes.POINTER(ctypes.c_size_t)])
 _sig("spx_ir_solve", [_MP, _MP, _vp, _vp, ctypes.POINTER(IrOpts), _vp, ctypes.c_size_t, _SIP, _vp])
 class BatchSystem(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("nnz", ctypes.c_int64),
+    _fields_ = [("n", ctypes.c_int32), ("path", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
@@ -110,7 +110,8 @@ class BatchSystem(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("iters_per_tick", ctypes.c_int32), ("tick_us", ctypes.c_int32)]
+                ("iters_per_tick", ctypes.c_int32), ("tick_us", ctypes.c_int32), ("wide_min_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -396,16 +397,20 @@ def ir_solve(A64: Matrix, Alow: Matrix, b: torch.Tensor, tol: float = 1e-10, inn
 
 
 # ------------------------------------------------------------------ batched CG and serving
-def cg_batch(mats, bs, tol=1e-8, maxit=100000, stream=None):
-    """Solve independent CSR systems (device Matrix objects, float64) with one
-    persistent launch, one work-group per system. Returns (xs, infos)."""
+BATCH_AUTO, BATCH_ONE_GROUP, BATCH_WIDE = 0, 1, 2
+
+
+def cg_batch(mats, bs, tol=1e-8, maxit=100000, path=BATCH_AUTO, stream=None):
+    """Solve independent CSR systems (device Matrix objects, float64) together:
+    one work-group per small system, the wide path for large ones (`path`
+    forces one). Returns (xs, infos)."""
     count = len(mats)
     arr = (BatchSystem * count)()
     xs = []
     for i, (A, b) in enumerate(zip(mats, bs)):
         x = torch.empty_like(b)
         xs.append(x)
-        arr[i] = BatchSystem(A.nrows, 0, A.nnz, _ptr(A.rowptr), _ptr(A.colidx), _ptr(A.vals), _ptr(b), _ptr(x),
+        arr[i] = BatchSystem(A.nrows, path, A.nnz, _ptr(A.rowptr), _ptr(A.colidx), _ptr(A.vals), _ptr(b), _ptr(x),
                              tol, maxit, 0, 0, 0, 0.0)
     nbytes = ctypes.c_size_t(0)
     check(_lib.spx_cg_batch_workspace(arr, count, ctypes.byref(nbytes)), "spx_cg_batch_workspace")
@@ -422,8 +427,8 @@ class Server:
     """Continuous-batching CG server (host requests, results copied back)."""
 
     def __init__(self, device: int = 0, max_slots: int = 1024, hbm_budget_bytes: int = 32 << 30,
-                 iters_per_tick: int = 0, tick_us: int = 0):
-        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us)
+                 iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0):
+        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us, wide_min_rows, 0)
         h = ctypes.c_void_p()
         check(_lib.spx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "spx_server_create")
         self._h = h

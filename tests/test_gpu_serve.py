@@ -167,3 +167,93 @@ def test_server_poll_and_slot_reuse():
             assert _relres(A, b, x) <= 1e-8
     finally:
         srv.close()
+
+
+# ---------------------------------------------------------------- wide systems
+WIDE_MIX = [("poisson", 160, 21), ("spd", 50000, 22), ("poisson", 40, 23), ("spd", 17000, 24), ("poisson", 129, 25)]
+
+
+def test_cg_batch_wide_converges_like_oracle():
+    for kind, size, seed in [("poisson", 160, 1), ("spd", 60000, 2)]:
+        A, b = _system(kind, size, seed)
+        assert A.n >= 16384
+        x, info = _alone(A, b, 1e-10)
+        assert info["status"] == spx.OK, info
+        assert _relres(A, b, x) <= 1e-10
+        _, io = O.cg(A, b, tol=1e-10)
+        assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
+
+
+def test_cg_batch_wide_and_one_group_agree():
+    A, b = _system("poisson", 130, 3)
+    Ad = spx.csr_from_host(A)
+    xw, iw = spx.cg_batch([Ad], [dev(b)], tol=1e-9, path=spx.BATCH_WIDE)
+    xn, inn = spx.cg_batch([Ad], [dev(b)], tol=1e-9, path=spx.BATCH_ONE_GROUP)
+    assert iw[0]["status"] == inn[0]["status"] == spx.OK
+    for x in (host(xw[0]), host(xn[0])):
+        assert _relres(A, b, x) <= 1e-9
+    assert abs(iw[0]["iters"] - inn[0]["iters"]) <= 5
+
+
+def test_cg_batch_wide_mix_alone_bitwise():
+    systems = [_system(*m) for m in WIDE_MIX]
+    mats = [spx.csr_from_host(A) for A, _ in systems]
+    xs, infos = spx.cg_batch(mats, [dev(b) for _, b in systems], tol=1e-8)
+    for (A, b), x, info in zip(systems, xs, infos):
+        assert info["status"] == spx.OK, info
+        x = host(x)
+        assert _relres(A, b, x) <= 1e-8
+        xa, ia = _alone(A, b, 1e-8)
+        assert ia["iters"] == info["iters"]
+        np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+
+
+def test_cg_batch_wide_status_codes():
+    n = 20000
+    # indefinite diagonal: p.q <= 0 at some step
+    d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    mk = lambda vals: spx.csr_from_host(S.CSR(n, rowptr, col, vals.astype(np.float64)))
+    b = np.ones(n)
+    _, inf = spx.cg_batch([mk(d)], [dev(b)], tol=1e-10, path=spx.BATCH_WIDE)
+    assert inf[0]["status"] == spx.ERR_BREAKDOWN
+    bn = b.copy()
+    bn[7] = np.nan
+    _, inf = spx.cg_batch([mk(np.ones(n))], [dev(bn)], tol=1e-10, path=spx.BATCH_WIDE)
+    assert inf[0]["status"] == spx.ERR_NONFINITE
+    xs, inf = spx.cg_batch([mk(np.ones(n))], [dev(np.zeros(n))], tol=1e-10, path=spx.BATCH_WIDE)
+    assert inf[0]["status"] == spx.OK and inf[0]["iters"] == 0
+    assert not host(xs[0]).any()
+    A, bb = _system("poisson", 150, 4)
+    _, inf = spx.cg_batch([spx.csr_from_host(A)], [dev(bb)], tol=1e-12, maxit=3, path=spx.BATCH_WIDE)
+    assert inf[0]["status"] == spx.ERR_NOT_CONVERGED and inf[0]["iters"] == 3
+
+
+def test_server_wide_and_narrow_mix_bitwise():
+    srv = spx.Server(max_slots=6, hbm_budget_bytes=512 << 20, tick_us=500)
+    try:
+        systems = [_system(*m) for m in WIDE_MIX + MIX[:4]]
+        tickets = [srv.submit(A, b, tol=1e-8) for A, b in systems]
+        for t, (A, b) in zip(tickets, systems):
+            x, info = srv.wait(t, timeout_s=120)
+            assert info["status"] == spx.OK, info
+            assert _relres(A, b, x) <= 1e-8
+            xa, ia = _alone(A, b, 1e-8)
+            assert ia["iters"] == info["iters"]
+            np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+    finally:
+        srv.close()
+
+
+def test_server_all_one_group_when_wide_disabled():
+    A, b = _system("poisson", 130, 5)
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20, wide_min_rows=-1)
+    try:
+        x, info = srv.wait(srv.submit(A, b, tol=1e-8), timeout_s=120)
+        assert info["status"] == spx.OK
+        Ad = spx.csr_from_host(A)
+        xs, _ = spx.cg_batch([Ad], [dev(b)], tol=1e-8, path=spx.BATCH_ONE_GROUP)
+        np.testing.assert_array_equal(host(xs[0]).view(np.uint64), x.view(np.uint64))
+    finally:
+        srv.close()
