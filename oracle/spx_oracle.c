@@ -814,8 +814,9 @@ out:
 /* scale s = ||r||_inf, rhs = fl32(r / s); inner unpreconditioned CG in      */
 /* float32 (vectors and accumulation) on the low-precision matrix, whose     */
 /* values are given as float32 (binary16-stored values are passed widened,   */
-/* which is exact), from zero to relative residual inner_tol; x += s * d.    */
-/* The inner CG stops on its recursive residual.                             */
+/* which is exact), from zero to relative residual                          */
+/* max(inner_tol, tol ||b|| / (2 ||r||)); x += s * d. The inner CG stops on  */
+/* its recursive residual.                                                   */
 /* ------------------------------------------------------------------------ */
 static int32_t cg_f32(int32_t n, const int32_t *rowptr, const int32_t *col, const float *val,
                       const float *b, float *x, float tol, int32_t maxit,
@@ -875,7 +876,11 @@ int orc_ir(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
         double s = 0.0;
         for (int32_t i = 0; i < n; ++i) if (fabs(r[i]) > s) s = fabs(r[i]);
         for (int32_t i = 0; i < n; ++i) rl[i] = (float)(r[i] / s);
-        int32_t it = cg_f32(n, rowptr, col, val_low, rl, d, (float)inner_tol, inner_maxit, w1, w2, w3);
+        /* the inner solve only has to close the remaining gap to tol * ||b||
+         * (with a factor 2 of margin), never less than inner_tol */
+        double itol = 0.5 * tol * bn / rn;
+        if (itol < inner_tol) itol = inner_tol;
+        int32_t it = cg_f32(n, rowptr, col, val_low, rl, d, (float)itol, inner_maxit, w1, w2, w3);
         info->outer_iters += 1;
         if (it < 0) { info->iters += -it; info->spmv_count += -it; info->status = ORC_BREAKDOWN; break; }
         info->iters += it;
