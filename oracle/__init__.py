@@ -90,6 +90,13 @@ def _declare(L):
     L.orc_csr_to_hyb.argtypes = [_i32, _i32p, _i32p, _f64p, _i32, _i64, _i32p, _f64p, _i32p, _i32p, _f64p]
     L.orc_hyb_to_csr.argtypes = [_i32, _i32, _i64, _i32p, _f64p, _i64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
     L.orc_hyb_auto_width.argtypes = [_i32, _i32p, _i32, _i32]
+    L.orc_sellp_shape.argtypes = [_i32, _i32p, _i32, _i32, _i32p]
+    L.orc_csr_to_sellp.argtypes = [_i32, _i32p, _i32p, _f64p, _i32, _i32p, _i32p, _f64p]
+    L.orc_sellp_spmv.argtypes = [_i32, _i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64]
+    L.orc_sellp_spmv.restype = None
+    L.orc_sellp_count.argtypes = [_i32, _i32, _i32p, _i32p]
+    L.orc_sellp_count.restype = _i64
+    L.orc_sellp_to_csr.argtypes = [_i32, _i32, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
     L.orc_cast_values.argtypes = [_i64, _f64p, _i32, ctypes.c_void_p]
     L.orc_cast_values.restype = _i64
     L.orc_f16_to_f64.argtypes = [ctypes.c_uint16]
@@ -220,6 +227,51 @@ def ell_to_csr(E):
     if st != 0:
         raise ValueError(f"ell_to_csr failed: {st}")
     return CSR(E.n, rp, col, val)
+
+
+@dataclass
+class Sellp:
+    n: int
+    C: int  # slice size (rows per slice)
+    T: int  # stride factor (slice widths are multiples of it)
+    slice_sets: np.ndarray  # int32 [nslices + 1], prefix sums of slice widths
+    col: np.ndarray  # int32 [slice_sets[-1] * C]
+    val: np.ndarray  # float64
+
+
+def csr_to_sellp(A, C=64, T=1):
+    nslices = (A.n + C - 1) // C
+    sets = np.empty(nslices + 1, np.int32)
+    rp, c, v = _csr(A)
+    st = lib().orc_sellp_shape(A.n, rp, C, T, sets)
+    if st != 0:
+        raise ValueError(f"sellp_shape failed: {st}")
+    total = int(sets[-1]) * C
+    scol = np.empty(total, np.int32)
+    sval = np.empty(total, np.float64)
+    st = lib().orc_csr_to_sellp(A.n, rp, c, v, C, sets, scol, sval)
+    if st != 0:
+        raise ValueError(f"csr_to_sellp failed: {st}")
+    return Sellp(A.n, C, T, sets, scol, sval)
+
+
+def sellp_spmv(P, x, y=None, alpha=1.0, beta=0.0):
+    out = np.zeros(P.n) if y is None else _c(y, np.float64).copy()
+    lib().orc_sellp_spmv(P.n, P.C, _c(P.slice_sets, np.int32), _c(P.col, np.int32), _c(P.val, np.float64),
+                         _c(x, np.float64), out, alpha, beta)
+    return out
+
+
+def sellp_to_csr(P):
+    sets, scol = _c(P.slice_sets, np.int32), _c(P.col, np.int32)
+    cnt = lib().orc_sellp_count(P.n, P.C, sets, scol)
+    if cnt < 0:
+        raise ValueError(f"sellp_count failed: {cnt}")
+    rp = np.empty(P.n + 1, np.int32)
+    col = np.empty(cnt, np.int32)
+    val = np.empty(cnt, np.float64)
+    lib().orc_sellp_to_csr(P.n, P.C, sets, scol, _c(P.val, np.float64), rp, col, val)
+    return CSR(P.n, rp, col, val)
 
 
 def hyb_auto_width(A, sv=8, si=4):

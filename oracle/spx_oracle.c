@@ -376,6 +376,117 @@ int32_t orc_hyb_auto_width(int32_t n, const int32_t *rowptr, int32_t sv, int32_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* SELL-P, the sliced ELL format with padding that the paper benchmarks as   */
+/* Sellp (Section 4); layout as in Anzt, Tomov and Dongarra (2014): rows are */
+/* grouped in slices of C consecutive rows; slice s stores its rows'         */
+/* entries column-major within the slice, with width                         */
+/*   w_s = T * ceil(max row length in the slice / T)                        */
+/* (T is the stride factor); slice_sets[s] is the sum of the widths of the   */
+/* slices before s, so entry k of row r = s*C + l sits at                    */
+/*   (slice_sets[s] + k) * C + l.                                            */
+/* Padding slots (and the lanes of a last, partial slice) hold column -1 and */
+/* value +0. A row's entries occupy its first slots, ascending by column.    */
+/* ------------------------------------------------------------------------ */
+
+/* slice_sets[0..nslices]; returns ORC_ERANGE if the total width overflows
+ * int32, ORC_EARG for C < 1 or T < 1. */
+int orc_sellp_shape(int32_t n, const int32_t *rowptr, int32_t C, int32_t T, int32_t *slice_sets)
+{
+    if (C < 1 || T < 1) return ORC_EARG;
+    int32_t nslices = (n + C - 1) / C;
+    int64_t acc = 0;
+    slice_sets[0] = 0;
+    for (int32_t s = 0; s < nslices; ++s) {
+        int32_t m = 0;
+        for (int32_t r = s * C; r < n && r < (s + 1) * C; ++r) {
+            int32_t len = rowptr[r + 1] - rowptr[r];
+            if (len > m) m = len;
+        }
+        int32_t w = ((m + T - 1) / T) * T;
+        acc += w;
+        if (acc > INT32_MAX) return ORC_ERANGE;
+        slice_sets[s + 1] = (int32_t)acc;
+    }
+    return ORC_OK;
+}
+
+int orc_csr_to_sellp(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t C,
+                     const int32_t *slice_sets, int32_t *scol, double *sval)
+{
+    if (C < 1) return ORC_EARG;
+    int32_t nslices = (n + C - 1) / C;
+    for (int32_t s = 0; s < nslices; ++s) {
+        int32_t w = slice_sets[s + 1] - slice_sets[s];
+        for (int32_t l = 0; l < C; ++l) {
+            int32_t r = s * C + l;
+            int32_t len = (r < n) ? rowptr[r + 1] - rowptr[r] : 0;
+            if (len > w) return ORC_EFORMAT;
+            for (int32_t k = 0; k < w; ++k) {
+                int64_t q = ((int64_t)slice_sets[s] + k) * C + l;
+                if (k < len) {
+                    scol[q] = col[rowptr[r] + k];
+                    memcpy(&sval[q], &val[rowptr[r] + k], 8);
+                } else {
+                    scol[q] = -1;
+                    sval[q] = 0.0;
+                }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* y = alpha * A x + beta * y; each row summed in slot order. */
+void orc_sellp_spmv(int32_t n, int32_t C, const int32_t *slice_sets, const int32_t *scol, const double *sval,
+                    const double *x, double *y, double alpha, double beta)
+{
+    for (int32_t r = 0; r < n; ++r) {
+        int32_t s = r / C, l = r % C;
+        double acc = 0.0;
+        for (int32_t k = 0; k < slice_sets[s + 1] - slice_sets[s]; ++k) {
+            int64_t q = ((int64_t)slice_sets[s] + k) * C + l;
+            if (scol[q] >= 0) acc += sval[q] * x[scol[q]];
+        }
+        y[r] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[r];
+    }
+}
+
+/* Stored entries of each row (slots up to the first padding slot). Returns
+ * ORC_EFORMAT if a stored entry follows padding in some row. */
+int64_t orc_sellp_count(int32_t n, int32_t C, const int32_t *slice_sets, const int32_t *scol)
+{
+    int64_t total = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        int32_t s = r / C, l = r % C, w = slice_sets[s + 1] - slice_sets[s];
+        int32_t k = 0;
+        while (k < w && scol[((int64_t)slice_sets[s] + k) * C + l] >= 0) ++k;
+        for (int32_t j = k; j < w; ++j)
+            if (scol[((int64_t)slice_sets[s] + j) * C + l] >= 0) return ORC_EFORMAT;
+        total += k;
+    }
+    return total;
+}
+
+int orc_sellp_to_csr(int32_t n, int32_t C, const int32_t *slice_sets, const int32_t *scol, const double *sval,
+                     int32_t *rowptr, int32_t *col, double *val)
+{
+    rowptr[0] = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        int32_t s = r / C, l = r % C, w = slice_sets[s + 1] - slice_sets[s];
+        int32_t c = rowptr[r];
+        for (int32_t k = 0; k < w; ++k) {
+            int64_t q = ((int64_t)slice_sets[s] + k) * C + l;
+            if (scol[q] < 0) break;
+            col[c] = scol[q];
+            memcpy(&val[c], &sval[q], 8);
+            ++c;
+        }
+        rowptr[r + 1] = c;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Value casts, round to nearest even (IEEE 754).                           */
 /* NaN maps to the canonical quiet NaN of the target with the sign kept.     */
 /* ------------------------------------------------------------------------ */
