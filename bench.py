@@ -40,6 +40,10 @@ def ell_bytes(n, K, sv, sx):
     return n * K * (sv + 4) + 2 * n * sx
 
 
+def sellp_bytes(n, slice_cols, C, sv, sx):
+    return slice_cols * C * (sv + 4) + (-(-n // C) + 1) * 4 + 2 * n * sx
+
+
 def hyb_bytes(n, K, coo_nnz, sv, sx):
     return n * K * (sv + 4) + coo_nnz * (sv + 8) + 2 * n * sx
 
@@ -64,6 +68,109 @@ def cg_iter_bytes(n, nnz, sv, precond):
     """Algorithmic bytes of one CG iteration: the CSR product plus 9 (no
     preconditioner) or 11 (Jacobi) vector passes of n values."""
     return csr_bytes(n, nnz, sv, sv) + (11 if precond else 9) * n * sv
+
+
+def format_sweep(spx, torch, dev, A, x_h, args, tag):
+    """Time y = A x in CSR, COO, ELL and HYB (automatic width), float64 and
+    float32 values, plus CSR with binary16 values and CSR without the
+    precomputed partition. Each format is built on the device from the CSR
+    upload by spx_convert. GB/s counts the format's own algorithmic bytes
+    (ELL padding included); csr_equiv_GBs counts the CSR bytes of the same
+    product, for comparison across formats."""
+    n, nnz = A.n, A.nnz
+    out = {}
+    K = int(A.row_lengths().max())
+    free = torch.cuda.mem_get_info()[0]
+    for vt, sv, vname in ((spx.F64, 8, "f64"), (spx.F32, 4, "f32"), (spx.F16, 2, "f16")):
+        base = spx.csr_from_host(A, vt, dev)
+        sx = 8 if vt == spx.F64 else 4
+        hyb = spx.convert(base, spx.HYB)
+        hK, hC = hyb.ell_width, hyb.coo_nnz
+        del hyb
+        sp = spx.convert(base, spx.SELLP)
+        scols = sp.slice_cols
+        del sp
+        variants = {"csr": (lambda: spx.csr_analyse(spx.csr_from_host(A, vt, dev)), csr_bytes(n, nnz, sv, sx))}
+        if vt != spx.F16:
+            variants.update({
+                "coo": (lambda: spx.convert(base, spx.COO), coo_bytes(n, nnz, sv, sx)),
+                "ell": (lambda: spx.convert(base, spx.ELL), ell_bytes(n, K, sv, sx)),
+                "hyb": (lambda: spx.convert(base, spx.HYB), hyb_bytes(n, hK, hC, sv, sx)),
+                "sellp": (lambda: spx.convert(base, spx.SELLP), sellp_bytes(n, scols, 64, sv, sx)),
+            })
+        if vt == spx.F64:
+            variants["csr_nopart"] = (lambda: spx.csr_from_host(A, vt, dev), csr_bytes(n, nnz, sv, sx))
+        for fmt, (make, vb) in variants.items():
+            name = f"{tag}_{fmt}_{vname}"
+            if vb > 0.8 * free:
+                out[name] = {"skipped": f"needs {vb / 1e9:.1f} GB"}
+                continue
+            Rv = max(1, int(np.ceil((1 << 30) / vb)))
+            Ms = [make() for _ in range(Rv)]
+            vdt = Ms[0].vec_dtype
+            Xs = [torch.from_numpy(x_h).to(dev).to(vdt) for _ in range(Rv)]
+            Ys = [torch.empty(n, dtype=vdt, device=dev) for _ in range(Rv)]
+            steps = args.steps if vb < (4 << 30) else max(3, args.steps // 20)
+            vms = time_launches(lambda i: spx.spmv(Ms[i % Rv], Xs[i % Rv], Ys[i % Rv]), steps,
+                                max(1, args.warmup // 4), torch)
+            out[name] = {"ms": vms, "GBs": vb / vms / 1e6, "bytes": vb,
+                         "csr_equiv_GBs": csr_bytes(n, nnz, sv, sx) / vms / 1e6}
+            if fmt == "hyb":
+                out[name].update(ell_width=hK, coo_nnz=hC)
+            del Ms, Xs, Ys
+            torch.cuda.empty_cache()
+        del base
+        torch.cuda.empty_cache()
+    return out
+
+
+def conversion_sweep(spx, torch, dev, A, tag, steps=20):
+    """Device format conversion, float64 values: CSR -> COO / ELL / HYB and
+    back, timed with HIP events around spx_convert alone (outputs and
+    workspace allocated by one untimed plan + conversion). GB/s counts one
+    read of the source arrays and one write of the destination arrays. The
+    float64 -> float32 value cast is timed around the (blocking) call."""
+    import ctypes
+
+    n, nnz = A.n, A.nnz
+    base = spx.csr_from_host(A, spx.F64, dev)
+    csr_b = (n + 1) * 4 + nnz * 12
+    out = {}
+
+    def fmt_bytes(M):
+        if M.fmt == spx.COO:
+            return nnz * 16
+        if M.fmt == spx.SELLP:
+            return M.slice_cols * M.slice_size * 12 + (-(-n // M.slice_size) + 1) * 4
+        if M.fmt == spx.ELL:
+            return M.ell_width * M.ell_ld * 12
+        return M.ell_width * M.ell_ld * 12 + M.coo_nnz * 16
+
+    def time_convert(src, dst):
+        ws = getattr(dst, "_ws")
+        d_src, d_dst = src.desc(), dst.desc()
+        fn = lambda i: spx.check(spx._lib.spx_convert(ctypes.byref(d_src), ctypes.byref(d_dst), spx._ptr(ws),
+                                                      ws.numel(), spx._stream()), "spx_convert")
+        return time_launches(fn, steps, 2, torch)
+
+    for fname, fmt in (("coo", spx.COO), ("ell", spx.ELL), ("hyb", spx.HYB), ("sellp", spx.SELLP)):
+        M = spx.convert(base, fmt)
+        ms = time_convert(base, M)
+        fb = fmt_bytes(M)
+        out[f"{tag}_csr_to_{fname}"] = {"ms": round(ms, 4), "GBs": round((csr_b + fb) / ms / 1e6, 1)}
+        back = spx.convert(M, spx.CSR)
+        ms = time_convert(M, back)
+        out[f"{tag}_{fname}_to_csr"] = {"ms": round(ms, 4), "GBs": round((csr_b + fb) / ms / 1e6, 1)}
+        del M, back
+        torch.cuda.empty_cache()
+    spx.cast_values(base, spx.F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        spx.cast_values(base, spx.F32)
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    out[f"{tag}_cast_f64_to_f32"] = {"ms": round(ms, 4), "GBs": round(nnz * 12 / ms / 1e6, 1)}
+    return out
 
 
 def profile_traffic(name, algo_bytes):
@@ -109,6 +216,20 @@ def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
     A = S.poisson2d(64)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
     bd = rhs(spx, S, torch, Ad)
+    # one product, 1,000 launches each bracketed by its own events
+    xv = torch.from_numpy(S.uniform_vector(A.n, seed=0)).to(dev)
+    yv = torch.empty_like(xv)
+    for _ in range(20):
+        spx.spmv(Ad, xv, yv)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(1000)]
+    for e0, e1 in ev:
+        e0.record()
+        spx.spmv(Ad, xv, yv)
+        e1.record()
+    torch.cuda.synchronize()
+    sl = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+    spmv_lat = {"p50_us": round(float(np.percentile(sl, 50)), 2), "p99_us": round(float(np.percentile(sl, 99)), 2),
+                "launches": len(ev)}
     for _ in range(3):
         spx.cg_solve(Ad, bd, tol=1e-10)
     torch.cuda.synchronize()
@@ -122,7 +243,7 @@ def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
         assert info["status"] == 0 and info["relres_true"] <= 1e-10, info
     tot = time.perf_counter() - t0
     lat = np.array(lat) * 1e3
-    out = {"single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+    out = {"spmv": spmv_lat, "single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
                       "relres_true": info["relres_true"]}}
     if nbatch > 0:
@@ -177,14 +298,24 @@ def bench_solvers(spx, S, torch, dev):
     t64 = info["device_ms"]
     out["cg_fp64_poisson192"] = {"ms": round(t64, 2), "iters": info["iters"], "relres_true": info["relres_true"]}
     x64 = x.clone()
+    xstar = torch.from_numpy(S.uniform_vector(A.n, seed=0, purpose="xstar")).to(dev)
+    nrm = torch.linalg.vector_norm
+    out["cg_fp64_poisson192"]["rel_err_vs_xstar"] = float(nrm(x64 - xstar) / nrm(xstar))
     for nm, low in (("ir_fp32_poisson192", spx.F32), ("ir_fp16v_poisson192", spx.F16)):
         Alow = spx.cast_values(A64, low)
-        spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
-        x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
-        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
-        out[nm] = {"ms": round(info["device_ms"], 2), "inner_iters": info["iters"], "outer": info["outer_iters"],
-                   "speedup_vs_fp64": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
-                   "rel_err_vs_fp64_cg": err}
+        sweep = {}
+        for itol in (1e-3, 1e-4, 1e-5, 1e-6):
+            spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=itol)
+            x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=itol)
+            sweep[f"{itol:.0e}"] = {
+                "ms": round(info["device_ms"], 2), "inner_iters": info["iters"], "outer": info["outer_iters"],
+                "speedup_vs_fp64": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
+                "status": info["status"], "rel_err_vs_fp64_cg": float(nrm(x - x64) / nrm(x64)),
+                "rel_err_vs_xstar": float(nrm(x - xstar) / nrm(xstar))}
+        ok = {k: v for k, v in sweep.items() if v["status"] == 0}
+        best = min(ok, key=lambda k: ok[k]["ms"]) if ok else None
+        out[nm] = dict(ok[best], inner_tol=best) if best else {"status": "failed"}
+        out[nm]["inner_tol_sweep"] = sweep
     return out
 
 
@@ -280,7 +411,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=int, default=100, help="27-point grid edge (100 -> n = 1e6)")
-    ap.add_argument("--sweep", action="store_true", help="also time COO/ELL/HYB and float32")
+    ap.add_argument("--sweep", action="store_true", help="also time COO/ELL/HYB and float32/binary16 (27-point)")
+    ap.add_argument("--zipf", action="store_true", help="also time every format on the Zipf(1.5) n=1e6 matrix")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solvers", action="store_true", help="also time the full-size Krylov solvers")
     ap.add_argument("--cg-solves", type=int, default=50, help="solves of the 64x64 CG latency run (0 = skip)")
@@ -330,32 +462,18 @@ def main():
     copy_gbs = 2 * cn * 8 / cms / 1e6
     del src, dst
 
+    conversions = None
     if args.sweep:
-        base = spx.csr_from_host(A, spx.F64, dev)
-        Kh = spx.convert(base, spx.HYB)
-        hybK, hybC = Kh.ell_width, Kh.coo_nnz
-        del Kh
-        variants = {
-            "coo_f64": (lambda: spx.convert(base, spx.COO), coo_bytes(n, nnz, 8, 8)),
-            "ell_f64": (lambda: spx.convert(base, spx.ELL), ell_bytes(n, int(A.row_lengths().max()), 8, 8)),
-            "hyb_f64": (lambda: spx.convert(base, spx.HYB), hyb_bytes(n, hybK, hybC, 8, 8)),
-            "csr_f32": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F32, dev)), csr_bytes(n, nnz, 4, 4)),
-            "csr_f16": (lambda: spx.csr_analyse(spx.csr_from_host(A, spx.F16, dev)), csr_bytes(n, nnz, 2, 4)),
-            "csr_f64_nopart": (lambda: spx.csr_from_host(A, spx.F64, dev), csr_bytes(n, nnz, 8, 8)),
-        }
         del mats
         torch.cuda.empty_cache()
-        for name, (make, vb) in variants.items():
-            Rv = max(2, int(np.ceil((1 << 30) / vb)))
-            Ms = [make() for _ in range(Rv)]
-            vdt = Ms[0].vec_dtype
-            Xs = [torch.from_numpy(x_h).to(dev).to(vdt) for _ in range(Rv)]
-            Ys = [torch.empty(n, dtype=vdt, device=dev) for _ in range(Rv)]
-            vms = time_launches(lambda i: spx.spmv(Ms[i % Rv], Xs[i % Rv], Ys[i % Rv]), args.steps, args.warmup,
-                                torch)
-            results[name] = {"ms": vms, "GBs": vb / vms / 1e6, "bytes": vb}
-            del Ms, Xs, Ys
-            torch.cuda.empty_cache()
+        results.update(format_sweep(spx, torch, dev, A, x_h, args, "27pt"))
+        conversions = conversion_sweep(spx, torch, dev, A, "27pt")
+    if args.zipf:
+        del A
+        Z = S.zipf_matrix(1_000_000, seed=0)
+        zx = S.uniform_vector(Z.n, seed=0)
+        results.update(format_sweep(spx, torch, dev, Z, zx, args, "zipf"))
+        del Z
 
     cg_small = bench_cg_small(spx, S, torch, dev, args.cg_solves, args.cg_batch) if args.cg_solves > 0 else None
     solvers = bench_solvers(spx, S, torch, dev) if args.solvers else None
@@ -399,7 +517,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(r["GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "csr_spmv_kernel<double,double,0,512,4096>", "bytes_per_launch": b},
-        "sweep": {k: {"GBs": round(v["GBs"], 2), "ms": round(v["ms"], 5)} for k, v in results.items()},
+        "sweep": {k: ({kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()})
+                  for k, v in results.items()},
+        "conversions": conversions,
         "cg_poisson64": cg_small,
         "solvers": solvers,
         "serve": serve,

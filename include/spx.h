@@ -58,7 +58,7 @@ typedef enum {
     SPX_F16 = 2  /* binary16 stored values, float32 vectors and accumulation       */
 } spx_dtype;
 
-typedef enum { SPX_CSR = 0, SPX_COO = 1, SPX_ELL = 2, SPX_HYB = 3 } spx_format;
+typedef enum { SPX_CSR = 0, SPX_COO = 1, SPX_ELL = 2, SPX_HYB = 3, SPX_SELLP = 4 } spx_format;
 
 /* Sparse matrix descriptor. Fields a format does not use are ignored.
  *  CSR: rowptr[nrows+1], colidx[nnz], vals[nnz]; rows ascending, columns
@@ -68,6 +68,13 @@ typedef enum { SPX_CSR = 0, SPX_COO = 1, SPX_ELL = 2, SPX_HYB = 3 } spx_format;
  *       slots hold column -1 and value +0 and come after a row's entries.
  *  HYB: an ELL part (ell_*) plus a COO part (rowidx/colidx/vals, coo_nnz
  *       entries, sorted); nnz = stored ELL entries + coo_nnz.
+ *  SELLP: sliced ELL with padding, the Sellp format the paper benchmarks
+ *       (Section 4): rows in slices of slice_size rows (a power of two, at
+ *       most 256); slice s has width w_s = stride_factor * ceil(longest row
+ *       of the slice / stride_factor); slice_sets[nslices+1] holds the
+ *       prefix sums of the widths (slice_cols = slice_sets[nslices]); entry
+ *       k of row r = s*slice_size + l is at (slice_sets[s] + k)*slice_size + l
+ *       of ell_col / ell_val ([slice_cols*slice_size] each); padding as ELL.
  * max_row_len is an optional hint (0 = unknown) used to choose kernels.     */
 typedef struct spx_matrix {
     int32_t fmt;       /* spx_format */
@@ -86,6 +93,10 @@ typedef struct spx_matrix {
     int32_t *ell_col;
     void *ell_val;
     const int32_t *csr_part; /* optional CSR partition from spx_csr_analyse (NULL = none) */
+    int32_t slice_size;      /* SELLP */
+    int32_t stride_factor;   /* SELLP */
+    int32_t *slice_sets;     /* SELLP, [ceil(nrows/slice_size) + 1] */
+    int64_t slice_cols;      /* SELLP, slice_sets[nslices] */
 } spx_matrix;
 
 /* Name of a status code (static string). */
@@ -133,14 +144,18 @@ int64_t spx_csr_analysis_bytes(const spx_matrix *A);
 spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ format conversion
- * Conversions between the formats of Section 1 (Csr <-> Coo, Csr -> Ell,
- * Csr -> Hybrid, Ell -> Csr, Hybrid -> Csr; other pairs go through Csr).
+ * Conversions between the formats of Section 1 and Sellp (Csr <-> Coo,
+ * Csr -> Ell, Csr -> Hybrid, Csr -> Sellp, Ell -> Csr, Hybrid -> Csr,
+ * Sellp -> Csr; other pairs go through Csr).
  * Index arrays are produced exactly and values are copied bit for bit, so
  * a round trip X -> Csr -> X reproduces the input.
  *
  * spx_convert_plan (BLOCKING: synchronizes `stream`) fills the shape fields
- * of *dst (fmt, val_type, nrows, ncols, nnz, coo_nnz, ell_width, ell_ld;
- * pointers are set to NULL) and the workspace size. ell_width: -1 chooses it
+ * of *dst (fmt, val_type, nrows, ncols, nnz, coo_nnz, ell_width, ell_ld,
+ * slice_cols; pointers are set to NULL) and the workspace size. For SELLP,
+ * dst->slice_size and dst->stride_factor are read as inputs (0 = 64 and 1)
+ * and kept; the caller allocates slice_sets[ceil(nrows/slice_size)+1] and
+ * ell_col/ell_val[slice_cols*slice_size]. ell_width: -1 chooses it
  * (Ell: the longest row; Hybrid: the width K that minimises stored bytes
  * n*K*(sv+4) + (entries beyond K)*(sv+8), smallest K on ties), otherwise the
  * given width (Ell: SPX_ERR_FORMAT if a row is longer). ell_ld: 0 = nrows.

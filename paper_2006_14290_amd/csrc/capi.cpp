@@ -53,6 +53,15 @@ spx_status check_matrix(const spx_matrix *A, const char *who)
         SPX_REQUIRE(A->coo_nnz == 0 || (A->rowidx && A->colidx && A->vals), SPX_ERR_ARG,
                     "%s: HYB needs its COO arrays", who);
         break;
+    case SPX_SELLP:
+        SPX_REQUIRE(A->slice_size >= 1 && A->slice_size <= 256 && (A->slice_size & (A->slice_size - 1)) == 0,
+                    SPX_ERR_ARG, "%s: SELLP slice_size %d is not a power of two <= 256", who, A->slice_size);
+        SPX_REQUIRE(A->stride_factor >= 1, SPX_ERR_ARG, "%s: SELLP stride_factor < 1", who);
+        SPX_REQUIRE(A->slice_cols >= 0 && A->slice_cols <= INT32_MAX, SPX_ERR_ARG, "%s: bad SELLP slice_cols", who);
+        SPX_REQUIRE(A->nrows == 0 || A->slice_sets != nullptr, SPX_ERR_ARG, "%s: SELLP needs slice_sets", who);
+        SPX_REQUIRE(A->slice_cols == 0 || (A->ell_col && A->ell_val), SPX_ERR_ARG,
+                    "%s: SELLP needs ell_col and ell_val", who);
+        break;
     default:
         SPX_REQUIRE(false, SPX_ERR_ARG, "%s: bad format %d", who, A->fmt);
     }
@@ -71,6 +80,7 @@ static spx_status spmv_typed(const spx_matrix &A, const void *x, void *y, double
     case SPX_COO: return coo_spmv_launch<V, X>(A, xx, yy, a, b, stream);
     case SPX_ELL: return ell_spmv_launch<V, X>(A, xx, yy, a, b, stream);
     case SPX_HYB: return hyb_spmv_launch<V, X>(A, xx, yy, a, b, stream);
+    case SPX_SELLP: return sellp_spmv_launch<V, X>(A, xx, yy, a, b, stream);
     default: break;
     }
     set_error("spmv: bad format");
@@ -170,7 +180,7 @@ extern "C" spx_status spx_convert_plan(const spx_matrix *src, int32_t dst_fmt, i
     clear_error();
     SPX_CHECK(check_matrix(src, "spx_convert_plan"));
     SPX_REQUIRE(dst != nullptr && ws_bytes != nullptr, SPX_ERR_ARG, "spx_convert_plan: null output");
-    SPX_REQUIRE(dst_fmt >= SPX_CSR && dst_fmt <= SPX_HYB, SPX_ERR_ARG, "spx_convert_plan: bad format %d", dst_fmt);
+    SPX_REQUIRE(dst_fmt >= SPX_CSR && dst_fmt <= SPX_SELLP, SPX_ERR_ARG, "spx_convert_plan: bad format %d", dst_fmt);
     return convert_plan(*src, dst_fmt, ell_width, ell_ld, dst, ws_bytes, stream);
 }
 
@@ -195,11 +205,17 @@ extern "C" spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hi
     SPX_REQUIRE(dst->val_type == SPX_F32 || dst->val_type == SPX_F16, SPX_ERR_ARG,
                 "spx_cast_values: target must be SPX_F32 or SPX_F16");
     SPX_REQUIRE(src->fmt == dst->fmt && src->nrows == dst->nrows && src->nnz == dst->nnz &&
-                    src->ell_width == dst->ell_width && src->ell_ld == dst->ell_ld && src->coo_nnz == dst->coo_nnz,
+                    src->ell_width == dst->ell_width && src->ell_ld == dst->ell_ld && src->coo_nnz == dst->coo_nnz &&
+                    (src->fmt != SPX_SELLP ||
+                     (src->slice_size == dst->slice_size && src->slice_cols == dst->slice_cols)),
                 SPX_ERR_ARG, "spx_cast_values: dst shape differs from src");
     int64_t ovf = 0, o = 0;
     if (src->fmt == SPX_CSR || src->fmt == SPX_COO) {
         SPX_CHECK(cast_values(static_cast<const double *>(src->vals), src->nnz, dst->val_type, dst->vals, &o, stream));
+        ovf += o;
+    } else if (src->fmt == SPX_SELLP) {
+        SPX_CHECK(cast_values(static_cast<const double *>(src->ell_val), src->slice_cols * src->slice_size,
+                              dst->val_type, dst->ell_val, &o, stream));
         ovf += o;
     } else {
         SPX_CHECK(cast_values(static_cast<const double *>(src->ell_val), (int64_t)src->ell_width * src->ell_ld,

@@ -377,6 +377,90 @@ __global__ __launch_bounds__(kCvThreads) void cast_kernel(const double *__restri
     if (m && lane_id() == 0) atomicAdd(ovf, (unsigned long long)__builtin_popcountll(m));
 }
 
+
+// ------------------------------------------------------------------ SELL-P
+// Width of every slice: stride_factor * ceil(longest row in the slice /
+// stride_factor), one thread per slice. Written as int32 (out32, shifted by
+// one so that an inclusive scan gives slice_sets) or int64 (out64).
+__global__ __launch_bounds__(kCvThreads) void sellp_width_kernel(const int32_t *__restrict__ rowptr, int32_t n,
+                                                                int32_t C, int32_t T, int64_t nslices,
+                                                                int32_t *__restrict__ out32,
+                                                                int64_t *__restrict__ out64)
+{
+    const int64_t s = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
+    if (s == 0 && out32) out32[0] = 0;
+    if (s >= nslices) return;
+    int32_t m = 0;
+    const int64_t r1 = min((int64_t)n, (s + 1) * C);
+    for (int64_t r = s * C; r < r1; ++r) m = max(m, rowptr[r + 1] - rowptr[r]);
+    const int32_t w = ((m + T - 1) / T) * T;
+    if (out32) out32[s + 1] = w;
+    if (out64) out64[s] = w;
+}
+
+// One thread per (slice, lane): row s*C + l written slot by slot (lanes of a
+// slice are adjacent, so each slot column is written coalesced).
+template <typename V>
+__global__ __launch_bounds__(kCvThreads) void csr_to_sellp_kernel(const int32_t *__restrict__ rowptr,
+                                                                 const int32_t *__restrict__ col,
+                                                                 const V *__restrict__ val, int32_t n, int32_t C,
+                                                                 int64_t nslices, const int32_t *__restrict__ sets,
+                                                                 int32_t *__restrict__ scol, V *__restrict__ sval)
+{
+    const int64_t t = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
+    if (t >= nslices * C) return;
+    const int64_t s = t / C, l = t % C, r = s * C + l;
+    const int32_t a = (r < n) ? rowptr[r] : 0;
+    const int32_t len = (r < n) ? rowptr[r + 1] - a : 0;
+    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = ((int64_t)k0 + k) * C + l;
+        if (k < len) {
+            scol[q] = col[a + k];
+            sval[q] = val[a + k];
+        } else {
+            scol[q] = -1;
+            sval[q] = V(0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kCvThreads) void sellp_count_kernel(const int32_t *__restrict__ sets,
+                                                                const int32_t *__restrict__ scol, int32_t n,
+                                                                int32_t C, int32_t *__restrict__ rowptr)
+{
+    const int64_t r = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
+    if (r == 0) rowptr[0] = 0;
+    if (r >= n) return;
+    const int64_t s = r / C, l = r % C;
+    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+    int32_t c = 0;
+    for (int32_t k = 0; k < w; ++k) c += scol[((int64_t)k0 + k) * C + l] >= 0;
+    rowptr[r + 1] = c;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kCvThreads) void sellp_to_csr_kernel(const int32_t *__restrict__ sets,
+                                                                 const int32_t *__restrict__ scol,
+                                                                 const V *__restrict__ sval, int32_t n, int32_t C,
+                                                                 const int32_t *__restrict__ rowptr,
+                                                                 int32_t *__restrict__ col, V *__restrict__ val)
+{
+    const int64_t r = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
+    if (r >= n) return;
+    const int64_t s = r / C, l = r % C;
+    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+    int32_t o = rowptr[r];
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = ((int64_t)k0 + k) * C + l;
+        if (scol[q] >= 0) {
+            col[o] = scol[q];
+            val[o] = sval[q];
+            ++o;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host side
 static size_t val_size(int32_t t) { return t == SPX_F64 ? 8 : (t == SPX_F32 ? 4 : 2); }
 
@@ -449,9 +533,14 @@ static spx_status hyb_auto_width(const spx_matrix &A, int32_t maxlen, int32_t *K
     return SPX_OK;
 }
 
-int64_t convert_ws_bytes(const spx_matrix &src, int32_t dst_fmt)
+static int32_t sellp_c(int32_t c) { return c > 0 ? c : 64; }
+static int32_t sellp_t(int32_t t) { return t > 0 ? t : 1; }
+
+int64_t convert_ws_bytes(const spx_matrix &src, int32_t dst_fmt, int32_t slice_size)
 {
     const int64_t n = src.nrows;
+    if (src.fmt == SPX_CSR && dst_fmt == SPX_SELLP) return scan_ws_bytes(ceil_div(n, sellp_c(slice_size)) + 1);
+    if (src.fmt == SPX_SELLP && dst_fmt == SPX_CSR) return scan_ws_bytes(n);
     if (src.fmt == SPX_CSR && dst_fmt == SPX_HYB) return (n + 1) * 8 + scan_ws_bytes(n);
     if (dst_fmt == SPX_CSR && (src.fmt == SPX_ELL || src.fmt == SPX_HYB)) return (n + 1) * 8 + scan_ws_bytes(n);
     return 0;
@@ -520,6 +609,41 @@ spx_status convert_plan(const spx_matrix &src, int32_t dst_fmt, int32_t ell_widt
             SPX_CHECK(read_scalar(cnt + n, &tot, stream));
         }
         d.nnz = tot;
+    } else if (src.fmt == SPX_CSR && dst_fmt == SPX_SELLP) {
+        const int32_t C = sellp_c(dst->slice_size), T = sellp_t(dst->stride_factor);
+        SPX_REQUIRE(C <= 256 && (C & (C - 1)) == 0, SPX_ERR_ARG, "convert: slice_size %d is not a power of two <= 256",
+                    C);
+        const int64_t ns = ceil_div(n, C);
+        DevScratch s;
+        SPX_HIP(hipMalloc(&s.p, (size_t)(ns + 1) * 8 + (size_t)scan_ws_bytes(ns + 1)));
+        int64_t *w = static_cast<int64_t *>(s.p);
+        int64_t tot = 0;
+        if (ns > 0) {
+            sellp_width_kernel<<<(unsigned)ceil_div(ns, kCvThreads), kCvThreads, 0, stream>>>(src.rowptr, src.nrows, C,
+                                                                                             T, ns, nullptr, w);
+            SPX_LAUNCHED();
+            SPX_CHECK(inclusive_scan<int64_t>(w, ns, w + ns + 1, stream));
+            SPX_CHECK(read_scalar(w + ns - 1, &tot, stream));
+        }
+        SPX_REQUIRE(tot <= INT32_MAX, SPX_ERR_RANGE, "convert: SELLP slice widths sum to %lld > int32",
+                    (long long)tot);
+        d.nnz = src.nnz;
+        d.slice_size = C;
+        d.stride_factor = T;
+        d.slice_cols = tot;
+    } else if (src.fmt == SPX_SELLP && dst_fmt == SPX_CSR) {
+        DevScratch s;
+        SPX_HIP(hipMalloc(&s.p, (size_t)(n + 1) * 4 + (size_t)scan_ws_bytes(n)));
+        int32_t *cnt = static_cast<int32_t *>(s.p);
+        int32_t tot = 0;
+        if (n > 0) {
+            sellp_count_kernel<<<(unsigned)ceil_div(n, kCvThreads), kCvThreads, 0, stream>>>(
+                src.slice_sets, src.ell_col, src.nrows, src.slice_size, cnt);
+            SPX_LAUNCHED();
+            SPX_CHECK(inclusive_scan<int32_t>(cnt + 1, n, static_cast<char *>(s.p) + (size_t)(n + 1) * 4, stream));
+            SPX_CHECK(read_scalar(cnt + n, &tot, stream));
+        }
+        d.nnz = tot;
     } else if (src.fmt == dst_fmt) {
         SPX_REQUIRE(false, SPX_ERR_ARG, "convert: source and destination formats are the same");
     } else {
@@ -527,7 +651,7 @@ spx_status convert_plan(const spx_matrix &src, int32_t dst_fmt, int32_t ell_widt
                     dst_fmt);
     }
     *dst = d;
-    *ws_bytes = (size_t)convert_ws_bytes(src, dst_fmt);
+    *ws_bytes = (size_t)convert_ws_bytes(src, dst_fmt, d.slice_size);
     return SPX_OK;
 }
 
@@ -595,15 +719,42 @@ static spx_status convert_typed(const spx_matrix &src, spx_matrix &dst, void *ws
         SPX_LAUNCHED();
         return SPX_OK;
     }
+    if (src.fmt == SPX_CSR && dst.fmt == SPX_SELLP) {
+        const int32_t C = dst.slice_size;
+        const int64_t ns = ceil_div(n, C);
+        sellp_width_kernel<<<(unsigned)ceil_div(ns + 1, kCvThreads), kCvThreads, 0, stream>>>(
+            src.rowptr, n, C, dst.stride_factor, ns, dst.slice_sets, nullptr);
+        SPX_LAUNCHED();
+        if (ns > 0) {
+            SPX_CHECK(inclusive_scan<int32_t>(dst.slice_sets + 1, ns, ws, stream));
+            csr_to_sellp_kernel<V><<<(unsigned)ceil_div(ns * C, kCvThreads), kCvThreads, 0, stream>>>(
+                src.rowptr, src.colidx, static_cast<const V *>(src.vals), n, C, ns, dst.slice_sets, dst.ell_col,
+                static_cast<V *>(dst.ell_val));
+            SPX_LAUNCHED();
+        }
+        return SPX_OK;
+    }
+    if (src.fmt == SPX_SELLP && dst.fmt == SPX_CSR) {
+        if (n == 0) return fill<int32_t>(dst.rowptr, 1, 0, stream);
+        sellp_count_kernel<<<gr, kCvThreads, 0, stream>>>(src.slice_sets, src.ell_col, n, src.slice_size, dst.rowptr);
+        SPX_LAUNCHED();
+        SPX_CHECK(inclusive_scan<int32_t>(dst.rowptr + 1, n, ws, stream));
+        sellp_to_csr_kernel<V><<<gr, kCvThreads, 0, stream>>>(src.slice_sets, src.ell_col,
+                                                               static_cast<const V *>(src.ell_val), n,
+                                                               src.slice_size, dst.rowptr, dst.colidx,
+                                                               static_cast<V *>(dst.vals));
+        SPX_LAUNCHED();
+        return SPX_OK;
+    }
     set_error("convert: unsupported pair %d -> %d", src.fmt, dst.fmt);
     return SPX_ERR_ARG;
 }
 
 spx_status convert_run(const spx_matrix &src, spx_matrix &dst, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    SPX_REQUIRE((int64_t)ws_bytes >= convert_ws_bytes(src, dst.fmt) && (ws != nullptr || convert_ws_bytes(src, dst.fmt) == 0),
-                SPX_ERR_ARG, "convert: workspace of %zu bytes is smaller than the %lld needed", ws_bytes,
-                (long long)convert_ws_bytes(src, dst.fmt));
+    const int64_t need = convert_ws_bytes(src, dst.fmt, dst.slice_size);
+    SPX_REQUIRE((int64_t)ws_bytes >= need && (ws != nullptr || need == 0), SPX_ERR_ARG,
+                "convert: workspace of %zu bytes is smaller than the %lld needed", ws_bytes, (long long)need);
     switch (val_size(src.val_type)) {
     case 8: return convert_typed<uint64_t>(src, dst, ws, stream);
     case 4: return convert_typed<uint32_t>(src, dst, ws, stream);

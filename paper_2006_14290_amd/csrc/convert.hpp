@@ -10,7 +10,7 @@ template <typename T>
 spx_status inclusive_scan(T *a, int64_t n, void *ws, hipStream_t stream);
 
 spx_status csr_max_row_len(const spx_matrix &A, int32_t *out, hipStream_t stream);
-int64_t convert_ws_bytes(const spx_matrix &src, int32_t dst_fmt);
+int64_t convert_ws_bytes(const spx_matrix &src, int32_t dst_fmt, int32_t slice_size);
 spx_status convert_plan(const spx_matrix &src, int32_t dst_fmt, int32_t ell_width, int64_t ell_ld, spx_matrix *dst,
                         size_t *ws_bytes, hipStream_t stream);
 spx_status convert_run(const spx_matrix &src, spx_matrix &dst, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -6,10 +6,12 @@
 //   ||r|| <= tol ||b||; s = ||r||_inf; rhat = fl32(r / s); inner CG on the
 //   low-precision matrix (float32 values, or binary16-stored values widened
 //   to float32 before each multiply-add; float32 vectors and sums) from zero
-//   to relative residual inner_tol; x += s * d (float64).
+//   to relative residual max(inner_tol, tol ||b|| / (2 ||r||)) -- the last
+//   step only needs to close the remaining gap; x += s * d (float64).
 // Float64 is used only for the outer residual, the update of x and the
 // stopping norms; every inner iteration moves float32 vectors and the
 // low-precision matrix.
+#include <algorithm>
 #include <cmath>
 
 #include "solver_common.hpp"
@@ -176,6 +178,9 @@ spx_status ir_run(const spx_matrix &A64_in, const spx_matrix &Alow_in, const dou
         ir_amax_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.amax);
         ir_scale_kernel<<<ge, kVecThreads, 0, s>>>(n, w.r, w.amax, w.rf);
         SPX_LAUNCHED();
+        // the inner solve need not reduce the residual (much) beyond what is
+        // left to reach tol ||b||
+        inner.tol = std::max(inner_tol, 0.5 * tol * std::sqrt(bb / rn2));
         spx_status is;
         if (Alow.val_type == SPX_F16)
             is = cg_run<_Float16, float>(Alow, w.rf, w.d, inner, w.inner, w.inner_bytes, &ii, s);

@@ -121,6 +121,22 @@ __global__ __launch_bounds__(kVecThreads) void diag_ell_kernel(const int32_t *__
     }
 }
 
+template <typename V, typename X>
+__global__ __launch_bounds__(kVecThreads) void diag_sellp_kernel(const int32_t *__restrict__ sets,
+                                                                const int32_t *__restrict__ scol,
+                                                                const V *__restrict__ sval, int32_t n, int32_t C,
+                                                                X *__restrict__ d)
+{
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = i / C, l = i % C;
+    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = ((int64_t)k0 + k) * C + l;
+        if (scol[q] == i) d[i] = widen(sval[q]);
+    }
+}
+
 template <typename X>
 __global__ __launch_bounds__(kVecThreads) void dinv_kernel(const X *__restrict__ d, X *__restrict__ dinv, int64_t n,
                                                           KState *st)
@@ -159,6 +175,11 @@ spx_status jacobi_setup(const spx_matrix &A, X *d, X *dinv, KState *st, hipStrea
         if (A.fmt == SPX_HYB && A.coo_nnz > 0)
             diag_coo_kernel<V, X><<<(unsigned)ceil_div(A.coo_nnz, kVecThreads), kVecThreads, 0, stream>>>(
                 A.rowidx, A.colidx, static_cast<const V *>(A.vals), A.coo_nnz, d);
+        break;
+    case SPX_SELLP:
+        diag_sellp_kernel<V, X><<<g, kVecThreads, 0, stream>>>(A.slice_sets, A.ell_col,
+                                                               static_cast<const V *>(A.ell_val), A.nrows,
+                                                               A.slice_size, d);
         break;
     default: break;
     }

@@ -14,6 +14,7 @@ constexpr int kCooThreads = 256;
 constexpr int kCooTiles = 4;                      // 64-entry tiles per wavefront chunk
 constexpr int kCooChunk = 64 * kCooTiles;          // entries per wavefront chunk
 constexpr int kEllThreads = 256;
+constexpr int kSellThreads = 256;
 
 template <typename V, typename X>
 spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
@@ -21,5 +22,7 @@ template <typename V, typename X>
 spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
 template <typename V, typename X>
 spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+template <typename V, typename X>
+spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
 
 }  // namespace spx

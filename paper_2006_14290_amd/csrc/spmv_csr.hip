@@ -65,7 +65,7 @@ __device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t 
 // kEpi: 0 = plain product; 1 = also sum_i y_i*w_i; 2 = also sum_i y_i*w_i
 // and sum_i y_i*y_i. With a solver state the sums are reduced across tiles
 // (deterministically) and finished by `op`; a set state flag skips the launch.
-template <typename V, typename X, int kEpi, int kThreads, int kTile>
+template <typename V, typename X, int kEpi, int kThreads, int kTile, int kVec>
 __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     int32_t nrows, int64_t nnz, int64_t ntiles, int64_t grid_padded, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y,
@@ -75,6 +75,10 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
     using A = X;  // accumulation type
     constexpr int kPer = kTile / kThreads;
+    constexpr int kNV = kPer / kVec;  // vector loads per thread and pass
+    static_assert(kPer % kVec == 0, "tile must split into whole vectors");
+    typedef V VV __attribute__((ext_vector_type(kVec)));
+    typedef int32_t CV __attribute__((ext_vector_type(kVec)));
     __shared__ A prod[kTile];
     __shared__ int32_t s_rp[kThreads + 1];
     __shared__ int64_t s_b[4];
@@ -120,25 +124,32 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     bool continued = false;  // row r holds a partial sum from an earlier pass
     int64_t w0 = s;
     while (true) {
-        const int64_t w1 = (e - w0 > kTile) ? w0 + kTile : e;
+        // A pass covers the kVec-aligned window [a0, a0 + kTile) of the
+        // nonzeros; entries before w0 (the previous owner's) or from w1 on
+        // are loaded only as far as they share a vector with ours, and are
+        // never summed.
+        const int64_t a0 = w0 & ~(int64_t)(kVec - 1);
+        const int64_t w1 = (e - a0 > kTile) ? a0 + kTile : e;
         const bool last = (w1 == e);
         __syncthreads();  // s_carry / prod / s_rp of the previous pass are consumed
         const A carry_in = s_carry;
         // every value and column load of the pass goes out before the first
         // gather; the row pointers of the first row batch are fetched alongside
-        const int cnt = (int)(w1 - w0);
-        const int32_t *__restrict__ colw = col + w0;
-        const V *__restrict__ valw = val + w0;
-        int32_t cc[kPer];
-        V vv[kPer];
+        CV cc[kNV];
+        VV vv[kNV];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int i = tid + u * kThreads;
-            cc[u] = 0;
-            vv[u] = V(0);
-            if (i < cnt) {
-                cc[u] = ld_stream(colw + i);
-                vv[u] = ld_stream(valw + i);
+        for (int u = 0; u < kNV; ++u) {
+            const int64_t base = a0 + ((int64_t)u * kThreads + tid) * kVec;
+            if (base < w1 && base + kVec <= nnz) {
+                cc[u] = ld_stream(reinterpret_cast<const CV *>(col + base));
+                vv[u] = ld_stream(reinterpret_cast<const VV *>(val + base));
+            } else {
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) {
+                    const bool ok = base < w1 && base + j < nnz;
+                    cc[u][j] = ok ? col[base + j] : 0;
+                    vv[u][j] = ok ? val[base + j] : V(0);
+                }
             }
         }
         int64_t row_t = r + tid;
@@ -148,9 +159,13 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
             rp_t1 = rowptr[row_t + 1];
         }
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int i = tid + u * kThreads;
-            if (i < cnt) prod[i] = widen(vv[u]) * x[cc[u]];
+        for (int u = 0; u < kNV; ++u) {
+            typedef A AV __attribute__((ext_vector_type(kVec)));
+            const int64_t base = a0 + ((int64_t)u * kThreads + tid) * kVec;
+            AV pv;
+#pragma unroll
+            for (int j = 0; j < kVec; ++j) pv[j] = (base + j < w1) ? widen(vv[u][j]) * x[cc[u][j]] : A(0);
+            *reinterpret_cast<AV *>(&prod[(u * kThreads + tid) * kVec]) = pv;
         }
         // rows of this pass, in batches of up to kThreads rows
         bool first_batch = true;
@@ -181,8 +196,8 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
                 const int j = j0 + g;
                 A sum = A(0);
                 if (j < nb) {
-                    const int a = (int)((s_rp[j] > w0 ? s_rp[j] : w0) - w0);
-                    const int b = (int)((s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - w0);
+                    const int a = (int)((s_rp[j] > w0 ? s_rp[j] : w0) - a0);
+                    const int b = (int)((s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - a0);
                     for (int p = a + sl; p < b; p += size) sum += prod[p];
                 }
                 sum = subwave_sum_dyn(sum, size);
@@ -252,13 +267,23 @@ spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
     const int64_t ntiles = csr_tiles(A.nnz);
     const int64_t grid = pad_to_xcds(ntiles);
     const V *val = static_cast<const V *>(A.vals);
-#define SPX_CSR_LAUNCH(E)                                                                                        \
-    csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile><<<(unsigned)grid, kCsrThreads, 0, stream>>>(                   \
+    // 16-byte value vectors (and matching column vectors) when both arrays
+    // are 16-byte aligned, else one entry per load
+    constexpr int kVec = 16 / (int)sizeof(V);
+    const bool vec = ((reinterpret_cast<uintptr_t>(A.colidx) | reinterpret_cast<uintptr_t>(val)) & 15) == 0;
+#define SPX_CSR_LAUNCH(E, VEC)                                                                                   \
+    csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile, VEC><<<(unsigned)grid, kCsrThreads, 0, stream>>>(              \
         A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials, A.csr_part, \
         st, op, ticket)
-    if (epi == 2) SPX_CSR_LAUNCH(2);
-    else if (epi == 1) SPX_CSR_LAUNCH(1);
-    else SPX_CSR_LAUNCH(0);
+    if (vec) {
+        if (epi == 2) SPX_CSR_LAUNCH(2, kVec);
+        else if (epi == 1) SPX_CSR_LAUNCH(1, kVec);
+        else SPX_CSR_LAUNCH(0, kVec);
+    } else {
+        if (epi == 2) SPX_CSR_LAUNCH(2, 1);
+        else if (epi == 1) SPX_CSR_LAUNCH(1, 1);
+        else SPX_CSR_LAUNCH(0, 1);
+    }
 #undef SPX_CSR_LAUNCH
     SPX_LAUNCHED();
     return SPX_OK;

@@ -246,10 +246,80 @@ spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
                                 beta, stream);
 }
 
+// SELL-P: one work-group of kSellThreads per slice. Lane l = tid % C owns row
+// s*C + l; the G = kSellThreads / C lane groups take the slice's slot
+// columns round robin (group g: columns g, g + G, ...), each slot column
+// read coalesced across the lanes; the G partial sums of a row are added in
+// group order. Padding slots (column -1) contribute nothing.
+template <typename V, typename X>
+__global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows, int32_t C, int32_t log2c,
+                                                                 int64_t nslices, int64_t grid_padded,
+                                                                 const int32_t *__restrict__ sets,
+                                                                 const int32_t *__restrict__ scol,
+                                                                 const V *__restrict__ sval, const X *__restrict__ x,
+                                                                 X *__restrict__ y, X alpha, X beta)
+{
+    __shared__ X part[kSellThreads];
+    const int64_t s = xcd_remap(blockIdx.x, grid_padded);
+    if (s >= nslices) return;
+    const int tid = threadIdx.x;
+    const int l = tid & (C - 1), g = tid >> log2c;
+    const int G = kSellThreads >> log2c;
+    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+    const int32_t *__restrict__ cs = scol + (int64_t)k0 * C + l;
+    const V *__restrict__ vs = sval + (int64_t)k0 * C + l;
+    X sum = X(0);
+    constexpr int U = 4;
+    int32_t k = g;
+    for (; k + (U - 1) * G < w; k += U * G) {
+        int32_t cc[U];
+        X vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = (int64_t)(k + u * G) * C;
+            cc[u] = ld_stream(cs + q);
+            vv[u] = widen(ld_stream(vs + q));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (cc[u] >= 0) sum += vv[u] * x[cc[u]];
+    }
+    for (; k < w; k += G) {
+        const int64_t q = (int64_t)k * C;
+        const int32_t c = ld_stream(cs + q);
+        const X v = widen(ld_stream(vs + q));
+        if (c >= 0) sum += v * x[c];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    const int64_t row = s * C + l;
+    if (g == 0 && row < nrows) {
+        X t = part[l];
+        for (int j = 1; j < G; ++j) t += part[j * C + l];
+        y[row] = alpha * t + scaled(y[row], beta);
+    }
+}
+
+template <typename V, typename X>
+spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+{
+    const int32_t C = A.slice_size;
+    int32_t log2c = 0;
+    while ((1 << log2c) < C) ++log2c;
+    const int64_t ns = ceil_div(A.nrows, C);
+    const int64_t grid = pad_to_xcds(ns);
+    sellp_spmv_kernel<V, X><<<(unsigned)grid, kSellThreads, 0, stream>>>(A.nrows, C, log2c, ns, grid, A.slice_sets,
+                                                                         A.ell_col, static_cast<const V *>(A.ell_val),
+                                                                         x, y, alpha, beta);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
 #define SPX_INST(V, X)                                                                                          \
     template spx_status coo_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
     template spx_status ell_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
-    template spx_status hyb_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);
+    template spx_status hyb_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
+    template spx_status sellp_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);
 SPX_INST(double, double)
 SPX_INST(float, float)
 SPX_INST(_Float16, float)

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, ERR_ARG, ERR_FORMAT, ERR_UNSORTED, ERR_DUPLICATE, ERR_RANGE, ERR_NOMEM, ERR_BUDGET, ERR_HIP, \
     ERR_ZERO_DIAG, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE, PENDING, CANCELLED = range(15)
 F64, F32, F16 = 0, 1, 2
-CSR, COO, ELL, HYB = 0, 1, 2, 3
+CSR, COO, ELL, HYB, SELLP = 0, 1, 2, 3, 4
 
 _VAL_DTYPE = {F64: torch.float64, F32: torch.float32, F16: torch.float16}
 _VEC_DTYPE = {F64: torch.float64, F32: torch.float32, F16: torch.float32}
@@ -47,7 +47,8 @@ class MatrixDesc(ctypes.Structure):
         ("rowidx", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
         ("coo_nnz", ctypes.c_int64), ("ell_width", ctypes.c_int32), ("max_row_len", ctypes.c_int32),
         ("ell_ld", ctypes.c_int64), ("ell_col", ctypes.c_void_p), ("ell_val", ctypes.c_void_p),
-        ("csr_part", ctypes.c_void_p),
+        ("csr_part", ctypes.c_void_p), ("slice_size", ctypes.c_int32), ("stride_factor", ctypes.c_int32),
+        ("slice_sets", ctypes.c_void_p), ("slice_cols", ctypes.c_int64),
     ]
 
 
@@ -187,6 +188,10 @@ class Matrix:
     ell_val: Optional[torch.Tensor] = None
     max_row_len: int = 0
     csr_part: Optional[torch.Tensor] = None
+    slice_size: int = 0
+    stride_factor: int = 0
+    slice_sets: Optional[torch.Tensor] = None
+    slice_cols: int = 0
     _desc: MatrixDesc = field(default=None, repr=False)
 
     def desc(self) -> MatrixDesc:
@@ -197,6 +202,8 @@ class Matrix:
         d.coo_nnz, d.ell_width, d.max_row_len, d.ell_ld = self.coo_nnz, self.ell_width, self.max_row_len, self.ell_ld
         d.ell_col, d.ell_val = _ptr(self.ell_col), _ptr(self.ell_val)
         d.csr_part = _ptr(self.csr_part)
+        d.slice_size, d.stride_factor, d.slice_cols = self.slice_size, self.stride_factor, self.slice_cols
+        d.slice_sets = _ptr(self.slice_sets)
         self._desc = d
         return d
 
@@ -206,7 +213,8 @@ class Matrix:
 
     def nbytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in
-                   (self.rowptr, self.rowidx, self.colidx, self.vals, self.ell_col, self.ell_val) if t is not None)
+                   (self.rowptr, self.rowidx, self.colidx, self.vals, self.ell_col, self.ell_val, self.slice_sets)
+                   if t is not None)
 
 
 def _dev_vals(vals: np.ndarray, dtype: int, device) -> torch.Tensor:
@@ -239,6 +247,15 @@ def ell_from_host(n, K, ld, ecol, eval_, dtype: int = F64, device="cuda") -> Mat
                   ell_col=torch.from_numpy(ecol).to(device), ell_val=_dev_vals(eval_, dtype, device))
 
 
+def sellp_from_host(n, C, T, slice_sets, scol, sval, dtype: int = F64, device="cuda") -> Matrix:
+    """Upload a host SELL-P matrix (slice size C, stride factor T)."""
+    scol = np.ascontiguousarray(scol, np.int32)
+    sets = np.ascontiguousarray(slice_sets, np.int32)
+    return Matrix(SELLP, dtype, int(n), int(n), int((scol >= 0).sum()), slice_size=int(C), stride_factor=int(T),
+                  slice_sets=torch.from_numpy(sets).to(device), slice_cols=int(sets[-1]),
+                  ell_col=torch.from_numpy(scol).to(device), ell_val=_dev_vals(sval, dtype, device))
+
+
 def hyb_from_host(n, K, ld, ecol, eval_, row, col, val, dtype: int = F64, device="cuda") -> Matrix:
     ecol = np.ascontiguousarray(ecol, np.int32)
     return Matrix(HYB, dtype, int(n), int(n), int((ecol >= 0).sum()) + int(len(row)), ell_width=int(K),
@@ -261,19 +278,23 @@ def csr_analyse(A: Matrix, stream=None) -> Matrix:
 
 
 # ------------------------------------------------------------------ conversion
-def convert(A: Matrix, fmt: int, ell_width: int = -1, ell_ld: int = 0, stream=None) -> Matrix:
+def convert(A: Matrix, fmt: int, ell_width: int = -1, ell_ld: int = 0, slice_size: int = 0,
+            stride_factor: int = 0, stream=None) -> Matrix:
     """Convert A to `fmt` on the device (plan: blocking size query; then an
-    asynchronous conversion into freshly allocated tensors)."""
+    asynchronous conversion into freshly allocated tensors). slice_size and
+    stride_factor apply to SELLP (0 = 64 and 1)."""
     src = A.desc()
     shape = MatrixDesc()
+    shape.slice_size, shape.stride_factor = slice_size, stride_factor
     ws = ctypes.c_size_t(0)
     check(_lib.spx_convert_plan(ctypes.byref(src), fmt, ell_width, ell_ld, ctypes.byref(shape), ctypes.byref(ws),
                                 _stream(stream)), "spx_convert_plan")
-    dev = (A.rowptr if A.rowptr is not None else (A.ell_col if A.ell_col is not None else A.colidx)).device
+    dev = next(t for t in (A.rowptr, A.ell_col, A.colidx, A.slice_sets) if t is not None).device
     vt = _VAL_DTYPE[A.dtype]
     i32 = dict(dtype=torch.int32, device=dev)
     out = Matrix(fmt, A.dtype, shape.nrows, shape.ncols, shape.nnz, coo_nnz=shape.coo_nnz,
-                 ell_width=shape.ell_width, ell_ld=shape.ell_ld)
+                 ell_width=shape.ell_width, ell_ld=shape.ell_ld, slice_size=shape.slice_size,
+                 stride_factor=shape.stride_factor, slice_cols=shape.slice_cols)
     if fmt == CSR:
         out.rowptr = torch.empty(shape.nrows + 1, **i32)
         out.colidx = torch.empty(shape.nnz, **i32)
@@ -282,6 +303,11 @@ def convert(A: Matrix, fmt: int, ell_width: int = -1, ell_ld: int = 0, stream=No
         out.rowidx = torch.empty(shape.nnz, **i32)
         out.colidx = torch.empty(shape.nnz, **i32)
         out.vals = torch.empty(shape.nnz, dtype=vt, device=dev)
+    elif fmt == SELLP:
+        ns = -(-shape.nrows // shape.slice_size)
+        out.slice_sets = torch.empty(ns + 1, **i32)
+        out.ell_col = torch.empty(shape.slice_cols * shape.slice_size, **i32)
+        out.ell_val = torch.empty(shape.slice_cols * shape.slice_size, dtype=vt, device=dev)
     else:
         out.ell_col = torch.empty(shape.ell_width * shape.ell_ld, **i32)
         out.ell_val = torch.empty(shape.ell_width * shape.ell_ld, dtype=vt, device=dev)
@@ -300,7 +326,8 @@ def cast_values(A: Matrix, dtype: int, stream=None) -> Matrix:
     """Copy of A (sharing its index arrays) with values rounded to dtype."""
     out = Matrix(A.fmt, dtype, A.nrows, A.ncols, A.nnz, rowptr=A.rowptr, rowidx=A.rowidx, colidx=A.colidx,
                  coo_nnz=A.coo_nnz, ell_width=A.ell_width, ell_ld=A.ell_ld, ell_col=A.ell_col,
-                 max_row_len=A.max_row_len, csr_part=A.csr_part)
+                 max_row_len=A.max_row_len, csr_part=A.csr_part, slice_size=A.slice_size,
+                 stride_factor=A.stride_factor, slice_sets=A.slice_sets, slice_cols=A.slice_cols)
     vt = _VAL_DTYPE[dtype]
     if A.vals is not None:
         out.vals = torch.empty(A.vals.numel(), dtype=vt, device=A.vals.device)
