@@ -280,7 +280,14 @@ def bench_solvers(spx, S, torch, dev):
                                  "us_per_iter": round(it_us, 2),
                                  "GBs": round(cg_iter_bytes(A.n, A.nnz, 8, True) / it_us / 1e3, 1),
                                  "relres_true": info["relres_true"]}
-    del Ad, A
+    # the same solve on the SELL-P form of the matrix (the paper runs CG on Sellp)
+    Ps = spx.convert(Ad, spx.SELLP)
+    spx.cg_solve(Ps, bd, tol=1e-10, precond=1, maxit=5000)
+    x, info = spx.cg_solve(Ps, bd, tol=1e-10, precond=1, maxit=5000)
+    it_us = 1e3 * info["device_ms"] / max(info["iters"], 1)
+    out["cg_jacobi_aniso128_sellp"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
+                                       "us_per_iter": round(it_us, 2), "relres_true": info["relres_true"]}
+    del Ad, A, Ps
     A = S.convdiff3d_upwind(128)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
     bd = rhs(spx, S, torch, Ad)

@@ -173,8 +173,7 @@ static BiBufs bi_carve(Carve &c, const spx_matrix &A, int precond)
     w.sh = precond ? c.take<X>(n) : w.s;
     w.d = precond ? c.take<X>(n) : nullptr;
     w.dinv = precond ? c.take<X>(n) : nullptr;
-    const int64_t slots = (csr_tiles(A.nnz) > vec_blocks(n) ? csr_tiles(A.nnz) : vec_blocks(n));
-    w.partials = c.take<X>(3 * slots);
+    w.partials = c.take<X>(3 * partial_slots(A));
     w.part = (A.fmt == SPX_CSR && A.csr_part == nullptr) ? c.take<int32_t>(csr_partition_bytes(A.nnz) / 4) : nullptr;
     return w;
 }

@@ -277,7 +277,7 @@ static GmBufs gm_carve(Carve &c, const spx_matrix &A, int precond, int m)
     w.d = precond ? c.take<X>(n) : nullptr;
     w.dinv = precond ? c.take<X>(n) : nullptr;
     const int64_t vb = vec_blocks(n);
-    const int64_t slots = csr_tiles(A.nnz) > (m + 2) * vb ? csr_tiles(A.nnz) : (m + 2) * vb;
+    const int64_t slots = spmv_dot_parts(A) > (m + 2) * vb ? spmv_dot_parts(A) : (m + 2) * vb;
     w.partials = c.take<X>(slots);
     w.gmem = c.take<X>((int64_t)(m + 1) * m + (m + 1) + 3 * m);
     w.part = (A.fmt == SPX_CSR && A.csr_part == nullptr) ? c.take<int32_t>(csr_partition_bytes(A.nnz) / 4) : nullptr;

@@ -89,7 +89,7 @@ static IrBufs ir_carve(Carve &c, const spx_matrix &A64, const spx_matrix &Alow)
     w.rf = c.take<float>(n);
     w.d = c.take<float>(n);
     w.amax = c.take<unsigned long long>(1);
-    w.partials = c.take<double>(3 * (csr_tiles(A64.nnz) > vec_blocks(n) ? csr_tiles(A64.nnz) : vec_blocks(n)));
+    w.partials = c.take<double>(3 * partial_slots(A64));
     w.part64 = (A64.fmt == SPX_CSR && A64.csr_part == nullptr) ? c.take<int32_t>(csr_partition_bytes(A64.nnz) / 4)
                                                                 : nullptr;
     w.partlo = (Alow.fmt == SPX_CSR && Alow.csr_part == nullptr) ? c.take<int32_t>(csr_partition_bytes(Alow.nnz) / 4)

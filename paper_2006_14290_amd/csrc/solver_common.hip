@@ -255,6 +255,10 @@ spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partia
         SPX_CHECK((csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op, ticket)));
         return launch_finish<X>(partials, csr_tiles(A.nnz), 1, st, op, stream);
     }
+    if (A.fmt == SPX_SELLP) {
+        SPX_CHECK((sellp_spmv_launch<V, X>(A, p, q, X(1), X(0), stream, 1, w, partials, st)));
+        return launch_finish<X>(partials, spmv_dot_parts(A), 1, st, op, stream);
+    }
     SPX_CHECK(spmv_dispatch(A, p, q, 1.0, 0.0, stream));
     dot_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, w, q, partials, st, op, ticket);
     SPX_LAUNCHED();
@@ -268,6 +272,10 @@ spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *part
     if (A.fmt == SPX_CSR) {
         SPX_CHECK((csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op, ticket)));
         return launch_finish<X>(partials, csr_tiles(A.nnz), 2, st, op, stream);
+    }
+    if (A.fmt == SPX_SELLP) {
+        SPX_CHECK((sellp_spmv_launch<V, X>(A, sv, t, X(1), X(0), stream, 2, w, partials, st)));
+        return launch_finish<X>(partials, spmv_dot_parts(A), 2, st, op, stream);
     }
     SPX_CHECK(spmv_dispatch(A, sv, t, 1.0, 0.0, stream));
     dot2_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, t, w, partials, st, op, ticket);

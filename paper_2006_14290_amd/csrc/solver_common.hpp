@@ -16,6 +16,21 @@ constexpr int kVecChunk = kVecThreads * kVecItems;     // elements per work-grou
 
 inline int64_t vec_blocks(int64_t n) { return n > 0 ? ceil_div(n, kVecChunk) : 1; }
 
+// Partials written by the fused product + dot of A (CSR: one per tile;
+// SELL-P: one per slice; other formats: the separate dot kernel's blocks),
+// and the partials slots a solver needs (at least one vector pass).
+inline int64_t spmv_dot_parts(const spx_matrix &A)
+{
+    if (A.fmt == SPX_CSR) return csr_tiles(A.nnz);
+    if (A.fmt == SPX_SELLP) return A.nrows > 0 ? ceil_div(A.nrows, A.slice_size) : 1;
+    return vec_blocks(A.nrows);
+}
+inline int64_t partial_slots(const spx_matrix &A)
+{
+    const int64_t a = spmv_dot_parts(A), b = vec_blocks(A.nrows);
+    return a > b ? a : b;
+}
+
 // Bump allocator over a caller-provided workspace (256-byte aligned pieces).
 struct Carve {
     char *base;

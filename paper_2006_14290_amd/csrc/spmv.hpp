@@ -22,7 +22,12 @@ template <typename V, typename X>
 spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
 template <typename V, typename X>
 spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+struct KState;
+// epi = 1: also one partial of sum_i y_i*dot_with_i per slice; epi = 2: that
+// and sum_i y_i^2 (partials[epi][nslices]); a set st->flag skips the launch.
 template <typename V, typename X>
-spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream,
+                             int epi = 0, const X *dot_with = nullptr, X *partials = nullptr,
+                             const KState *st = nullptr);
 
 }  // namespace spx

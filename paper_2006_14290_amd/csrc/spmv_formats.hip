@@ -21,6 +21,7 @@
 // adds the COO part (plain read-modify-write for rows inside a chunk, atomics
 // for rows crossing a chunk boundary).
 #include "common.hpp"
+#include "krylov.hpp"
 #include "spmv.hpp"
 #include "wave.hpp"
 
@@ -251,14 +252,20 @@ spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
 // columns round robin (group g: columns g, g + G, ...), each slot column
 // read coalesced across the lanes; the G partial sums of a row are added in
 // group order. Padding slots (column -1) contribute nothing.
-template <typename V, typename X>
+// kEpi: 0 = plain product; 1 = also the slice's sum of y_i*w_i; 2 = that and
+// sum of y_i^2 (one partial per slice, reduced later in a fixed order; a set
+// solver flag skips the launch).
+template <typename V, typename X, int kEpi>
 __global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows, int32_t C, int32_t log2c,
                                                                  int64_t nslices, int64_t grid_padded,
                                                                  const int32_t *__restrict__ sets,
                                                                  const int32_t *__restrict__ scol,
                                                                  const V *__restrict__ sval, const X *__restrict__ x,
-                                                                 X *__restrict__ y, X alpha, X beta)
+                                                                 X *__restrict__ y, X alpha, X beta,
+                                                                 const X *__restrict__ dot_with,
+                                                                 X *__restrict__ partials, const KState *st)
 {
+    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
     __shared__ X part[kSellThreads];
     const int64_t s = xcd_remap(blockIdx.x, grid_padded);
     if (s >= nslices) return;
@@ -293,24 +300,41 @@ __global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows,
     part[tid] = sum;
     __syncthreads();
     const int64_t row = s * C + l;
+    X d1 = X(0), d2 = X(0);
     if (g == 0 && row < nrows) {
         X t = part[l];
         for (int j = 1; j < G; ++j) t += part[j * C + l];
-        y[row] = alpha * t + scaled(y[row], beta);
+        const X out = alpha * t + scaled(y[row], beta);
+        y[row] = out;
+        if constexpr (kEpi >= 1) d1 = out * dot_with[row];
+        if constexpr (kEpi >= 2) d2 = out * out;
+    }
+    if constexpr (kEpi > 0) {
+        __shared__ X s_red[kSellThreads / kWave];
+        X v[kEpi];
+        v[0] = block_sum<X, kSellThreads>(d1, s_red);
+        if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<X, kSellThreads>(d2, s_red);
+        write_partials<X, kEpi>(v, partials, nslices, s);
     }
 }
 
 template <typename V, typename X>
-spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream, int epi,
+                             const X *dot_with, X *partials, const KState *st)
 {
     const int32_t C = A.slice_size;
     int32_t log2c = 0;
     while ((1 << log2c) < C) ++log2c;
     const int64_t ns = ceil_div(A.nrows, C);
     const int64_t grid = pad_to_xcds(ns);
-    sellp_spmv_kernel<V, X><<<(unsigned)grid, kSellThreads, 0, stream>>>(A.nrows, C, log2c, ns, grid, A.slice_sets,
-                                                                         A.ell_col, static_cast<const V *>(A.ell_val),
-                                                                         x, y, alpha, beta);
+#define SPX_SELL_LAUNCH(E)                                                                                         \
+    sellp_spmv_kernel<V, X, E><<<(unsigned)grid, kSellThreads, 0, stream>>>(                                       \
+        A.nrows, C, log2c, ns, grid, A.slice_sets, A.ell_col, static_cast<const V *>(A.ell_val), x, y, alpha, beta, \
+        dot_with, partials, st)
+    if (epi == 2) SPX_SELL_LAUNCH(2);
+    else if (epi == 1) SPX_SELL_LAUNCH(1);
+    else SPX_SELL_LAUNCH(0);
+#undef SPX_SELL_LAUNCH
     SPX_LAUNCHED();
     return SPX_OK;
 }
@@ -319,7 +343,8 @@ spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X b
     template spx_status coo_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
     template spx_status ell_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
     template spx_status hyb_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
-    template spx_status sellp_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);
+    template spx_status sellp_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t, int,      \
+                                                const X *, X *, const KState *);
 SPX_INST(double, double)
 SPX_INST(float, float)
 SPX_INST(_Float16, float)

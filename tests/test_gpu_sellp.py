@@ -110,3 +110,15 @@ def test_sellp_bad_slice_size_rejected():
     y = dev(np.zeros(A.n))
     st = spx._lib.spx_spmv(ctypes.byref(Pd.desc()), spx._ptr(x), spx._ptr(y), 1.0, 0.0, spx._stream())
     assert st == spx.ERR_ARG
+
+
+def test_sellp_bicgstab_gmres_convdiff():
+    A = S.convdiff3d_upwind(20)
+    xs = S.uniform_vector(A.n, seed=0, purpose="xstar")
+    b, _ = O.csr_spmv_dot2(A, xs)
+    Pd = spx.convert(spx.csr_from_host(A), spx.SELLP, slice_size=32, stride_factor=2)
+    for fn in (spx.bicgstab_solve, spx.gmres_solve):
+        x, info = fn(Pd, dev(b), tol=1e-10, precond=1, maxit=5000)
+        assert info["status"] == spx.OK, info
+        _, rn = O.residual(A, b, host(x))
+        assert rn / np.linalg.norm(b) <= 1e-10
