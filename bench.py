@@ -173,6 +173,27 @@ def conversion_sweep(spx, torch, dev, A, tag, steps=20):
     return out
 
 
+def subwarp_sweep(spx, torch, dev):
+    """Subwarp reduction cost versus subwarp size (the protocol of the paper's
+    reduction benchmark, Section 3.3): every lane of 2^22 float64 values
+    repeats the subwarp sum 1,000 times on its running value. The cost per
+    reduction step (size 1 subtracted) should grow as log2(size)."""
+    n = 1 << 22
+    loops = 1000
+    x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n)).to(dev)
+    out = torch.empty_like(x)
+    t = {}
+    for size in (1, 2, 4, 8, 16, 32, 64):
+        ms = time_launches(lambda i: spx.subwarp_sum(x, size, loops, out), 5, 2, torch)
+        t[size] = ms
+    base = t[1]
+    res = {str(k): {"ms": round(v, 4), "ns_per_reduction_per_wave": round((v - base) * 1e6 / (loops * n / 64 / 1), 6)}
+           for k, v in t.items()}
+    res["ratio_4_over_64"] = round((t[4] - base) / (t[64] - base), 3)
+    res["theory_4_over_64"] = round(2 / 6, 3)
+    return res
+
+
 def profile_traffic(name, algo_bytes):
     """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter runs
     summarised in profiles/<name>.md, or None when the kernel sources listed
@@ -426,6 +447,7 @@ def main():
     ap.add_argument("--cg-batch", type=int, default=1024, help="systems in the batched 64x64 CG run (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving run (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--subwarp", action="store_true", help="also time the subwarp reduction versus subwarp size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -485,6 +507,7 @@ def main():
     cg_small = bench_cg_small(spx, S, torch, dev, args.cg_solves, args.cg_batch) if args.cg_solves > 0 else None
     solvers = bench_solvers(spx, S, torch, dev) if args.solvers else None
     serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed) if args.serve_requests > 0 else None
+    subwarp = subwarp_sweep(spx, torch, dev) if args.subwarp else None
 
     cpu = None
     if not args.no_cpu:
@@ -530,6 +553,7 @@ def main():
         "cg_poisson64": cg_small,
         "solvers": solvers,
         "serve": serve,
+        "subwarp": subwarp,
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
     }

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kVecThreads) void cg_init_kernel(int64_t n, const X
     write_partials<X, 3>(v, partials, gridDim.x, blockIdx.x);
 }
 
-template <typename X>
+// Each thread takes kVecItems consecutive entries: one 16/32-byte load per
+// vector when kVec (all pointers suitably aligned), else element by element.
+template <typename X, bool kVec>
 __global__ __launch_bounds__(kVecThreads) void cg_update_kernel(int64_t n, X *__restrict__ x, const X *__restrict__ p,
                                                                const X *__restrict__ q, X *__restrict__ r,
                                                                X *__restrict__ z, const X *__restrict__ dinv,
@@ -58,13 +60,30 @@ __global__ __launch_bounds__(kVecThreads) void cg_update_kernel(int64_t n, X *__
 {
     if (st->flag != kRunning) return;
     __shared__ X s_red[kVecThreads / kWave];
+    typedef X XV __attribute__((ext_vector_type(kVecItems)));
     const X a = (X)st->alpha;
-    const int64_t base = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t i0 = ((int64_t)blockIdx.x * kVecThreads + threadIdx.x) * kVecItems;
     X rz = X(0), rr = X(0);
+    if (kVec && i0 + kVecItems <= n) {
+        XV xv = *reinterpret_cast<const XV *>(x + i0);
+        const XV pv = *reinterpret_cast<const XV *>(p + i0);
+        const XV qv = *reinterpret_cast<const XV *>(q + i0);
+        XV rv = *reinterpret_cast<const XV *>(r + i0);
+        XV zv;
+        const XV dv = dinv ? *reinterpret_cast<const XV *>(dinv + i0) : XV{};
 #pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-        const int64_t i = base + threadIdx.x + u * kVecThreads;
-        if (i < n) {
+        for (int u = 0; u < kVecItems; ++u) {
+            xv[u] += a * pv[u];
+            rv[u] = rv[u] - a * qv[u];
+            zv[u] = dinv ? rv[u] * dv[u] : rv[u];
+            rz += rv[u] * zv[u];
+            rr += rv[u] * rv[u];
+        }
+        *reinterpret_cast<XV *>(x + i0) = xv;
+        *reinterpret_cast<XV *>(r + i0) = rv;
+        if (dinv) *reinterpret_cast<XV *>(z + i0) = zv;
+    } else {
+        for (int64_t i = i0; i < i0 + kVecItems && i < n; ++i) {
             x[i] += a * p[i];
             const X ri = r[i] - a * q[i];
             r[i] = ri;
@@ -78,17 +97,22 @@ __global__ __launch_bounds__(kVecThreads) void cg_update_kernel(int64_t n, X *__
     write_partials<X, 2>(v, partials, gridDim.x, blockIdx.x);
 }
 
-template <typename X>
+template <typename X, bool kVec>
 __global__ __launch_bounds__(kVecThreads) void cg_p_kernel(int64_t n, const X *__restrict__ z, X *__restrict__ p,
                                                           const KState *st)
 {
     if (st->flag != kRunning) return;
+    typedef X XV __attribute__((ext_vector_type(kVecItems)));
     const X be = (X)st->beta;
-    const int64_t base = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t i0 = ((int64_t)blockIdx.x * kVecThreads + threadIdx.x) * kVecItems;
+    if (kVec && i0 + kVecItems <= n) {
+        const XV zv = *reinterpret_cast<const XV *>(z + i0);
+        XV pv = *reinterpret_cast<const XV *>(p + i0);
 #pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-        const int64_t i = base + threadIdx.x + u * kVecThreads;
-        if (i < n) p[i] = z[i] + be * p[i];
+        for (int u = 0; u < kVecItems; ++u) pv[u] = zv[u] + be * pv[u];
+        *reinterpret_cast<XV *>(p + i0) = pv;
+    } else {
+        for (int64_t i = i0; i < i0 + kVecItems && i < n; ++i) p[i] = z[i] + be * p[i];
     }
 }
 
@@ -201,13 +225,22 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
 
     GraphGuard graph;
     const int m = sp.check_every > 0 ? sp.check_every : 16;
+    // vector loads need every vector aligned to kVecItems entries (x is the
+    // caller's; the workspace pieces are 256-byte aligned)
+    const bool vec = (reinterpret_cast<uintptr_t>(x) % (kVecItems * sizeof(X))) == 0;
     auto iterations = [&]() -> spx_status {
         for (int it = 0; it < m; ++it) {
             SPX_CHECK((spmv_dot<V, X>(A, w.p, w.q, w.p, w.partials, w.st, kOpCgAlpha, 0, s)));
-            cg_update_kernel<X><<<gv, kVecThreads, 0, s>>>(n, x, w.p, w.q, w.r, sp.precond ? w.z : nullptr,
-                                                          w.dinv, w.partials, w.st);
+            if (vec) {
+                cg_update_kernel<X, true><<<gv, kVecThreads, 0, s>>>(n, x, w.p, w.q, w.r, sp.precond ? w.z : nullptr,
+                                                                    w.dinv, w.partials, w.st);
+            } else {
+                cg_update_kernel<X, false><<<gv, kVecThreads, 0, s>>>(n, x, w.p, w.q, w.r,
+                                                                     sp.precond ? w.z : nullptr, w.dinv, w.partials,
+                                                                     w.st);
+            }
             SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpCgRho, s));
-            cg_p_kernel<X><<<gv, kVecThreads, 0, s>>>(n, w.z, w.p, w.st);
+            cg_p_kernel<X, true><<<gv, kVecThreads, 0, s>>>(n, w.z, w.p, w.st);
             SPX_LAUNCHED();
         }
         return SPX_OK;

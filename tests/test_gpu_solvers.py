@@ -70,6 +70,24 @@ def test_cg_jacobi_nonconstant_diag_and_x0():
     assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
 
 
+def test_cg_unaligned_solution_vector():
+    """x that is not 32-byte aligned takes the element-wise update kernels;
+    the solve must reach the same tolerance and (the same arithmetic in each
+    element) the same iterate as an aligned x."""
+    A = S.poisson2d(37)
+    xs, b = _problem(A, seed=3)
+    Ad = spx.csr_from_host(A)
+    big = torch.zeros(A.n + 1, dtype=torch.float64, device="cuda")
+    xu = big[1:]
+    assert xu.data_ptr() % 32 != 0
+    xu, info = spx.cg_solve(Ad, dev(b), xu, tol=1e-10, precond=1)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(xu)) <= 1e-10
+    xa, ia = spx.cg_solve(Ad, dev(b), tol=1e-10, precond=1)
+    assert ia["iters"] == info["iters"]
+    np.testing.assert_array_equal(host(xa).view(np.uint64), host(xu).view(np.uint64))
+
+
 def test_cg_bitwise_reproducible():
     A = S.poisson3d_7pt(20, 1, 1, 0.01)
     xs, b = _problem(A)
