@@ -98,8 +98,12 @@ def format_sweep(spx, torch, dev, A, x_h, args, tag):
                 "hyb": (lambda: spx.convert(base, spx.HYB), hyb_bytes(n, hK, hC, sv, sx)),
                 "sellp": (lambda: spx.convert(base, spx.SELLP), sellp_bytes(n, scols, 64, sv, sx)),
             })
-        if vt == spx.F64:
-            variants["csr_nopart"] = (lambda: spx.csr_from_host(A, vt, dev), csr_bytes(n, nnz, sv, sx))
+        def load_balanced():
+            M = spx.csr_from_host(A, vt, dev)
+            M.max_row_len = 0  # no row-length hint: the load-balanced kernel
+            return spx.csr_analyse(M)
+
+        variants["csr_lb"] = (load_balanced, csr_bytes(n, nnz, sv, sx))
         for fmt, (make, vb) in variants.items():
             name = f"{tag}_{fmt}_{vname}"
             if vb > 0.8 * free:
@@ -192,6 +196,18 @@ def subwarp_sweep(spx, torch, dev):
     res["ratio_4_over_64"] = round((t[4] - base) / (t[64] - base), 3)
     res["theory_4_over_64"] = round(2 / 6, 3)
     return res
+
+
+def csr_kernel_name(M):
+    """Name of the CSR kernel the library picks for M (mirrors its rule:
+    row-per-subwarp when rows are short and even, else load-balanced)."""
+    if M is None or M.max_row_len <= 0 or M.nnz <= 0 or M.nrows > 65536:
+        return "csr_spmv_kernel (load-balanced)"
+    mean = -(-M.nnz // M.nrows)
+    sub = 4
+    while sub < 64 and sub < mean:
+        sub *= 2
+    return f"csr_rows_kernel (subwarp {sub})" if M.max_row_len <= 2 * sub else "csr_spmv_kernel (load-balanced)"
 
 
 def profile_traffic(name, algo_bytes):
@@ -471,6 +487,7 @@ def main():
     fp = csr_bytes(n, nnz, 8, 8)
     R = max(2, int(np.ceil((1 << 30) / fp)))
     mats = [spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev)) for _ in range(R)]
+    kname = csr_kernel_name(mats[0])
     xs = [torch.from_numpy(x_h).to(dev) for _ in range(R)]
     ys = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(R)]
 
@@ -546,7 +563,7 @@ def main():
         "pct_of_copy": round(100 * r["GBs"] / copy_gbs, 2),
         "roofline": {"bound": "hbm", "achieved": round(r["GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "csr_spmv_kernel<double,double,0,512,4096>", "bytes_per_launch": b},
+                     "kernel": kname, "bytes_per_launch": b},
         "sweep": {k: ({kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()})
                   for k, v in results.items()},
         "conversions": conversions,

@@ -122,16 +122,24 @@ int32_t spx_version(void);
 spx_status spx_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
                     hipStream_t stream);
 
-/* Same as spx_spmv but requires fmt == SPX_CSR. The rows are split into
- * work-groups of equal nonzero count (a row is owned by the group in which it
- * starts), so skewed row lengths stay balanced; each group stages products
- * in LDS and reduces every row with a subwarp whose size adapts to the
- * number of rows in the group. */
+/* Same as spx_spmv but requires fmt == SPX_CSR. Two kernels:
+ *  - small matrices (at most 65536 rows) with short, even rows
+ *    (A->max_row_len known and at most twice the power of two at or above
+ *    the mean row length): one subwarp of that many lanes per row, DPP row
+ *    sums;
+ *  - otherwise (or max_row_len == 0): load balanced. The rows are split into
+ *    work-groups of equal nonzero count (a row is owned by the group in which
+ *    it starts), so skewed row lengths stay balanced; each group stages the
+ *    column indices and values in LDS and reduces every row with a subwarp
+ *    whose size adapts to the number of rows in the group, gathering x as it
+ *    goes.
+ * max_row_len is a hint: a wrong value changes the speed, not the result
+ * beyond rounding. */
 spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
                         hipStream_t stream);
 
 /* CSR analysis: the row partition of the load-balanced CSR product.
- * The nonzeros are cut into tiles of 4096; for every tile boundary the
+ * The nonzeros are cut into tiles of 2048; for every tile boundary the
  * partition stores (first row starting at or after the boundary, that row's
  * offset) as two int32. Computing it once per matrix lets every later
  * product (and every solver iteration) skip the per-tile search of the row

@@ -253,7 +253,7 @@ spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partia
 {
     if (A.fmt == SPX_CSR) {
         SPX_CHECK((csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op, ticket)));
-        return launch_finish<X>(partials, csr_tiles(A.nnz), 1, st, op, stream);
+        return launch_finish<X>(partials, csr_dot_parts(A), 1, st, op, stream);
     }
     if (A.fmt == SPX_SELLP) {
         SPX_CHECK((sellp_spmv_launch<V, X>(A, p, q, X(1), X(0), stream, 1, w, partials, st)));
@@ -271,7 +271,7 @@ spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *part
 {
     if (A.fmt == SPX_CSR) {
         SPX_CHECK((csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op, ticket)));
-        return launch_finish<X>(partials, csr_tiles(A.nnz), 2, st, op, stream);
+        return launch_finish<X>(partials, csr_dot_parts(A), 2, st, op, stream);
     }
     if (A.fmt == SPX_SELLP) {
         SPX_CHECK((sellp_spmv_launch<V, X>(A, sv, t, X(1), X(0), stream, 2, w, partials, st)));

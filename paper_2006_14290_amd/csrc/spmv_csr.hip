@@ -65,7 +65,7 @@ __device__ int64_t lower_bound_wave(const int32_t *__restrict__ rowptr, int64_t 
 // kEpi: 0 = plain product; 1 = also sum_i y_i*w_i; 2 = also sum_i y_i*w_i
 // and sum_i y_i*y_i. With a solver state the sums are reduced across tiles
 // (deterministically) and finished by `op`; a set state flag skips the launch.
-template <typename V, typename X, int kEpi, int kThreads, int kTile, int kVec>
+template <typename V, typename X, int kEpi, int kThreads, int kTile, int kVec, bool kLate>
 __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     int32_t nrows, int64_t nnz, int64_t ntiles, int64_t grid_padded, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y,
@@ -79,7 +79,15 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     static_assert(kPer % kVec == 0, "tile must split into whole vectors");
     typedef V VV __attribute__((ext_vector_type(kVec)));
     typedef int32_t CV __attribute__((ext_vector_type(kVec)));
-    __shared__ A prod[kTile];
+    // kLate: the pass's columns and values are staged and x is gathered while
+    // the rows are reduced (a subwarp's lanes then sit on neighbouring rows,
+    // so a gather instruction touches few cache lines on banded matrices);
+    // otherwise the products are formed while staging.
+    constexpr size_t kLdsBytes = kLate ? (size_t)kTile * (sizeof(int32_t) + sizeof(V)) : (size_t)kTile * sizeof(A);
+    __shared__ __align__(16) unsigned char s_raw[kLdsBytes];
+    A *prod = reinterpret_cast<A *>(s_raw);
+    V *s_val = reinterpret_cast<V *>(s_raw);
+    int32_t *s_col = reinterpret_cast<int32_t *>(s_raw + (size_t)kTile * sizeof(V));
     __shared__ int32_t s_rp[kThreads + 1];
     __shared__ int64_t s_b[4];
     __shared__ A s_carry;
@@ -160,12 +168,17 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
         }
 #pragma unroll
         for (int u = 0; u < kNV; ++u) {
-            typedef A AV __attribute__((ext_vector_type(kVec)));
-            const int64_t base = a0 + ((int64_t)u * kThreads + tid) * kVec;
-            AV pv;
+            if constexpr (kLate) {
+                *reinterpret_cast<VV *>(&s_val[(u * kThreads + tid) * kVec]) = vv[u];
+                *reinterpret_cast<CV *>(&s_col[(u * kThreads + tid) * kVec]) = cc[u];
+            } else {
+                typedef A AV __attribute__((ext_vector_type(kVec)));
+                const int64_t base = a0 + ((int64_t)u * kThreads + tid) * kVec;
+                AV pv;
 #pragma unroll
-            for (int j = 0; j < kVec; ++j) pv[j] = (base + j < w1) ? widen(vv[u][j]) * x[cc[u][j]] : A(0);
-            *reinterpret_cast<AV *>(&prod[(u * kThreads + tid) * kVec]) = pv;
+                for (int j = 0; j < kVec; ++j) pv[j] = (base + j < w1) ? widen(vv[u][j]) * x[cc[u][j]] : A(0);
+                *reinterpret_cast<AV *>(&prod[(u * kThreads + tid) * kVec]) = pv;
+            }
         }
         // rows of this pass, in batches of up to kThreads rows
         bool first_batch = true;
@@ -198,7 +211,12 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
                 if (j < nb) {
                     const int a = (int)((s_rp[j] > w0 ? s_rp[j] : w0) - a0);
                     const int b = (int)((s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - a0);
-                    for (int p = a + sl; p < b; p += size) sum += prod[p];
+                    if constexpr (kLate) {
+#pragma unroll 4
+                        for (int p = a + sl; p < b; p += size) sum += widen(s_val[p]) * x[s_col[p]];
+                    } else {
+                        for (int p = a + sl; p < b; p += size) sum += prod[p];
+                    }
                 }
                 sum = subwave_sum_dyn(sum, size);
                 if (j < nb && sl == 0) {
@@ -234,6 +252,82 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     }
 }
 
+
+// Row-per-subwarp CSR product for short, regular rows (the "classical"
+// strategy: a subwarp of kSub lanes per row, kSub the power of two at or
+// above the mean row length). A block takes kRowU * kRowThreads / kSub
+// consecutive rows; at step u the subwarps of a wavefront hold adjacent rows,
+// so every load instruction reads one contiguous stretch of col / val. The
+// first kSub entries of all kRowU rows are loaded before the first gather;
+// longer rows continue in a loop. Rows are reduced with DPP (fixed order).
+// A block repeats this kRowIters times over the following rows.
+template <typename V, typename X, int kEpi, int kSub>
+__global__ __launch_bounds__(kRowThreads) void csr_rows_kernel(
+    int32_t nrows, int64_t nblocks, int64_t grid_padded, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y, X alpha,
+    X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, KState *__restrict__ st)
+{
+    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    constexpr int kSubs = kRowThreads / kSub;
+    constexpr int64_t kStep = (int64_t)kSubs * kRowU;  // rows per block iteration
+    const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
+    if (blk >= nblocks) return;
+    const int tid = threadIdx.x, sw = tid / kSub, sl = tid % kSub;
+    X d1 = X(0), d2 = X(0);
+    for (int it = 0; it < kRowIters; ++it) {
+        const int64_t base = (blk * kRowIters + it) * kStep + sw;
+        if (base - sw >= nrows) break;  // uniform across the block
+        int32_t a[kRowU], b[kRowU], c[kRowU];
+        V v[kRowU];
+#pragma unroll
+        for (int u = 0; u < kRowU; ++u) {
+            const int64_t row = base + (int64_t)u * kSubs;
+            a[u] = 0;
+            b[u] = 0;
+            if (row < nrows) {
+                a[u] = rowptr[row];
+                b[u] = rowptr[row + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowU; ++u) {
+            const int32_t k = a[u] + sl;
+            c[u] = -1;
+            v[u] = V(0);
+            if (k < b[u]) {
+                c[u] = ld_stream(col + k);
+                v[u] = ld_stream(val + k);
+            }
+        }
+        X sum[kRowU];
+#pragma unroll
+        for (int u = 0; u < kRowU; ++u) sum[u] = c[u] >= 0 ? widen(v[u]) * x[c[u]] : X(0);
+#pragma unroll
+        for (int u = 0; u < kRowU; ++u)
+            for (int32_t k = a[u] + sl + kSub; k < b[u]; k += kSub)
+                sum[u] += widen(ld_stream(val + k)) * x[ld_stream(col + k)];
+#pragma unroll
+        for (int u = 0; u < kRowU; ++u) {
+            const X t = subwave_sum<kSub>(sum[u]);
+            const int64_t row = base + (int64_t)u * kSubs;
+            if (sl == 0 && row < nrows) {
+                X out = alpha * t;
+                if (beta != X(0)) out += beta * y[row];
+                y[row] = out;
+                if constexpr (kEpi >= 1) d1 += out * dot_with[row];
+                if constexpr (kEpi >= 2) d2 += out * out;
+            }
+        }
+    }
+    if constexpr (kEpi > 0) {
+        __shared__ X s_red[kRowThreads / kWave];
+        X vv[kEpi];
+        vv[0] = block_sum<X, kRowThreads>(d1, s_red);
+        if constexpr (kEpi >= 2) vv[kEpi - 1] = block_sum<X, kRowThreads>(d2, s_red);
+        write_partials<X, kEpi>(vv, dot_partials, nblocks, blk);
+    }
+}
+
 // One wavefront per tile boundary k in [0, ntiles]: the first row starting
 // at or after k*kCsrTile (nrows for the final boundary) and its offset.
 __global__ __launch_bounds__(256) void csr_partition_kernel(int32_t nrows, int64_t nnz, int64_t ntiles,
@@ -260,19 +354,63 @@ spx_status csr_partition_launch(const spx_matrix &A, int32_t *part, hipStream_t 
     return SPX_OK;
 }
 
+int csr_rows_sub(const spx_matrix &A)
+{
+    // measured on gfx950: the row-per-subwarp kernel wins only on small
+    // matrices (a few launches' worth of work, where the load-balanced
+    // kernel's staging and barriers dominate); the load-balanced kernel
+    // streams large banded matrices faster
+    if (A.nrows <= 0 || A.nrows > kRowMaxRows || A.max_row_len <= 0 || A.nnz <= 0) return 0;
+    const int64_t mean = ceil_div(A.nnz, A.nrows);
+    int sub = 4;
+    while (sub < 64 && sub < mean) sub <<= 1;
+    return A.max_row_len <= 2 * sub ? sub : 0;
+}
+
+int64_t csr_dot_parts(const spx_matrix &A)
+{
+    const int sub = csr_rows_sub(A);
+    if (sub == 0) return csr_tiles(A.nnz);
+    return ceil_div(A.nrows, (int64_t)(kRowThreads / sub) * kRowU * kRowIters);
+}
+
 template <typename V, typename X>
 spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, const X *dot_with,
                            X *dot_partials, hipStream_t stream, int epi, KState *st, int op, int ticket)
 {
+    const V *val = static_cast<const V *>(A.vals);
+    const int sub = csr_rows_sub(A);
+    if (sub > 0) {
+        const int64_t nblocks = csr_dot_parts(A);
+        const int64_t grid = pad_to_xcds(nblocks);
+#define SPX_ROWS_LAUNCH(E, SUB)                                                                                      \
+    csr_rows_kernel<V, X, E, SUB><<<(unsigned)grid, kRowThreads, 0, stream>>>(A.nrows, nblocks, grid, A.rowptr,         \
+                                                                               A.colidx, val, x, y, alpha, beta,       \
+                                                                               dot_with, dot_partials, st)
+#define SPX_ROWS_EPI(SUB)                                                                                            \
+    if (epi == 2) SPX_ROWS_LAUNCH(2, SUB);                                                                           \
+    else if (epi == 1) SPX_ROWS_LAUNCH(1, SUB);                                                                      \
+    else SPX_ROWS_LAUNCH(0, SUB);
+        switch (sub) {
+        case 4: SPX_ROWS_EPI(4) break;
+        case 8: SPX_ROWS_EPI(8) break;
+        case 16: SPX_ROWS_EPI(16) break;
+        case 32: SPX_ROWS_EPI(32) break;
+        default: SPX_ROWS_EPI(64) break;
+        }
+#undef SPX_ROWS_EPI
+#undef SPX_ROWS_LAUNCH
+        SPX_LAUNCHED();
+        return SPX_OK;
+    }
     const int64_t ntiles = csr_tiles(A.nnz);
     const int64_t grid = pad_to_xcds(ntiles);
-    const V *val = static_cast<const V *>(A.vals);
     // 16-byte value vectors (and matching column vectors) when both arrays
     // are 16-byte aligned, else one entry per load
     constexpr int kVec = 16 / (int)sizeof(V);
     const bool vec = ((reinterpret_cast<uintptr_t>(A.colidx) | reinterpret_cast<uintptr_t>(val)) & 15) == 0;
 #define SPX_CSR_LAUNCH(E, VEC)                                                                                   \
-    csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile, VEC><<<(unsigned)grid, kCsrThreads, 0, stream>>>(              \
+    csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile, VEC, kCsrLateGather><<<(unsigned)grid, kCsrThreads, 0, stream>>>( \
         A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials, A.csr_part, \
         st, op, ticket)
     if (vec) {

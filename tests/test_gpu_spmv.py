@@ -48,8 +48,12 @@ IDS = [m[0] for m in MATS]
 
 def _device_matrix(fmt, A, dtype, sv):
     dt = spx.DTYPE_NAMES[dtype]
-    if fmt == "csr":
+    if fmt == "csr":  # row-per-subwarp kernel where rows are short and even
         return spx.csr_from_host(A, dt)
+    if fmt == "csr_lb":  # no row-length hint: always the load-balanced kernel
+        M = spx.csr_from_host(A, dt)
+        M.max_row_len = 0
+        return M
     if fmt == "coo":
         return spx.coo_from_host(A.n, O.csr_to_coo_rows(A), A.col, A.val, dt)
     if fmt == "ell":
@@ -59,7 +63,7 @@ def _device_matrix(fmt, A, dtype, sv):
     return spx.hyb_from_host(A.n, H.ell.K, H.ell.ld, H.ell.col, H.ell.val, H.row, H.col, H.val, dt)
 
 
-@pytest.mark.parametrize("fmt", ["csr", "coo", "ell", "hyb"])
+@pytest.mark.parametrize("fmt", ["csr", "csr_lb", "coo", "ell", "hyb"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("mi", range(len(MATS)), ids=IDS)
 def test_spmv_parity(fmt, dtype, mi):
@@ -82,7 +86,7 @@ def test_spmv_parity(fmt, dtype, mi):
         assert_spmv_low(y, yref, absax, np.diff(A.rowptr))
 
 
-@pytest.mark.parametrize("fmt", ["csr", "coo", "ell", "hyb"])
+@pytest.mark.parametrize("fmt", ["csr", "csr_lb", "coo", "ell", "hyb"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_spmv_alpha_beta(fmt, dtype):
     A = S.random_small(700, 0.02, seed=6, empty_rows=(3, 4, 5, 699), long_rows=(100,))
@@ -110,16 +114,17 @@ def test_csr_analysed_partition(mi):
     name, make = MATS[mi]
     A = make()
     Ad = spx.csr_from_host(A, spx.F64)
+    Ad.max_row_len = 0  # the partition belongs to the load-balanced kernel
     x = S.uniform_vector(A.n, seed=4)
     xd = dev(x)
     y0 = host(spx.spmv(Ad, xd))
     spx.csr_analyse(Ad)
     part = host(Ad.csr_part)
-    # partition pins: tile k starts at the first row whose offset is >= 4096*k
-    ntiles = max(1, -(-A.nnz // 4096))
+    # partition pins: tile k starts at the first row whose offset is >= 2048*k
+    ntiles = max(1, -(-A.nnz // 2048))
     rp = A.rowptr.astype(np.int64)
     for k in range(ntiles + 1):
-        row = A.n if k == ntiles else int(np.searchsorted(rp, 4096 * k, side="left"))
+        row = A.n if k == ntiles else int(np.searchsorted(rp, 2048 * k, side="left"))
         assert part[2 * k] == row and part[2 * k + 1] == rp[row], k
     y1 = host(spx.spmv(Ad, xd))
     np.testing.assert_array_equal(y0.view(np.uint64), y1.view(np.uint64))
@@ -127,13 +132,28 @@ def test_csr_analysed_partition(mi):
     assert_spmv_f64(y1, yref, absax)
 
 
-def test_csr_bitwise_reproducible():
-    A = S.zipf_matrix(30000, seed=8)
+@pytest.mark.parametrize("make", [lambda: S.zipf_matrix(30000, seed=8), lambda: S.stencil27_random(40, seed=8)],
+                         ids=["zipf_load_balanced", "stencil27_rows"])
+def test_csr_bitwise_reproducible(make):
+    A = make()
     Ad = spx.csr_from_host(A, spx.F64)
     xd = dev(S.uniform_vector(A.n, seed=3))
     y1 = host(spx.spmv(Ad, xd, csr_only=True))
     y2 = host(spx.spmv(Ad, xd, csr_only=True))
     np.testing.assert_array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+def test_csr_row_hint_too_small_still_correct():
+    """max_row_len is only a hint: a wrong (too small) value selects the
+    row-per-subwarp kernel for rows longer than its first chunk, which must
+    still be exact to the tolerance."""
+    A = S.random_small(500, 0.05, seed=21, long_rows=(17, 300))
+    Ad = spx.csr_from_host(A, spx.F64)
+    Ad.max_row_len = 8
+    x = S.uniform_vector(A.n, seed=2)
+    y = host(spx.spmv(Ad, dev(x)))
+    yref, absax = O.csr_spmv_dot2(A, x)
+    assert_spmv_f64(y, yref, absax)
 
 
 def test_stencil_closed_form_on_gpu():
