@@ -22,7 +22,7 @@ inline int64_t vec_blocks(int64_t n) { return n > 0 ? ceil_div(n, kVecChunk) : 1
 inline int64_t spmv_dot_parts(const spx_matrix &A)
 {
     if (A.fmt == SPX_CSR) return csr_dot_parts(A);
-    if (A.fmt == SPX_SELLP) return A.nrows > 0 ? ceil_div(A.nrows, A.slice_size) : 1;
+    if (A.fmt == SPX_SELLP) return sellp_dot_parts(A);
     return vec_blocks(A.nrows);
 }
 inline int64_t partial_slots(const spx_matrix &A)

@@ -318,14 +318,96 @@ __global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows,
     }
 }
 
+// SELL-P with 64-row slices: one wavefront per slice, one lane per row, four
+// slot columns in flight per lane (the slot columns are read coalesced and,
+// on banded matrices, so are the gathers of x); no cross-lane reduction.
+template <typename V, typename X, int kEpi>
+__global__ __launch_bounds__(kSellThreads) void sellp64_spmv_kernel(int32_t nrows, int64_t nslices,
+                                                                   int64_t grid_padded,
+                                                                   const int32_t *__restrict__ sets,
+                                                                   const int32_t *__restrict__ scol,
+                                                                   const V *__restrict__ sval,
+                                                                   const X *__restrict__ x, X *__restrict__ y,
+                                                                   X alpha, X beta, const X *__restrict__ dot_with,
+                                                                   X *__restrict__ partials, const KState *st)
+{
+    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    constexpr int kSlices = kSellThreads / kWave;  // slices per work-group
+    const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
+    const int64_t nblocks = (nslices + kSlices - 1) / kSlices;
+    if (blk >= nblocks) return;
+    const int64_t s = blk * kSlices + threadIdx.x / kWave;
+    const int l = lane_id();
+    X d1 = X(0), d2 = X(0);
+    if (s < nslices) {
+        const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+        const int32_t *__restrict__ cs = scol + (int64_t)k0 * kWave + l;
+        const V *__restrict__ vs = sval + (int64_t)k0 * kWave + l;
+        X sum = X(0);
+        constexpr int U = 4;
+        int32_t k = 0;
+        for (; k + U <= w; k += U) {
+            int32_t cc[U];
+            X vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cc[u] = ld_stream(cs + (int64_t)(k + u) * kWave);
+                vv[u] = widen(ld_stream(vs + (int64_t)(k + u) * kWave));
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cc[u] >= 0) sum += vv[u] * x[cc[u]];
+        }
+        for (; k < w; ++k) {
+            const int32_t c = ld_stream(cs + (int64_t)k * kWave);
+            const X v = widen(ld_stream(vs + (int64_t)k * kWave));
+            if (c >= 0) sum += v * x[c];
+        }
+        const int64_t row = s * kWave + l;
+        if (row < nrows) {
+            const X out = alpha * sum + scaled(y[row], beta);
+            y[row] = out;
+            if constexpr (kEpi >= 1) d1 = out * dot_with[row];
+            if constexpr (kEpi >= 2) d2 = out * out;
+        }
+    }
+    if constexpr (kEpi > 0) {
+        __shared__ X s_red[kSellThreads / kWave];
+        X v[kEpi];
+        v[0] = block_sum<X, kSellThreads>(d1, s_red);
+        if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<X, kSellThreads>(d2, s_red);
+        write_partials<X, kEpi>(v, partials, nblocks, blk);
+    }
+}
+
+int64_t sellp_dot_parts(const spx_matrix &A)
+{
+    const int64_t ns = A.nrows > 0 ? ceil_div(A.nrows, A.slice_size) : 1;
+    return A.slice_size == kWave ? ceil_div(ns, kSellThreads / kWave) : ns;
+}
+
 template <typename V, typename X>
 spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream, int epi,
                              const X *dot_with, X *partials, const KState *st)
 {
     const int32_t C = A.slice_size;
+    const int64_t ns = ceil_div(A.nrows, C);
+    if (C == kWave) {
+        const int64_t nblocks = sellp_dot_parts(A);
+        const int64_t grid = pad_to_xcds(nblocks);
+#define SPX_SELL64_LAUNCH(E)                                                                                       \
+    sellp64_spmv_kernel<V, X, E><<<(unsigned)grid, kSellThreads, 0, stream>>>(                                     \
+        A.nrows, ns, grid, A.slice_sets, A.ell_col, static_cast<const V *>(A.ell_val), x, y, alpha, beta, dot_with, \
+        partials, st)
+        if (epi == 2) SPX_SELL64_LAUNCH(2);
+        else if (epi == 1) SPX_SELL64_LAUNCH(1);
+        else SPX_SELL64_LAUNCH(0);
+#undef SPX_SELL64_LAUNCH
+        SPX_LAUNCHED();
+        return SPX_OK;
+    }
     int32_t log2c = 0;
     while ((1 << log2c) < C) ++log2c;
-    const int64_t ns = ceil_div(A.nrows, C);
     const int64_t grid = pad_to_xcds(ns);
 #define SPX_SELL_LAUNCH(E)                                                                                         \
     sellp_spmv_kernel<V, X, E><<<(unsigned)grid, kSellThreads, 0, stream>>>(                                       \
