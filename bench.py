@@ -398,7 +398,8 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32):
     gen_s = time.time() - t0
     srv = spx.Server(max_slots=2048, hbm_budget_bytes=int(budget_gb * (1 << 30)))
 
-    def run(arrivals):
+    def run(arrivals, label):
+        print(f"serve {label}: submitting {nreq} requests", file=sys.stderr, flush=True)
         tickets, t_sched, t_sub = [], [], []
         start = time.perf_counter()
         for i, (kind, size) in enumerate(reqs):
@@ -410,9 +411,12 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32):
             tickets.append(srv.submit(A, b, tol=1e-8))
             t_sched.append(start + (arrivals[i] if arrivals is not None else 0.0))
         lat, iters, worst, last = [], [], 0.0, start
-        for t, ts, tu in zip(tickets, t_sched, t_sub):
+        for i, (t, ts, tu) in enumerate(zip(tickets, t_sched, t_sub)):
             x, info = srv.wait(t, timeout_s=900)
             assert info["status"] == 0, info
+            if (i + 1) % 500 == 0:
+                print(f"serve {label}: {i + 1}/{nreq} done, {time.perf_counter() - start:.1f} s", file=sys.stderr,
+                      flush=True)
             done = tu + info["device_ms"] * 1e-3
             last = max(last, done)
             lat.append(done - ts)
@@ -424,11 +428,12 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32):
                 "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
                 "mean_iters": round(float(np.mean(iters)), 1), "max_relres_true": worst}
 
-    burst = run(None)
+    print(f"serve: {len(mats)} distinct matrices built in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    burst = run(None, "burst")
     streams = {}
     for frac in (0.5, 0.7, 0.9):
         rate = frac * burst["solves_per_s"]
-        r = run(S.poisson_arrivals(nreq, rate, seed=seed))
+        r = run(S.poisson_arrivals(nreq, rate, seed=seed), f"{frac:.1f}x")
         r["rate_per_s"] = round(rate, 2)
         streams[f"{frac:.1f}x"] = r
     st = srv.stats()

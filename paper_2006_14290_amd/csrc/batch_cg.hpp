@@ -49,8 +49,10 @@ inline int32_t batch_sub_for(int64_t n, int64_t nnz)
 // blocks of all wide systems (vb_slot maps a virtual block to its system).
 // A system's partition, partial sums and their fixed summation order depend
 // only on its own n, so its iterates are bitwise the same alone or in any mix.
-constexpr int kWideThreads = 256;
-constexpr int kWideRows = 1024;
+constexpr int kWideThreads = 256;    // vector and commit phases
+constexpr int kWideAThreads = 1024;  // product phase
+constexpr int kWideRows = 1024;      // rows per virtual block
+constexpr int kWideU = 2;            // row groups in flight per subwave in the product
 
 enum WideMode : int32_t {
     kWideInit = 0,   // r = b (x0 = 0), p = r, bb = ||b||^2

@@ -23,6 +23,7 @@ namespace spx {
 constexpr int kWideWaves = kWideThreads / kWave;
 
 // Work-group sum in a fixed order (result in every thread).
+template <int kThreads = kWideThreads>
 __device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
 {
     v = wave_sum(v);
@@ -31,7 +32,7 @@ __device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWideWaves; ++w) t += s_red[w];
+    for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w];
     return t;
 }
 
@@ -44,37 +45,60 @@ __device__ __forceinline__ double wide_part_sum(const double *part, int32_t cnt,
     return wide_wg_sum(t, s_red);
 }
 
-// q[rows] = A v[rows]; returns the work-group sum of v_i q_i over the rows if dot.
+// q[rows] = A v[rows]; returns the work-group sum of v_i q_i over the rows if
+// dot. A subwave of `sub` lanes per row; each step covers kWideU row groups
+// whose first `sub` entries are all loaded before the first gather.
 __device__ __forceinline__ double wide_rows_spmv(const WideSlot &S, int32_t r0, int32_t r1, const double *__restrict__ v,
                                                  double *__restrict__ q, bool dot, double *s_red)
 {
     const int sub = S.sub;
     const int g = threadIdx.x / sub, sl = threadIdx.x % sub;
-    const int G = kWideThreads / sub;
+    const int G = kWideAThreads / sub;
     double acc = 0.0;
-    for (int32_t row0 = r0; row0 < r1; row0 += G) {  // uniform trip count: whole subwaves reduce together
-        const int32_t row = row0 + g;
-        double sum = 0.0;
-        if (row < r1) {
-            const int32_t a = S.rowptr[row], b = S.rowptr[row + 1];
-            for (int32_t k = a + sl; k < b; k += sub) sum += S.val[k] * v[S.col[k]];
+    for (int32_t row0 = r0; row0 < r1; row0 += G * kWideU) {  // uniform trip count: whole subwaves reduce together
+        int32_t a[kWideU], b[kWideU], c[kWideU];
+        double w[kWideU], sum[kWideU];
+#pragma unroll
+        for (int u = 0; u < kWideU; ++u) {
+            const int32_t row = row0 + u * G + g;
+            a[u] = 0;
+            b[u] = 0;
+            if (row < r1) {
+                a[u] = S.rowptr[row];
+                b[u] = S.rowptr[row + 1];
+            }
         }
-        sum = subwave_sum_dyn(sum, sub);
-        if (row < r1 && sl == 0) {
-            q[row] = sum;
-            if (dot) acc += sum * v[row];
+#pragma unroll
+        for (int u = 0; u < kWideU; ++u) {
+            const int32_t k = a[u] + sl;
+            c[u] = k < b[u] ? S.col[k] : -1;
+            w[u] = k < b[u] ? S.val[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kWideU; ++u) {
+            sum[u] = c[u] >= 0 ? w[u] * v[c[u]] : 0.0;
+            for (int32_t k = a[u] + sl + sub; k < b[u]; k += sub) sum[u] += S.val[k] * v[S.col[k]];
+        }
+#pragma unroll
+        for (int u = 0; u < kWideU; ++u) {
+            const double t = subwave_sum_dyn(sum[u], sub);
+            const int32_t row = row0 + u * G + g;
+            if (row < r1 && sl == 0) {
+                q[row] = t;
+                if (dot) acc += t * v[row];
+            }
         }
     }
-    return dot ? wide_wg_sum(acc, s_red) : 0.0;
+    return dot ? wide_wg_sum<kWideAThreads>(acc, s_red) : 0.0;
 }
 
-__global__ __launch_bounds__(kWideThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
-                                                              const WideState *__restrict__ st,
-                                                              const WideMap *__restrict__ map,
-                                                              const int32_t *__restrict__ vb_slot,
-                                                              const int32_t *__restrict__ vb_local)
+__global__ __launch_bounds__(kWideAThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
+                                                               const WideState *__restrict__ st,
+                                                               const WideMap *__restrict__ map,
+                                                               const int32_t *__restrict__ vb_slot,
+                                                               const int32_t *__restrict__ vb_local)
 {
-    __shared__ double s_red[kWideWaves];
+    __shared__ double s_red[kWideAThreads / kWave];
     const int32_t total = map->total_vb;
     for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
         const int32_t s = vb_slot[v], lv = vb_local[v];
@@ -256,7 +280,7 @@ spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const Wid
                                  const int32_t *vb_slot, const int32_t *vb_local, int grid, int commit_grid,
                                  hipStream_t stream)
 {
-    wide_a_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
+    wide_a_kernel<<<grid, kWideAThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
     SPX_LAUNCHED();
     wide_b_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
     SPX_LAUNCHED();
