@@ -42,6 +42,15 @@ inline int32_t batch_sub_for(int64_t n, int64_t nnz)
     return s;
 }
 
+// Lanes per row in the one-group kernel: batch_sub_for divided by
+// 2^kNarrowSubShift (more rows per pass, fewer dependent passes per product).
+constexpr int kNarrowSubShift = 3;
+inline int32_t narrow_sub_for(int64_t n, int64_t nnz)
+{
+    const int32_t s = batch_sub_for(n, nnz) >> kNarrowSubShift;
+    return s > 0 ? s : 1;
+}
+
 // ---------------------------------------------------------------- wide systems
 // Systems too large for one work-group are advanced together by a sequence of
 // grid-wide phases. Each wide system is cut into virtual blocks of kWideRows
@@ -87,6 +96,14 @@ struct WideMap {
 };
 
 inline int32_t wide_nvb(int64_t n) { return (int32_t)((n + kWideRows - 1) / kWideRows); }
+
+// Lanes per row in the wide product: batch_sub_for divided by 2^kWideSubShift.
+constexpr int kWideSubShift = 1;
+inline int32_t wide_sub_for(int64_t n, int64_t nnz)
+{
+    const int32_t s = batch_sub_for(n, nnz) >> kWideSubShift;
+    return s > 0 ? s : 1;
+}
 
 // One iteration (four launches: product, update, direction, commit) for all
 // listed wide systems. grid: physical blocks of the three vector phases.

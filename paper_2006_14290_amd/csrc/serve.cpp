@@ -288,7 +288,7 @@ int admit(spx_server &S)
             w.part = part;
             w.n = (int32_t)n;
             w.nvb = wide_nvb(n);
-            w.sub = batch_sub_for(n, nnz);
+            w.sub = wide_sub_for(n, nnz);
             w.maxit = p.req.maxit > 0 ? p.req.maxit : 100000;
             w.tol2 = p.req.tol * p.req.tol;
             WideState &ws = S.winit_host[si];
@@ -317,7 +317,7 @@ int admit(spx_server &S)
         d.p = pp;
         d.q = q;
         d.n = (int32_t)n;
-        d.sub = batch_sub_for(n, nnz);
+        d.sub = narrow_sub_for(n, nnz);
         d.status = kSlotRunning;
         d.started = 0;
         d.tol2 = p.req.tol * p.req.tol;
@@ -879,7 +879,7 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
             off += align256((size_t)wide_nvb(sys[i].n) * 16);
             w.n = sys[i].n;
             w.nvb = wide_nvb(sys[i].n);
-            w.sub = batch_sub_for(sys[i].n, sys[i].nnz);
+            w.sub = wide_sub_for(sys[i].n, sys[i].nnz);
             w.maxit = maxit;
             w.tol2 = sys[i].tol * sys[i].tol;
             const int32_t k = (int32_t)whost.size();
@@ -905,7 +905,7 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
             d.p = p;
             d.q = q;
             d.n = sys[i].n;
-            d.sub = batch_sub_for(sys[i].n, sys[i].nnz);
+            d.sub = narrow_sub_for(sys[i].n, sys[i].nnz);
             d.status = kSlotRunning;
             d.tol2 = sys[i].tol * sys[i].tol;
             d.maxit = maxit;
