@@ -460,6 +460,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=int, default=100, help="27-point grid edge (100 -> n = 1e6)")
+    ap.add_argument("--matrix", choices=("27pt", "zipf"), default="27pt",
+                    help="matrix of the headline CSR product (27-point stencil or the Zipf(1.5) rows)")
     ap.add_argument("--sweep", action="store_true", help="also time COO/ELL/HYB and float32/binary16 (27-point)")
     ap.add_argument("--zipf", action="store_true", help="also time every format on the Zipf(1.5) n=1e6 matrix")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -483,7 +485,12 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    A = S.stencil27_random(args.grid, seed=0)
+    if args.matrix == "zipf":
+        A = S.zipf_matrix(1_000_000, seed=0)
+        mdesc, mtag = f"Zipf(1.5) rows clipped to 10,000, n=1e6", "zipf"
+    else:
+        A = S.stencil27_random(args.grid, seed=0)
+        mdesc, mtag = f"27-point stencil {args.grid}^3", f"27pt{args.grid}"
     x_h = S.uniform_vector(A.n, seed=0)
     n, nnz = A.n, A.nnz
     gen_s = time.time() - t0
@@ -520,7 +527,6 @@ def main():
         results.update(format_sweep(spx, torch, dev, A, x_h, args, "27pt"))
         conversions = conversion_sweep(spx, torch, dev, A, "27pt")
     if args.zipf:
-        del A
         Z = S.zipf_matrix(1_000_000, seed=0)
         zx = S.uniform_vector(Z.n, seed=0)
         results.update(format_sweep(spx, torch, dev, Z, zx, args, "zipf"))
@@ -543,7 +549,7 @@ def main():
             reps += 1
         cs = (time.perf_counter() - t1) / reps
         cpu = {"value": b / cs / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} plain float64 CSR products of the full 27-point 100^3 matrix, "
+               "sample": f"{reps} plain float64 CSR products of the full {mdesc} matrix, "
                          f"{cs * 1e3:.1f} ms each, 1 thread"}
 
     r = results["csr_f64"]
@@ -560,7 +566,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"SpMV y=Ax, CSR float64, 27-point stencil {args.grid}^3 (n={n}, nnz={nnz}), "
+        "config": {"workload": f"SpMV y=Ax, CSR float64, {mdesc} (n={n}, nnz={nnz}), "
                                f"uniform[-1,1) values, {R} rotated copies"},
         "pct_hbm_peak": round(100 * r["GBs"] / HBM_PEAK_GBS, 2),
         "gflops": round(2 * nnz / r["ms"] / 1e6, 2),
@@ -579,7 +585,7 @@ def main():
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
     }
-    traffic = profile_traffic(f"csr_spmv_f64_27pt{args.grid}", b)
+    traffic = profile_traffic(f"csr_spmv_f64_{mtag}", b)
     if traffic is not None:
         line["roofline"]["traffic"] = traffic
         line["roofline"]["traffic_over_algorithmic"] = round(traffic / b, 4)

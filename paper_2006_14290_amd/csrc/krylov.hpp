@@ -49,7 +49,6 @@ struct KState {
     double tmp[4];
     int32_t flag, iters, maxit, spmv_count;
     int32_t restart_j, jend, pad0, pad1;
-    uint32_t ticket[8];
     double dots[2 * kMaxDots];  // GMRES multi-dot results
 };
 

@@ -233,10 +233,10 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
     auto iterations = [&]() -> spx_status {
         for (int it = 0; it < m; ++it) {
             bi_p_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.v, w.p, w.ph, w.dinv, w.st);
-            SPX_CHECK((spmv_dot<double, double>(A, w.ph, w.v, w.rh, w.partials, w.st, kOpBiAlpha, 0, s)));
+            SPX_CHECK((spmv_dot<double, double>(A, w.ph, w.v, w.rh, w.partials, w.st, kOpBiAlpha, s)));
             bi_s_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.v, w.s, w.sh, w.dinv, w.partials, w.st);
             SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpBiS, s));
-            SPX_CHECK((spmv_dot2<double, double>(A, w.sh, w.t, w.s, w.partials, w.st, kOpBiOmega, 2, s)));
+            SPX_CHECK((spmv_dot2<double, double>(A, w.sh, w.t, w.s, w.partials, w.st, kOpBiOmega, s)));
             bi_x_kernel<<<gv, kVecThreads, 0, s>>>(n, x, w.ph, w.sh, w.s, w.t, w.r, w.rh, w.partials, w.st);
             SPX_LAUNCHED();
             SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpBiRho, s));
@@ -261,7 +261,7 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
                 SPX_LAUNCHED();
             }
             SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
-            SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, 5, s));
+            SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, s));
             SPX_CHECK(read_state(env, w.st, &hs));
             have_true = true;
             true2 = hs.tmp[0];
@@ -294,7 +294,7 @@ spx_status bicgstab_run(const spx_matrix &A_in, const double *b, double *x, cons
     }
     if (!have_true && hs.bb > 0.0) {
         SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
-        SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, 5, s));
+        SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, s));
         KState h2;
         SPX_CHECK(read_state(env, w.st, &h2));
         true2 = h2.tmp[0];

@@ -2,12 +2,13 @@
 //
 // Textbook PCG (Hestenes & Stiefel 1952; the preconditioned form of Barrett
 // et al., "Templates", 1994) with a scalar Jacobi preconditioner, the solver
-// the paper benchmarks in Section 4. One iteration is three launches:
-//   1. q = A p fused with the partial sums of p.q (CSR epilogue), whose last
-//      tile computes alpha = rho / p.q;
-//   2. x += alpha p, r -= alpha q, z = D^{-1} r, partial sums of r.z and r.r;
-//      the last group forms beta and tests ||r|| <= tol ||b||;
-//   3. p = z + beta p.
+// the paper benchmarks in Section 4. One iteration is five launches:
+//   1. q = A p fused with the partial sums of p.q (CSR and SELL-P epilogue;
+//      a separate dot kernel for the other formats);
+//   2. a one-work-group finisher sums them in a fixed order: alpha = rho / p.q;
+//   3. x += alpha p, r -= alpha q, z = D^{-1} r, partial sums of r.z and r.r;
+//   4. a finisher forms beta and tests ||r|| <= tol ||b||;
+//   5. p = z + beta p.
 // Scalars never leave the device; a block of `check_every` iterations is
 // captured once into a hipGraph and replayed, and the host reads the state
 // only between replays. When the recursive residual passes, the true residual
@@ -230,7 +231,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
     const bool vec = (reinterpret_cast<uintptr_t>(x) % (kVecItems * sizeof(X))) == 0;
     auto iterations = [&]() -> spx_status {
         for (int it = 0; it < m; ++it) {
-            SPX_CHECK((spmv_dot<V, X>(A, w.p, w.q, w.p, w.partials, w.st, kOpCgAlpha, 0, s)));
+            SPX_CHECK((spmv_dot<V, X>(A, w.p, w.q, w.p, w.partials, w.st, kOpCgAlpha, s)));
             if (vec) {
                 cg_update_kernel<X, true><<<gv, kVecThreads, 0, s>>>(n, x, w.p, w.q, w.r, sp.precond ? w.z : nullptr,
                                                                     w.dinv, w.partials, w.st);
@@ -263,7 +264,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
                 break;
             }
             SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
-            SPX_CHECK(residual_norm<X>(n, b, w.q, w.r, w.partials, w.st, 3, s));
+            SPX_CHECK(residual_norm<X>(n, b, w.q, w.r, w.partials, w.st, s));
             SPX_CHECK(read_state(env, w.st, &hs));
             have_true = true;
             true2 = hs.tmp[0];
@@ -296,7 +297,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
     }
     if (!have_true && hs.bb > 0.0) {
         SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
-        SPX_CHECK(residual_norm<X>(n, b, w.q, w.r, w.partials, w.st, 3, s));
+        SPX_CHECK(residual_norm<X>(n, b, w.q, w.r, w.partials, w.st, s));
         KState h2;
         SPX_CHECK(read_state(env, w.st, &h2));
         true2 = h2.tmp[0];

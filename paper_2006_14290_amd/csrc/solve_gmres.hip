@@ -359,7 +359,7 @@ spx_status gmres_run(const spx_matrix &A_in, const double *b, double *x, const S
     while (true) {
         // true residual into v0
         SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
-        SPX_CHECK(residual_norm<double>(n, b, w.q, w.V, w.partials, w.st, 5, s));
+        SPX_CHECK(residual_norm<double>(n, b, w.q, w.V, w.partials, w.st, s));
         SPX_CHECK(read_state(env, w.st, &hs));
         true2 = hs.tmp[0];
         if (hs.flag == kZeroRhs) {

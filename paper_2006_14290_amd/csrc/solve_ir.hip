@@ -151,7 +151,7 @@ spx_status ir_run(const spx_matrix &A64_in, const spx_matrix &Alow_in, const dou
     SPX_LAUNCHED();
     // ||b||^2: the residual of x = 0 is b
     SPX_CHECK(spmv_dispatch(A64, x, w.q, 1.0, 0.0, s));
-    SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, 5, s));
+    SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, s));
     KState hs;
     SPX_CHECK(read_state(env, w.st, &hs));
     const double bb = hs.tmp[0];
@@ -196,7 +196,7 @@ spx_status ir_run(const spx_matrix &A64_in, const spx_matrix &Alow_in, const dou
         ir_update_kernel<<<ge, kVecThreads, 0, s>>>(n, x, w.d, w.amax);
         SPX_LAUNCHED();
         SPX_CHECK(spmv_dispatch(A64, x, w.q, 1.0, 0.0, s));
-        SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, 5, s));
+        SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, s));
         SPX_CHECK(read_state(env, w.st, &hs));
         info->spmv_count += 1;
         rn2 = hs.tmp[0];

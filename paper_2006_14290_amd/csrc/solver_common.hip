@@ -52,7 +52,6 @@ __global__ void state_init_kernel(KState *st, double tol, int32_t maxit)
         st->restart_j = 0;
         st->jend = 0;
     }
-    if (threadIdx.x < 8) st->ticket[threadIdx.x] = 0u;
 }
 
 spx_status state_init(KState *st, double tol, int32_t maxit, hipStream_t stream)
@@ -191,7 +190,7 @@ spx_status jacobi_setup(const spx_matrix &A, X *d, X *dinv, KState *st, hipStrea
 // ------------------------------------------------------------------ dots
 template <typename X>
 __global__ __launch_bounds__(kVecThreads) void dot_kernel(int64_t n, const X *__restrict__ a, const X *__restrict__ b,
-                                                         X *__restrict__ partials, KState *st, int op, int ticket)
+                                                         X *__restrict__ partials, KState *st, int op)
 {
     if (st->flag != kRunning) return;
     __shared__ X s_red[kVecThreads / kWave];
@@ -208,7 +207,7 @@ __global__ __launch_bounds__(kVecThreads) void dot_kernel(int64_t n, const X *__
 
 template <typename X>
 __global__ __launch_bounds__(kVecThreads) void dot2_kernel(int64_t n, const X *__restrict__ a, const X *__restrict__ w,
-                                                          X *__restrict__ partials, KState *st, int op, int ticket)
+                                                          X *__restrict__ partials, KState *st, int op)
 {
     if (st->flag != kRunning) return;
     __shared__ X s_red[kVecThreads / kWave];
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(kVecThreads) void dot2_kernel(int64_t n, const X *_
 template <typename X>
 __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, const X *__restrict__ b,
                                                               const X *__restrict__ q, X *__restrict__ r,
-                                                              X *__restrict__ partials, KState *st, int ticket)
+                                                              X *__restrict__ partials, KState *st)
 {
     __shared__ X s_red[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
@@ -248,11 +247,11 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, const 
 }
 
 template <typename V, typename X>
-spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partials, KState *st, int op, int ticket,
+spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partials, KState *st, int op,
                     hipStream_t stream)
 {
     if (A.fmt == SPX_CSR) {
-        SPX_CHECK((csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op, ticket)));
+        SPX_CHECK((csr_spmv_launch<V, X>(A, p, q, X(1), X(0), w, partials, stream, 1, st, op)));
         return launch_finish<X>(partials, csr_dot_parts(A), 1, st, op, stream);
     }
     if (A.fmt == SPX_SELLP) {
@@ -260,17 +259,17 @@ spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partia
         return launch_finish<X>(partials, spmv_dot_parts(A), 1, st, op, stream);
     }
     SPX_CHECK(spmv_dispatch(A, p, q, 1.0, 0.0, stream));
-    dot_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, w, q, partials, st, op, ticket);
+    dot_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, w, q, partials, st, op);
     SPX_LAUNCHED();
     return launch_finish<X>(partials, vec_blocks(A.nrows), 1, st, op, stream);
 }
 
 template <typename V, typename X>
-spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *partials, KState *st, int op, int ticket,
+spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *partials, KState *st, int op,
                      hipStream_t stream)
 {
     if (A.fmt == SPX_CSR) {
-        SPX_CHECK((csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op, ticket)));
+        SPX_CHECK((csr_spmv_launch<V, X>(A, sv, t, X(1), X(0), w, partials, stream, 2, st, op)));
         return launch_finish<X>(partials, csr_dot_parts(A), 2, st, op, stream);
     }
     if (A.fmt == SPX_SELLP) {
@@ -278,16 +277,16 @@ spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *part
         return launch_finish<X>(partials, spmv_dot_parts(A), 2, st, op, stream);
     }
     SPX_CHECK(spmv_dispatch(A, sv, t, 1.0, 0.0, stream));
-    dot2_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, t, w, partials, st, op, ticket);
+    dot2_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, t, w, partials, st, op);
     SPX_LAUNCHED();
     return launch_finish<X>(partials, vec_blocks(A.nrows), 2, st, op, stream);
 }
 
 template <typename X>
-spx_status residual_norm(int64_t n, const X *b, const X *q, X *r, X *partials, KState *st, int ticket,
+spx_status residual_norm(int64_t n, const X *b, const X *q, X *r, X *partials, KState *st,
                          hipStream_t stream)
 {
-    residual_kernel<X><<<(unsigned)vec_blocks(n), kVecThreads, 0, stream>>>(n, b, q, r, partials, st, ticket);
+    residual_kernel<X><<<(unsigned)vec_blocks(n), kVecThreads, 0, stream>>>(n, b, q, r, partials, st);
     SPX_LAUNCHED();
     return launch_finish<X>(partials, vec_blocks(n), 1, st, kOpNorm2, stream);
 }
@@ -296,16 +295,16 @@ template spx_status jacobi_setup<double, double>(const spx_matrix &, double *, d
 template spx_status jacobi_setup<float, float>(const spx_matrix &, float *, float *, KState *, hipStream_t);
 template spx_status jacobi_setup<_Float16, float>(const spx_matrix &, float *, float *, KState *, hipStream_t);
 template spx_status spmv_dot<double, double>(const spx_matrix &, const double *, double *, const double *, double *,
-                                             KState *, int, int, hipStream_t);
+                                             KState *, int, hipStream_t);
 template spx_status spmv_dot<float, float>(const spx_matrix &, const float *, float *, const float *, float *, KState *,
-                                           int, int, hipStream_t);
+                                           int, hipStream_t);
 template spx_status spmv_dot<_Float16, float>(const spx_matrix &, const float *, float *, const float *, float *,
-                                              KState *, int, int, hipStream_t);
+                                              KState *, int, hipStream_t);
 template spx_status spmv_dot2<double, double>(const spx_matrix &, const double *, double *, const double *, double *,
-                                              KState *, int, int, hipStream_t);
-template spx_status residual_norm<double>(int64_t, const double *, const double *, double *, double *, KState *, int,
+                                              KState *, int, hipStream_t);
+template spx_status residual_norm<double>(int64_t, const double *, const double *, double *, double *, KState *,
                                           hipStream_t);
-template spx_status residual_norm<float>(int64_t, const float *, const float *, float *, float *, KState *, int,
+template spx_status residual_norm<float>(int64_t, const float *, const float *, float *, float *, KState *,
                                          hipStream_t);
 
 }  // namespace spx

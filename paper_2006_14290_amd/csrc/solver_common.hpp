@@ -119,17 +119,17 @@ inline spx_status status_of_flag(int32_t flag)
 // Generic product q = A p (any format) plus the deterministic sum w.q
 // finished by `op`; CSR fuses the sum into the product's epilogue.
 template <typename V, typename X>
-spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partials, KState *st, int op, int ticket,
+spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partials, KState *st, int op,
                     hipStream_t stream);
 
 // t = A s plus the two sums t.s and t.t finished by `op` (CSR: fused epilogue).
 template <typename V, typename X>
-spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *partials, KState *st, int op, int ticket,
+spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *partials, KState *st, int op,
                      hipStream_t stream);
 
 // r = b - q (q = A x) with ||r||^2 finished into st->tmp[0] (kOpNorm2).
 template <typename X>
-spx_status residual_norm(int64_t n, const X *b, const X *q, X *r, X *partials, KState *st, int ticket,
+spx_status residual_norm(int64_t n, const X *b, const X *q, X *r, X *partials, KState *st,
                          hipStream_t stream);
 
 }  // namespace spx

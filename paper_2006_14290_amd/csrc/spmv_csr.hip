@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     int32_t nrows, int64_t nnz, int64_t ntiles, int64_t grid_padded, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y,
     X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, const int32_t *__restrict__ part,
-    KState *__restrict__ st, int op, int ticket)
+    KState *__restrict__ st, int op)
 {
     if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
     using A = X;  // accumulation type
@@ -376,7 +376,7 @@ int64_t csr_dot_parts(const spx_matrix &A)
 
 template <typename V, typename X>
 spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, const X *dot_with,
-                           X *dot_partials, hipStream_t stream, int epi, KState *st, int op, int ticket)
+                           X *dot_partials, hipStream_t stream, int epi, KState *st, int op)
 {
     const V *val = static_cast<const V *>(A.vals);
     const int sub = csr_rows_sub(A);
@@ -412,7 +412,7 @@ spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
 #define SPX_CSR_LAUNCH(E, VEC)                                                                                   \
     csr_spmv_kernel<V, X, E, kCsrThreads, kCsrTile, VEC, kCsrLateGather><<<(unsigned)grid, kCsrThreads, 0, stream>>>( \
         A.nrows, A.nnz, ntiles, grid, A.rowptr, A.colidx, val, x, y, alpha, beta, dot_with, dot_partials, A.csr_part, \
-        st, op, ticket)
+        st, op)
     if (vec) {
         if (epi == 2) SPX_CSR_LAUNCH(2, kVec);
         else if (epi == 1) SPX_CSR_LAUNCH(1, kVec);
@@ -428,10 +428,10 @@ spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
 }
 
 template spx_status csr_spmv_launch<double, double>(const spx_matrix &, const double *, double *, double, double,
-                                                    const double *, double *, hipStream_t, int, KState *, int, int);
+                                                    const double *, double *, hipStream_t, int, KState *, int);
 template spx_status csr_spmv_launch<float, float>(const spx_matrix &, const float *, float *, float, float,
-                                                  const float *, float *, hipStream_t, int, KState *, int, int);
+                                                  const float *, float *, hipStream_t, int, KState *, int);
 template spx_status csr_spmv_launch<_Float16, float>(const spx_matrix &, const float *, float *, float, float,
-                                                     const float *, float *, hipStream_t, int, KState *, int, int);
+                                                     const float *, float *, hipStream_t, int, KState *, int);
 
 }  // namespace spx

@@ -36,7 +36,6 @@ inline int64_t csr_partition_bytes(int64_t nnz) { return 2 * (csr_tiles(nnz) + 1
 
 template <typename V, typename X>
 spx_status csr_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, const X *dot_with,
-                           X *dot_partials, hipStream_t stream, int epi = 0, KState *st = nullptr, int op = 0,
-                           int ticket = 0);
+                           X *dot_partials, hipStream_t stream, int epi = 0, KState *st = nullptr, int op = 0);
 
 }  // namespace spx
