@@ -58,10 +58,8 @@ inline int32_t narrow_sub_for(int64_t n, int64_t nnz)
 // blocks of all wide systems (vb_slot maps a virtual block to its system).
 // A system's partition, partial sums and their fixed summation order depend
 // only on its own n, so its iterates are bitwise the same alone or in any mix.
-constexpr int kWideThreads = 256;    // vector and commit phases
-constexpr int kWideAThreads = 1024;  // product phase
-constexpr int kWideRows = 1024;      // rows per virtual block
-constexpr int kWideU = 2;            // row groups in flight per subwave in the product
+constexpr int kWideThreads = 256;  // vector and commit phases
+constexpr int kWideRows = 1024;    // rows per virtual block of the vector phases
 
 enum WideMode : int32_t {
     kWideInit = 0,   // r = b (x0 = 0), p = r, bb = ||b||^2
@@ -70,15 +68,21 @@ enum WideMode : int32_t {
     kWideDone = 3,
 };
 
-// Written by the host when the system is admitted.
+// Written by the host when the system is admitted. The product phase runs
+// the load-balanced CSR tile kernel over the system's ntiles tiles (its
+// partition in csr_part), one partial p.q per tile in part_a; the vector
+// phases work on nvb blocks of kWideRows rows, one partial each in part.
 struct WideSlot {
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
     const double *b;
     double *x, *r, *p, *q;
-    double *part;  // 2 * nvb partial sums
-    int32_t n, nvb, sub, maxit;
+    double *part;             // nvb partial sums of the vector phase
+    double *part_a;           // ntiles partial sums of the product phase
+    const int32_t *csr_part;  // tile partition of the product
+    int64_t nnz;
+    int32_t n, nvb, ntiles, maxit;
     double tol2;
 };
 
@@ -88,28 +92,25 @@ struct WideState {
     double rho, bb, rr, relres_true;
 };
 
-// Header of the virtual-block map, device memory: {total virtual blocks,
-// number of listed systems}; list[] holds the slot index of each listed system.
+// Header of the virtual-block maps, device memory: {total virtual row blocks,
+// number of listed systems, total product tiles}; list[] holds the slot
+// index of each listed system.
 struct WideMap {
     int32_t total_vb;
     int32_t nlisted;
+    int32_t total_ta;
+    int32_t pad;
 };
 
 inline int32_t wide_nvb(int64_t n) { return (int32_t)((n + kWideRows - 1) / kWideRows); }
 
-// Lanes per row in the wide product: batch_sub_for divided by 2^kWideSubShift.
-constexpr int kWideSubShift = 1;
-inline int32_t wide_sub_for(int64_t n, int64_t nnz)
-{
-    const int32_t s = batch_sub_for(n, nnz) >> kWideSubShift;
-    return s > 0 ? s : 1;
-}
-
 // One iteration (four launches: product, update, direction, commit) for all
-// listed wide systems. grid: physical blocks of the three vector phases.
+// listed wide systems. grid: physical blocks of the product and vector
+// phases. ta_slot / ta_local map product tiles, vb_slot / vb_local vector
+// blocks to (system, local index).
 spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
-                                 const int32_t *vb_slot, const int32_t *vb_local, int grid, int commit_grid,
-                                 hipStream_t stream);
+                                 const int32_t *vb_slot, const int32_t *vb_local, const int32_t *ta_slot,
+                                 const int32_t *ta_local, int grid, int commit_grid, hipStream_t stream);
 
 // Advance slots[0..nslots) by at most slot.budget CG iterations each (or to
 // convergence); work-groups take slots from *counter, which must be 0 at

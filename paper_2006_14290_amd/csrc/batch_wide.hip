@@ -4,7 +4,8 @@
 // Unpreconditioned CG (Hestenes & Stiefel), x0 = 0, one iteration as four
 // grid-wide phases over every listed system (a launch boundary is the only
 // global synchronisation):
-//   A  q = A p (or q = A x in the true-residual mode), partial sums of p.q;
+//   A  q = A p (or q = A x in the true-residual mode), partial sums of p.q:
+//      the load-balanced CSR tile kernel over every listed system's tiles;
 //   B  alpha = rho / p.q from the partials; x += alpha p, r -= alpha q,
 //      partial sums of r.r (true-residual mode: r = b - q; init: r = b);
 //   C  beta = r.r / rho from the partials; p = r + beta p (or p = r on a
@@ -16,6 +17,8 @@
 // blocks, partials and summation order depend only on its own size; its
 // arithmetic is therefore independent of the other systems in the launch.
 #include "batch_cg.hpp"
+#include "spmv_csr.hpp"
+#include "spmv_csr_tile.hpp"
 #include "wave.hpp"
 
 namespace spx {
@@ -23,7 +26,6 @@ namespace spx {
 constexpr int kWideWaves = kWideThreads / kWave;
 
 // Work-group sum in a fixed order (result in every thread).
-template <int kThreads = kWideThreads>
 __device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
 {
     v = wave_sum(v);
@@ -32,7 +34,7 @@ __device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w];
+    for (int w = 0; w < kWideWaves; ++w) t += s_red[w];
     return t;
 }
 
@@ -45,73 +47,24 @@ __device__ __forceinline__ double wide_part_sum(const double *part, int32_t cnt,
     return wide_wg_sum(t, s_red);
 }
 
-// q[rows] = A v[rows]; returns the work-group sum of v_i q_i over the rows if
-// dot. A subwave of `sub` lanes per row; each step covers kWideU row groups
-// whose first `sub` entries are all loaded before the first gather.
-__device__ __forceinline__ double wide_rows_spmv(const WideSlot &S, int32_t r0, int32_t r1, const double *__restrict__ v,
-                                                 double *__restrict__ q, bool dot, double *s_red)
+// Product phase: one work-group per virtual tile (system, tile). The tile
+// kernel runs with its p.q epilogue in both modes (the true-residual mode
+// multiplies x and ignores the partial).
+__global__ __launch_bounds__(kCsrThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
+                                                             const WideState *__restrict__ st,
+                                                             const WideMap *__restrict__ map,
+                                                             const int32_t *__restrict__ ta_slot,
+                                                             const int32_t *__restrict__ ta_local)
 {
-    const int sub = S.sub;
-    const int g = threadIdx.x / sub, sl = threadIdx.x % sub;
-    const int G = kWideAThreads / sub;
-    double acc = 0.0;
-    for (int32_t row0 = r0; row0 < r1; row0 += G * kWideU) {  // uniform trip count: whole subwaves reduce together
-        int32_t a[kWideU], b[kWideU], c[kWideU];
-        double w[kWideU], sum[kWideU];
-#pragma unroll
-        for (int u = 0; u < kWideU; ++u) {
-            const int32_t row = row0 + u * G + g;
-            a[u] = 0;
-            b[u] = 0;
-            if (row < r1) {
-                a[u] = S.rowptr[row];
-                b[u] = S.rowptr[row + 1];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kWideU; ++u) {
-            const int32_t k = a[u] + sl;
-            c[u] = k < b[u] ? S.col[k] : -1;
-            w[u] = k < b[u] ? S.val[k] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kWideU; ++u) {
-            sum[u] = c[u] >= 0 ? w[u] * v[c[u]] : 0.0;
-            for (int32_t k = a[u] + sl + sub; k < b[u]; k += sub) sum[u] += S.val[k] * v[S.col[k]];
-        }
-#pragma unroll
-        for (int u = 0; u < kWideU; ++u) {
-            const double t = subwave_sum_dyn(sum[u], sub);
-            const int32_t row = row0 + u * G + g;
-            if (row < r1 && sl == 0) {
-                q[row] = t;
-                if (dot) acc += t * v[row];
-            }
-        }
-    }
-    return dot ? wide_wg_sum<kWideAThreads>(acc, s_red) : 0.0;
-}
-
-__global__ __launch_bounds__(kWideAThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
-                                                               const WideState *__restrict__ st,
-                                                               const WideMap *__restrict__ map,
-                                                               const int32_t *__restrict__ vb_slot,
-                                                               const int32_t *__restrict__ vb_local)
-{
-    __shared__ double s_red[kWideAThreads / kWave];
-    const int32_t total = map->total_vb;
+    const int32_t total = map->total_ta;
     for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
-        const int32_t s = vb_slot[v], lv = vb_local[v];
+        const int32_t s = ta_slot[v], k = ta_local[v];
         const int32_t mode = st[s].mode;
         if (mode != kWideRun && mode != kWideCheck) continue;
         const WideSlot S = slots[s];
-        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
-        if (mode == kWideRun) {
-            const double pq = wide_rows_spmv(S, r0, r1, S.p, S.q, true, s_red);
-            if (threadIdx.x == 0) S.part[lv] = pq;
-        } else {
-            wide_rows_spmv(S, r0, r1, S.x, S.q, false, s_red);
-        }
+        const double *src = mode == kWideRun ? S.p : S.x;
+        csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
+            k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, S.q, 1.0, 0.0, src, S.part_a, S.csr_part);
     }
 }
 
@@ -131,7 +84,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_b_kernel(const WideSlot *__
         const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
         double t = 0.0;
         if (mode == kWideRun) {
-            const double pq = wide_part_sum(S.part, S.nvb, s_red);
+            const double pq = wide_part_sum(S.part_a, S.ntiles, s_red);
             if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;  // the commit phase records the breakdown
             const double alpha = st[s].rho / pq;
             for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
@@ -154,7 +107,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_b_kernel(const WideSlot *__
             }
         }
         t = wide_wg_sum(t, s_red);
-        if (threadIdx.x == 0) S.part[S.nvb + lv] = t;
+        if (threadIdx.x == 0) S.part[lv] = t;
     }
 }
 
@@ -174,14 +127,14 @@ __global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__
         const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
         const double bb = st[s].bb;
         if (mode == kWideRun) {
-            const double pq = wide_part_sum(S.part, S.nvb, s_red);
+            const double pq = wide_part_sum(S.part_a, S.ntiles, s_red);
             if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;
-            const double rr = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+            const double rr = wide_part_sum(S.part, S.nvb, s_red);
             if (!__builtin_isfinite(rr) || rr <= S.tol2 * bb) continue;  // stop or check next
             const double beta = rr / st[s].rho;
             for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i] + beta * S.p[i];
         } else if (mode == kWideCheck) {
-            const double tr = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+            const double tr = wide_part_sum(S.part, S.nvb, s_red);
             if (tr <= S.tol2 * bb) continue;
             for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];  // restart
         } else {
@@ -267,8 +220,8 @@ __global__ __launch_bounds__(kWideThreads) void wide_d_kernel(const WideSlot *__
         WideState W = st[s];
         if (W.mode == kWideDone) continue;
         const WideSlot S = slots[s];
-        const double s1 = wide_part_sum(S.part, S.nvb, s_red);
-        const double s2 = wide_part_sum(S.part + S.nvb, S.nvb, s_red);
+        const double s1 = wide_part_sum(S.part_a, S.ntiles, s_red);
+        const double s2 = wide_part_sum(S.part, S.nvb, s_red);
         if (threadIdx.x == 0) {
             commit(W, S, s1, s2);
             st[s] = W;
@@ -277,10 +230,10 @@ __global__ __launch_bounds__(kWideThreads) void wide_d_kernel(const WideSlot *__
 }
 
 spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
-                                 const int32_t *vb_slot, const int32_t *vb_local, int grid, int commit_grid,
-                                 hipStream_t stream)
+                                 const int32_t *vb_slot, const int32_t *vb_local, const int32_t *ta_slot,
+                                 const int32_t *ta_local, int grid, int commit_grid, hipStream_t stream)
 {
-    wide_a_kernel<<<grid, kWideAThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
+    wide_a_kernel<<<grid, kCsrThreads, 0, stream>>>(slots, st, map, ta_slot, ta_local);
     SPX_LAUNCHED();
     wide_b_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
     SPX_LAUNCHED();

@@ -32,6 +32,7 @@
 
 #include "batch_cg.hpp"
 #include "common.hpp"
+#include "spmv_csr.hpp"
 
 using namespace spx;
 using Clock = std::chrono::steady_clock;
@@ -47,12 +48,20 @@ constexpr int kWideGrids[3] = {256, 1024, 4096};  // physical grids of the wide 
 constexpr int kWideCommitGrid = 128;
 constexpr int32_t kWideDefaultRows = 16384;
 
-// Device bytes of one system: CSR arrays + b, x, r, p, q (+ the partial sums
-// of the wide path).
+// Extra device bytes of a wide system: vector-phase partials, product
+// partials and the product's tile partition.
+size_t wide_extra_bytes(int64_t n, int64_t nnz)
+{
+    return align256((size_t)wide_nvb(n) * 8) + align256((size_t)csr_tiles(nnz) * 8) +
+           align256((size_t)csr_partition_bytes(nnz));
+}
+
+// Device bytes of one system: CSR arrays + b, x, r, p, q (+ the partials and
+// partition of the wide path).
 size_t system_bytes(int64_t n, int64_t nnz, bool wide)
 {
     return align256((size_t)(n + 1) * 4) + align256((size_t)nnz * 4) + align256((size_t)nnz * 8) +
-           5 * align256((size_t)n * 8) + (wide ? align256((size_t)wide_nvb(n) * 16) : 0);
+           5 * align256((size_t)n * 8) + (wide ? wide_extra_bytes(n, nnz) : 0);
 }
 
 bool is_wide(int32_t wide_min_rows, int64_t n)
@@ -166,6 +175,8 @@ struct spx_server {
     int32_t *wlist_dev = nullptr, *wlist_host = nullptr;
     int32_t *vb_dev = nullptr, *vb_host = nullptr;  // [2 * vb_cap]: slot, then local index
     int64_t vb_cap = 0;
+    int32_t *ta_dev = nullptr, *ta_host = nullptr;  // [2 * ta_cap]: product tiles, same layout
+    int64_t ta_cap = 0;
     std::vector<WideSlot> wstaged;
     hipGraphExec_t wide_tick[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
@@ -264,7 +275,9 @@ int admit(spx_server &S)
         double *r = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *pp = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *q = reinterpret_cast<double *>(carve((size_t)n * 8));
-        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 16)) : nullptr;
+        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 8)) : nullptr;
+        double *part_a = p.wide ? reinterpret_cast<double *>(carve((size_t)csr_tiles(nnz) * 8)) : nullptr;
+        int32_t *cpart = p.wide ? reinterpret_cast<int32_t *>(carve((size_t)csr_partition_bytes(nnz))) : nullptr;
         (void)hipMemcpyAsync(rp, p.req.rowptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, S.s_copy);
         if (nnz > 0) {
             (void)hipMemcpyAsync(ci, p.req.colidx, (size_t)nnz * 4, hipMemcpyHostToDevice, S.s_copy);
@@ -286,9 +299,21 @@ int admit(spx_server &S)
             w.p = pp;
             w.q = q;
             w.part = part;
+            w.part_a = part_a;
+            w.csr_part = cpart;
+            w.nnz = nnz;
+            w.ntiles = (int32_t)csr_tiles(nnz);
             w.n = (int32_t)n;
             w.nvb = wide_nvb(n);
-            w.sub = wide_sub_for(n, nnz);
+            {
+                spx_matrix d{};
+                d.fmt = SPX_CSR;
+                d.nrows = (int32_t)n;
+                d.ncols = (int32_t)n;
+                d.nnz = nnz;
+                d.rowptr = rp;
+                (void)csr_partition_launch(d, cpart, S.s_copy);  // after the row pointer copy (same stream)
+            }
             w.maxit = p.req.maxit > 0 ? p.req.maxit : 100000;
             w.tol2 = p.req.tol * p.req.tol;
             WideState &ws = S.winit_host[si];
@@ -358,23 +383,29 @@ void apply_staged(spx_server &S)
 bool rebuild_wide_map(spx_server &S)
 {
     int32_t nl = 0;
-    int64_t tot = 0;
+    int64_t tot = 0, tta = 0;
     for (int i = 0; i < (int)S.active.size(); ++i) {
         Active &a = S.active[i];
         a.in_map = false;
         if (!a.live || !a.wide || a.staged || a.cancel) continue;
-        const int32_t nvb = S.wslots_host[i].nvb;
-        if (tot + nvb > S.vb_cap) return false;
+        const int32_t nvb = S.wslots_host[i].nvb, nt = S.wslots_host[i].ntiles;
+        if (tot + nvb > S.vb_cap || tta + nt > S.ta_cap) return false;
         S.wlist_host[nl++] = i;
         for (int32_t k = 0; k < nvb; ++k) {
             S.vb_host[tot + k] = i;
             S.vb_host[S.vb_cap + tot + k] = k;
         }
+        for (int32_t k = 0; k < nt; ++k) {
+            S.ta_host[tta + k] = i;
+            S.ta_host[S.ta_cap + tta + k] = k;
+        }
         tot += nvb;
+        tta += nt;
         a.in_map = true;
     }
     S.wmap_host->total_vb = (int32_t)tot;
     S.wmap_host->nlisted = nl;
+    S.wmap_host->total_ta = (int32_t)tta;
     const size_t tb = sizeof(WideSlot) * S.active.size();
     hipError_t e = hipMemcpyAsync(S.wslots_dev, S.wslots_host, tb, hipMemcpyHostToDevice, S.s_wide);
     if (e == hipSuccess) e = hipMemcpyAsync(S.wmap_dev, S.wmap_host, sizeof(WideMap), hipMemcpyHostToDevice, S.s_wide);
@@ -384,6 +415,12 @@ bool rebuild_wide_map(spx_server &S)
         e = hipMemcpyAsync(S.vb_dev, S.vb_host, sizeof(int32_t) * tot, hipMemcpyHostToDevice, S.s_wide);
         if (e == hipSuccess)
             e = hipMemcpyAsync(S.vb_dev + S.vb_cap, S.vb_host + S.vb_cap, sizeof(int32_t) * tot,
+                               hipMemcpyHostToDevice, S.s_wide);
+    }
+    if (e == hipSuccess && tta > 0) {
+        e = hipMemcpyAsync(S.ta_dev, S.ta_host, sizeof(int32_t) * tta, hipMemcpyHostToDevice, S.s_wide);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.ta_dev + S.ta_cap, S.ta_host + S.ta_cap, sizeof(int32_t) * tta,
                                hipMemcpyHostToDevice, S.s_wide);
     }
     S.wide_dirty = false;
@@ -474,7 +511,7 @@ void worker_main(spx_server *Sp)
             if (e == hipSuccess) e = hipMemcpyAsync(S.slots_host, S.slots_dev, tb, hipMemcpyDeviceToHost, S.s_compute);
         }
         if (nwide > 0 && e == hipSuccess) {
-            const int32_t tot = S.wmap_host->total_vb;
+            const int32_t tot = std::max(S.wmap_host->total_vb, S.wmap_host->total_ta);
             const int gi = tot <= kWideGrids[0] ? 0 : (tot <= kWideGrids[1] ? 1 : 2);
             e = hipEventRecord(S.ev_w0, S.s_wide);
             for (int l = 0; l < S.wide_launches && e == hipSuccess; ++l) e = hipGraphLaunch(S.wide_tick[gi], S.s_wide);
@@ -536,10 +573,11 @@ void server_free(spx_server *S)
     if (S->ev_w0) (void)hipEventDestroy(S->ev_w0);
     if (S->ev_w1) (void)hipEventDestroy(S->ev_w1);
     for (void *p : {(void *)S->pool_base, (void *)S->slots_dev, (void *)S->counter, (void *)S->wslots_dev,
-                    (void *)S->wstate_dev, (void *)S->wmap_dev, (void *)S->wlist_dev, (void *)S->vb_dev})
+                    (void *)S->wstate_dev, (void *)S->wmap_dev, (void *)S->wlist_dev, (void *)S->vb_dev,
+                    (void *)S->ta_dev})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)S->slots_host, (void *)S->wslots_host, (void *)S->wstate_host, (void *)S->winit_host,
-                    (void *)S->wmap_host, (void *)S->wlist_host, (void *)S->vb_host})
+                    (void *)S->wmap_host, (void *)S->wlist_host, (void *)S->vb_host, (void *)S->ta_host})
         if (p) (void)hipHostFree(p);
     if (S->s_compute) (void)hipStreamDestroy(S->s_compute);
     if (S->s_copy) (void)hipStreamDestroy(S->s_copy);
@@ -590,6 +628,9 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     const size_t ms = (size_t)cfg->max_slots;
     // every wide row costs at least 44 pool bytes (row pointer + five vectors)
     S->vb_cap = (int64_t)(cfg->hbm_budget_bytes / (44 * (size_t)kWideRows)) + (int64_t)ms + 1;
+    // every stored nonzero costs 12 pool bytes and a system has at most
+    // nnz / kCsrTile + 1 tiles
+    S->ta_cap = (int64_t)(cfg->hbm_budget_bytes / (12 * (size_t)kCsrTile)) + (int64_t)ms + 1;
     hipError_t e;
     auto fail = [&](const char *what) {
         set_error("spx_server_create: %s: %s", what, hipGetErrorString(e));
@@ -611,7 +652,9 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
         (e = dev_alloc(&S->wmap_dev, 1)) != hipSuccess || (e = host_alloc(&S->wmap_host, 1)) != hipSuccess ||
         (e = dev_alloc(&S->wlist_dev, ms)) != hipSuccess || (e = host_alloc(&S->wlist_host, ms)) != hipSuccess ||
         (e = dev_alloc(&S->vb_dev, 2 * (size_t)S->vb_cap)) != hipSuccess ||
-        (e = host_alloc(&S->vb_host, 2 * (size_t)S->vb_cap)) != hipSuccess)
+        (e = host_alloc(&S->vb_host, 2 * (size_t)S->vb_cap)) != hipSuccess ||
+        (e = dev_alloc(&S->ta_dev, 2 * (size_t)S->ta_cap)) != hipSuccess ||
+        (e = host_alloc(&S->ta_host, 2 * (size_t)S->ta_cap)) != hipSuccess)
         return fail("tables");
     for (size_t i = 0; i < ms; ++i) {
         S->slots_host[i].status = kSlotEmpty;
@@ -640,7 +683,8 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
             [&](hipStream_t st) {
                 for (int it = 0; it < kWideIters; ++it) {
                     spx_status s1 = wide_iteration_launch(S->wslots_dev, S->wstate_dev, S->wmap_dev, S->wlist_dev,
-                                                          S->vb_dev, S->vb_dev + S->vb_cap, kWideGrids[gi],
+                                                          S->vb_dev, S->vb_dev + S->vb_cap, S->ta_dev,
+                                                          S->ta_dev + S->ta_cap, kWideGrids[gi],
                                                           kWideCommitGrid, st);
                     if (s1 != SPX_OK) return s1;
                 }
@@ -780,8 +824,8 @@ bool batch_is_wide(const spx_batch_system &s)
 // Workspace: narrow slot table, counter, wide tables, then per system r, p, q
 // (+ 2 * nvb partial sums for wide systems).
 struct BatchLayout {
-    size_t slots, counter, wslots, wstate, wmap, wlist, vb, vectors, total;
-    int64_t nwide, total_vb;
+    size_t slots, counter, wslots, wstate, wmap, wlist, vb, ta, vectors, total;
+    int64_t nwide, total_vb, total_ta;
 };
 
 BatchLayout batch_layout(const spx_batch_system *sys, int32_t count)
@@ -791,6 +835,7 @@ BatchLayout batch_layout(const spx_batch_system *sys, int32_t count)
         if (batch_is_wide(sys[i])) {
             L.nwide += 1;
             L.total_vb += wide_nvb(sys[i].n);
+            L.total_ta += csr_tiles(sys[i].nnz);
         }
     size_t off = 0;
     L.slots = off;
@@ -807,10 +852,12 @@ BatchLayout batch_layout(const spx_batch_system *sys, int32_t count)
     off += align256(sizeof(int32_t) * (size_t)L.nwide);
     L.vb = off;
     off += align256(sizeof(int32_t) * 2 * (size_t)L.total_vb);
+    L.ta = off;
+    off += align256(sizeof(int32_t) * 2 * (size_t)L.total_ta);
     L.vectors = off;
     for (int32_t i = 0; i < count; ++i) {
         off += 3 * align256((size_t)sys[i].n * 8);
-        if (batch_is_wide(sys[i])) off += align256((size_t)wide_nvb(sys[i].n) * 16);
+        if (batch_is_wide(sys[i])) off += wide_extra_bytes(sys[i].n, sys[i].nnz);
     }
     L.total = off;
     return L;
@@ -848,12 +895,13 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
     WideMap *wmap_dev = reinterpret_cast<WideMap *>(base + L.wmap);
     int32_t *wlist_dev = reinterpret_cast<int32_t *>(base + L.wlist);
     int32_t *vb_dev = reinterpret_cast<int32_t *>(base + L.vb);
+    int32_t *ta_dev = reinterpret_cast<int32_t *>(base + L.ta);
     size_t off = L.vectors;
     std::vector<BatchSlot> host((size_t)count);
     std::vector<WideSlot> whost;
     std::vector<WideState> wstate;
-    std::vector<int32_t> wlist, vb((size_t)(2 * L.total_vb)), widx((size_t)count, -1);
-    int64_t tot = 0;
+    std::vector<int32_t> wlist, vb((size_t)(2 * L.total_vb)), ta((size_t)(2 * L.total_ta)), widx((size_t)count, -1);
+    int64_t tot = 0, tta = 0;
     int32_t maxit_max = 1;
     for (int32_t i = 0; i < count; ++i) {
         const size_t vb_bytes = align256((size_t)sys[i].n * 8);
@@ -875,11 +923,27 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
             w.r = r;
             w.p = p;
             w.q = q;
+            const int64_t nnz = sys[i].nnz;
             w.part = reinterpret_cast<double *>(base + off);
-            off += align256((size_t)wide_nvb(sys[i].n) * 16);
+            off += align256((size_t)wide_nvb(sys[i].n) * 8);
+            w.part_a = reinterpret_cast<double *>(base + off);
+            off += align256((size_t)csr_tiles(nnz) * 8);
+            int32_t *cpart = reinterpret_cast<int32_t *>(base + off);
+            off += align256((size_t)csr_partition_bytes(nnz));
+            w.csr_part = cpart;
+            w.nnz = nnz;
+            w.ntiles = (int32_t)csr_tiles(nnz);
+            {
+                spx_matrix d{};
+                d.fmt = SPX_CSR;
+                d.nrows = sys[i].n;
+                d.ncols = sys[i].n;
+                d.nnz = nnz;
+                d.rowptr = const_cast<int32_t *>(sys[i].rowptr);
+                SPX_CHECK(csr_partition_launch(d, cpart, stream));
+            }
             w.n = sys[i].n;
             w.nvb = wide_nvb(sys[i].n);
-            w.sub = wide_sub_for(sys[i].n, sys[i].nnz);
             w.maxit = maxit;
             w.tol2 = sys[i].tol * sys[i].tol;
             const int32_t k = (int32_t)whost.size();
@@ -889,6 +953,11 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
                 vb[L.total_vb + tot + v] = v;
             }
             tot += w.nvb;
+            for (int32_t v = 0; v < w.ntiles; ++v) {
+                ta[tta + v] = k;
+                ta[L.total_ta + tta + v] = v;
+            }
+            tta += w.ntiles;
             whost.push_back(w);
             WideState s0{};
             s0.mode = kWideInit;
@@ -921,20 +990,22 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
         SPX_HIP(hipMemcpyAsync(host.data(), slots_dev, sizeof(BatchSlot) * (size_t)count, hipMemcpyDeviceToHost, stream));
     }
     if (L.nwide > 0) {
-        const WideMap m{(int32_t)L.total_vb, (int32_t)L.nwide};
+        const WideMap m{(int32_t)L.total_vb, (int32_t)L.nwide, (int32_t)L.total_ta, 0};
         SPX_HIP(hipMemcpyAsync(wslots_dev, whost.data(), sizeof(WideSlot) * whost.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(wstate_dev, wstate.data(), sizeof(WideState) * wstate.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(wmap_dev, &m, sizeof(m), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(wlist_dev, wlist.data(), sizeof(int32_t) * wlist.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(vb_dev, vb.data(), sizeof(int32_t) * vb.size(), hipMemcpyHostToDevice, stream));
-        const int grid = (int)std::min<int64_t>(L.total_vb, 4096);
+        SPX_HIP(hipMemcpyAsync(ta_dev, ta.data(), sizeof(int32_t) * ta.size(), hipMemcpyHostToDevice, stream));
+        const int grid = (int)std::min<int64_t>(std::max(L.total_vb, L.total_ta), 4096);
         // every iteration either counts a CG step or is a true-residual check
         // followed by one, so 2 * maxit + 4 iterations finish every system
         const int64_t limit = 2 * (int64_t)maxit_max + 4;
         for (int64_t done = 0; done < limit;) {
             for (int k = 0; k < 16; ++k, ++done)
                 SPX_CHECK(wide_iteration_launch(wslots_dev, wstate_dev, wmap_dev, wlist_dev, vb_dev,
-                                                vb_dev + L.total_vb, grid, kWideCommitGrid, stream));
+                                                vb_dev + L.total_vb, ta_dev, ta_dev + L.total_ta, grid,
+                                                kWideCommitGrid, stream));
             SPX_HIP(hipMemcpyAsync(wstate.data(), wstate_dev, sizeof(WideState) * wstate.size(), hipMemcpyDeviceToHost,
                                    stream));
             SPX_HIP(hipStreamSynchronize(stream));
