@@ -360,6 +360,21 @@ def bench_solvers(spx, S, torch, dev):
         best = min(ok, key=lambda k: ok[k]["ms"]) if ok else None
         out[nm] = dict(ok[best], inner_tol=best) if best else {"status": "failed"}
         out[nm]["inner_tol_sweep"] = sweep
+    # the same comparison with every matrix in ELL (the fastest format on this
+    # stencil): plain float64 CG against IR with float32 / binary16 values
+    E64 = spx.convert(A64, spx.ELL)
+    spx.cg_solve(E64, bd, tol=1e-10, maxit=5000)
+    x, info = spx.cg_solve(E64, bd, tol=1e-10, maxit=5000)
+    te = info["device_ms"]
+    out["cg_fp64_poisson192_ell"] = {"ms": round(te, 2), "iters": info["iters"], "relres_true": info["relres_true"]}
+    for nm, low in (("ir_fp32_poisson192_ell", spx.F32), ("ir_fp16v_poisson192_ell", spx.F16)):
+        Elow = spx.cast_values(E64, low)
+        spx.ir_solve(E64, Elow, bd, tol=1e-10, inner_tol=1e-6)
+        x, info = spx.ir_solve(E64, Elow, bd, tol=1e-10, inner_tol=1e-6)
+        out[nm] = {"ms": round(info["device_ms"], 2), "inner_iters": info["iters"], "outer": info["outer_iters"],
+                   "speedup_vs_fp64_ell": round(te / info["device_ms"], 3),
+                   "speedup_vs_fp64_csr": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
+                   "status": info["status"], "rel_err_vs_xstar": float(nrm(x - xstar) / nrm(xstar))}
     return out
 
 

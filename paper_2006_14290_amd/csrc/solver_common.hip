@@ -258,6 +258,10 @@ spx_status spmv_dot(const spx_matrix &A, const X *p, X *q, const X *w, X *partia
         SPX_CHECK((sellp_spmv_launch<V, X>(A, p, q, X(1), X(0), stream, 1, w, partials, st)));
         return launch_finish<X>(partials, spmv_dot_parts(A), 1, st, op, stream);
     }
+    if (A.fmt == SPX_ELL) {
+        SPX_CHECK((ell_spmv_launch<V, X>(A, p, q, X(1), X(0), stream, 1, w, partials, st)));
+        return launch_finish<X>(partials, spmv_dot_parts(A), 1, st, op, stream);
+    }
     SPX_CHECK(spmv_dispatch(A, p, q, 1.0, 0.0, stream));
     dot_kernel<X><<<(unsigned)vec_blocks(A.nrows), kVecThreads, 0, stream>>>(A.nrows, w, q, partials, st, op);
     SPX_LAUNCHED();
@@ -274,6 +278,10 @@ spx_status spmv_dot2(const spx_matrix &A, const X *sv, X *t, const X *w, X *part
     }
     if (A.fmt == SPX_SELLP) {
         SPX_CHECK((sellp_spmv_launch<V, X>(A, sv, t, X(1), X(0), stream, 2, w, partials, st)));
+        return launch_finish<X>(partials, spmv_dot_parts(A), 2, st, op, stream);
+    }
+    if (A.fmt == SPX_ELL) {
+        SPX_CHECK((ell_spmv_launch<V, X>(A, sv, t, X(1), X(0), stream, 2, w, partials, st)));
         return launch_finish<X>(partials, spmv_dot_parts(A), 2, st, op, stream);
     }
     SPX_CHECK(spmv_dispatch(A, sv, t, 1.0, 0.0, stream));

@@ -23,6 +23,7 @@ inline int64_t spmv_dot_parts(const spx_matrix &A)
 {
     if (A.fmt == SPX_CSR) return csr_dot_parts(A);
     if (A.fmt == SPX_SELLP) return sellp_dot_parts(A);
+    if (A.fmt == SPX_ELL) return ell_dot_parts(A);
     return vec_blocks(A.nrows);
 }
 inline int64_t partial_slots(const spx_matrix &A)

@@ -18,11 +18,16 @@ constexpr int kSellThreads = 256;
 
 template <typename V, typename X>
 spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+struct KState;
+// epi = 1: also one partial of sum_i y_i*dot_with_i per work-group
+// (ell_dot_parts(A) of them); epi = 2: that and sum_i y_i^2; a set st->flag
+// skips the launch.
 template <typename V, typename X>
-spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
+spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream, int epi = 0,
+                           const X *dot_with = nullptr, X *partials = nullptr, const KState *st = nullptr);
+int64_t ell_dot_parts(const spx_matrix &A);
 template <typename V, typename X>
 spx_status hyb_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream);
-struct KState;
 // epi = 1: also the partials of sum_i y_i*dot_with_i (sellp_dot_parts(A) of
 // them); epi = 2: that and sum_i y_i^2 (partials[epi][parts]); a set
 // st->flag skips the launch.

@@ -164,12 +164,18 @@ __global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, in
         coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, row_before, row_after, y, alpha, beta);
 }
 
-template <typename V, typename X>
+// kEpi: 0 = plain product; 1 = also the block's sum of y_i*w_i; 2 = that and
+// the sum of y_i^2 (one partial per work-group, reduced later in a fixed
+// order; a set solver flag skips the launch).
+template <typename V, typename X, int kEpi>
 __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, int32_t K, int64_t ld,
                                                                int64_t grid_padded, const int32_t *__restrict__ ecol,
                                                                const V *__restrict__ eval, const X *__restrict__ x,
-                                                               X *__restrict__ y, X alpha, X beta)
+                                                               X *__restrict__ y, X alpha, X beta,
+                                                               const X *__restrict__ dot_with,
+                                                               X *__restrict__ partials, const KState *st)
 {
+    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
     const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
     const int64_t i = blk * kEllThreads + threadIdx.x;
     if (blk * kEllThreads >= nrows) return;
@@ -194,7 +200,20 @@ __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, in
             if (cc[u] >= 0) sum += vv[u] * x[cc[u]];
         if (ballot64(cc[U - 1] >= 0) == 0) break;  // every row of the wavefront is into its padding
     }
-    if (in) y[i] = alpha * sum + scaled(y[i], beta);
+    X d1 = X(0), d2 = X(0);
+    if (in) {
+        const X out = alpha * sum + scaled(y[i], beta);
+        y[i] = out;
+        if constexpr (kEpi >= 1) d1 = out * dot_with[i];
+        if constexpr (kEpi >= 2) d2 = out * out;
+    }
+    if constexpr (kEpi > 0) {
+        __shared__ X s_red[kEllThreads / kWave];
+        X v[kEpi];
+        v[0] = block_sum<X, kEllThreads>(d1, s_red);
+        if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<X, kEllThreads>(d2, s_red);
+        write_partials<X, kEpi>(v, partials, (nrows + kEllThreads - 1) / kEllThreads, blk);
+    }
 }
 
 template <typename V, typename X, bool kAccumulate>
@@ -228,13 +247,22 @@ spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
                                  beta, stream);
 }
 
+int64_t ell_dot_parts(const spx_matrix &A) { return A.nrows > 0 ? ceil_div(A.nrows, kEllThreads) : 1; }
+
 template <typename V, typename X>
-spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream)
+spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream, int epi,
+                           const X *dot_with, X *partials, const KState *st)
 {
     const int64_t blocks = ceil_div(A.nrows, kEllThreads);
     const int64_t grid = pad_to_xcds(blocks);
-    ell_spmv_kernel<V, X><<<(unsigned)grid, kEllThreads, 0, stream>>>(
-        A.nrows, A.ell_width, A.ell_ld, grid, A.ell_col, static_cast<const V *>(A.ell_val), x, y, alpha, beta);
+#define SPX_ELL_LAUNCH(E)                                                                                          \
+    ell_spmv_kernel<V, X, E><<<(unsigned)grid, kEllThreads, 0, stream>>>(A.nrows, A.ell_width, A.ell_ld, grid,      \
+                                                                         A.ell_col, static_cast<const V *>(A.ell_val), \
+                                                                         x, y, alpha, beta, dot_with, partials, st)
+    if (epi == 2) SPX_ELL_LAUNCH(2);
+    else if (epi == 1) SPX_ELL_LAUNCH(1);
+    else SPX_ELL_LAUNCH(0);
+#undef SPX_ELL_LAUNCH
     SPX_LAUNCHED();
     return SPX_OK;
 }
@@ -423,7 +451,8 @@ spx_status sellp_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X b
 
 #define SPX_INST(V, X)                                                                                          \
     template spx_status coo_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
-    template spx_status ell_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
+    template spx_status ell_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t, int,        \
+                                              const X *, X *, const KState *);                                    \
     template spx_status hyb_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t);          \
     template spx_status sellp_spmv_launch<V, X>(const spx_matrix &, const X *, X *, X, X, hipStream_t, int,      \
                                                 const X *, X *, const KState *);

@@ -267,3 +267,19 @@ def test_ir_full_192_vs_fp64_cg():
         assert _true_relres(A, b, x) <= 1e-10
         assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 2 * kappa * 1e-10
         print("ir 192^3", low, info, "fp64 cg", i64, flush=True)
+
+
+@pytest.mark.parametrize("low", ["f32", "f16"])
+def test_ir_ell_inner(low):
+    """IR with both matrices in ELL (fused product + dot epilogue of the ELL
+    kernel in the inner CG)."""
+    A = S.poisson3d_7pt(20)
+    xs, b = _problem(A)
+    E64 = spx.convert(spx.csr_from_host(A), spx.ELL)
+    Elow = spx.cast_values(E64, spx.DTYPE_NAMES[low])
+    x, info = spx.ir_solve(E64, Elow, dev(b), tol=1e-10, inner_tol=1e-5)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    xc, ic = spx.cg_solve(E64, dev(b), tol=1e-10, precond=1)
+    assert ic["status"] == spx.OK
+    assert _true_relres(A, b, host(xc)) <= 1e-10
