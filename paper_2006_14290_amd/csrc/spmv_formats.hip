@@ -164,10 +164,13 @@ __global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, in
         coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, row_before, row_after, y, alpha, beta);
 }
 
+// One thread per kR consecutive rows (kR = 2 loads the two rows' slots as
+// one vector when ld is even and the arrays are aligned), four slot columns
+// in flight; a wavefront stops once all its rows are into their padding.
 // kEpi: 0 = plain product; 1 = also the block's sum of y_i*w_i; 2 = that and
 // the sum of y_i^2 (one partial per work-group, reduced later in a fixed
 // order; a set solver flag skips the launch).
-template <typename V, typename X, int kEpi>
+template <typename V, typename X, int kEpi, int kR>
 __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, int32_t K, int64_t ld,
                                                                int64_t grid_padded, const int32_t *__restrict__ ecol,
                                                                const V *__restrict__ eval, const X *__restrict__ x,
@@ -176,43 +179,63 @@ __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, in
                                                                X *__restrict__ partials, const KState *st)
 {
     if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    typedef int32_t CR __attribute__((ext_vector_type(kR)));
+    typedef V VR __attribute__((ext_vector_type(kR)));
+    const int64_t nblocks = ((int64_t)nrows + kEllThreads * kR - 1) / (kEllThreads * kR);
     const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
-    const int64_t i = blk * kEllThreads + threadIdx.x;
-    if (blk * kEllThreads >= nrows) return;
-    const bool in = i < nrows;
-    X sum = X(0);
+    if (blk >= nblocks) return;
+    const int64_t i0 = (blk * kEllThreads + threadIdx.x) * kR;
+    const bool in = i0 < nrows;
+    X sum[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) sum[r] = X(0);
     constexpr int U = 4;
     for (int k = 0; k < K; k += U) {
-        int32_t cc[U];
-        X vv[U];
+        CR cc[U];
+        VR vv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            cc[u] = -1;
-            vv[u] = X(0);
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                cc[u][r] = -1;
+                vv[u][r] = V(0);
+            }
             if (in && k + u < K) {
-                const int64_t q = (int64_t)(k + u) * ld + i;
-                cc[u] = ld_stream(ecol + q);
-                vv[u] = widen(ld_stream(eval + q));
+                const int64_t q = (int64_t)(k + u) * ld + i0;
+                cc[u] = ld_stream(reinterpret_cast<const CR *>(ecol + q));
+                vv[u] = ld_stream(reinterpret_cast<const VR *>(eval + q));
+#pragma unroll
+                for (int r = 1; r < kR; ++r)
+                    if (i0 + r >= nrows) cc[u][r] = -1;  // a slot past the last row is not the matrix's
             }
         }
+        bool live = false;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (cc[u] >= 0) sum += vv[u] * x[cc[u]];
-        if (ballot64(cc[U - 1] >= 0) == 0) break;  // every row of the wavefront is into its padding
+#pragma unroll
+            for (int r = 0; r < kR; ++r)
+                if (cc[u][r] >= 0) sum[r] += widen(vv[u][r]) * x[cc[u][r]];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) live |= cc[U - 1][r] >= 0;
+        if (ballot64(live) == 0) break;  // every row of the wavefront is into its padding
     }
     X d1 = X(0), d2 = X(0);
-    if (in) {
-        const X out = alpha * sum + scaled(y[i], beta);
-        y[i] = out;
-        if constexpr (kEpi >= 1) d1 = out * dot_with[i];
-        if constexpr (kEpi >= 2) d2 = out * out;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int64_t i = i0 + r;
+        if (i < nrows) {
+            const X out = alpha * sum[r] + scaled(y[i], beta);
+            y[i] = out;
+            if constexpr (kEpi >= 1) d1 += out * dot_with[i];
+            if constexpr (kEpi >= 2) d2 += out * out;
+        }
     }
     if constexpr (kEpi > 0) {
         __shared__ X s_red[kEllThreads / kWave];
         X v[kEpi];
         v[0] = block_sum<X, kEllThreads>(d1, s_red);
         if constexpr (kEpi >= 2) v[kEpi - 1] = block_sum<X, kEllThreads>(d2, s_red);
-        write_partials<X, kEpi>(v, partials, (nrows + kEllThreads - 1) / kEllThreads, blk);
+        write_partials<X, kEpi>(v, partials, nblocks, blk);
     }
 }
 
@@ -247,21 +270,44 @@ spx_status coo_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X bet
                                  beta, stream);
 }
 
-int64_t ell_dot_parts(const spx_matrix &A) { return A.nrows > 0 ? ceil_div(A.nrows, kEllThreads) : 1; }
+// Two rows per thread when the slot columns can be read two rows at a time:
+// even leading dimension (so a pair never straddles a slot column; with an
+// odd nrows the last pair's second row is in-bounds padding) and arrays
+// aligned to two entries.
+static int ell_rows_per_thread(const spx_matrix &A)
+{
+    const size_t sv = A.val_type == SPX_F64 ? 8 : (A.val_type == SPX_F32 ? 4 : 2);
+    const bool even = (A.ell_ld % 2) == 0;
+    const bool aligned = (reinterpret_cast<uintptr_t>(A.ell_col) % 8 == 0) &&
+                         (reinterpret_cast<uintptr_t>(A.ell_val) % (2 * sv) == 0);
+    return even && aligned ? 2 : 1;
+}
+
+int64_t ell_dot_parts(const spx_matrix &A)
+{
+    return A.nrows > 0 ? ceil_div(A.nrows, (int64_t)kEllThreads * ell_rows_per_thread(A)) : 1;
+}
 
 template <typename V, typename X>
 spx_status ell_spmv_launch(const spx_matrix &A, const X *x, X *y, X alpha, X beta, hipStream_t stream, int epi,
                            const X *dot_with, X *partials, const KState *st)
 {
-    const int64_t blocks = ceil_div(A.nrows, kEllThreads);
+    const int kr = ell_rows_per_thread(A);
+    const int64_t blocks = ceil_div(A.nrows, (int64_t)kEllThreads * kr);
     const int64_t grid = pad_to_xcds(blocks);
-#define SPX_ELL_LAUNCH(E)                                                                                          \
-    ell_spmv_kernel<V, X, E><<<(unsigned)grid, kEllThreads, 0, stream>>>(A.nrows, A.ell_width, A.ell_ld, grid,      \
-                                                                         A.ell_col, static_cast<const V *>(A.ell_val), \
-                                                                         x, y, alpha, beta, dot_with, partials, st)
-    if (epi == 2) SPX_ELL_LAUNCH(2);
-    else if (epi == 1) SPX_ELL_LAUNCH(1);
-    else SPX_ELL_LAUNCH(0);
+#define SPX_ELL_LAUNCH(E, R)                                                                                        \
+    ell_spmv_kernel<V, X, E, R><<<(unsigned)grid, kEllThreads, 0, stream>>>(                                        \
+        A.nrows, A.ell_width, A.ell_ld, grid, A.ell_col, static_cast<const V *>(A.ell_val), x, y, alpha, beta,      \
+        dot_with, partials, st)
+    if (kr == 2) {
+        if (epi == 2) SPX_ELL_LAUNCH(2, 2);
+        else if (epi == 1) SPX_ELL_LAUNCH(1, 2);
+        else SPX_ELL_LAUNCH(0, 2);
+    } else {
+        if (epi == 2) SPX_ELL_LAUNCH(2, 1);
+        else if (epi == 1) SPX_ELL_LAUNCH(1, 1);
+        else SPX_ELL_LAUNCH(0, 1);
+    }
 #undef SPX_ELL_LAUNCH
     SPX_LAUNCHED();
     return SPX_OK;
