@@ -25,6 +25,8 @@
 namespace spx {
 
 constexpr int kCvThreads = 256;
+constexpr int kCvStageRows = 128;   // rows per work-group of the staged conversions
+constexpr int kCvStageNnz = 4096;   // their LDS capacity in entries
 constexpr int kScanItems = 4;                           // per thread
 constexpr int kScanBlock = kCvThreads * kScanItems;     // elements per scan block
 
@@ -193,22 +195,71 @@ __global__ __launch_bounds__(kCvThreads) void coo_rowptr_kernel(const int32_t *_
 }
 
 // ------------------------------------------------------------------ CSR -> ELL / HYB (ELL part)
-template <typename V>
-__global__ __launch_bounds__(kCvThreads) void csr_to_ell_kernel(const int32_t *__restrict__ rowptr,
-                                                               const int32_t *__restrict__ col,
-                                                               const V *__restrict__ val, int32_t n, int32_t K,
-                                                               int64_t ld, int32_t *__restrict__ ecol,
-                                                               V *__restrict__ eval)
+// Conversions that turn rows into slot columns (or back) go through LDS:
+// the kCvStageRows consecutive rows of a work-group occupy one contiguous
+// stretch of the CSR arrays, read (or written) coalesced there, while each
+// thread walks its own row in LDS. A block whose rows hold more than
+// kCvStageNnz entries reads / writes the CSR arrays directly instead.
+struct StageRange {
+    int32_t base, cnt;
+    bool staged;
+};
+
+__device__ __forceinline__ StageRange stage_range(const int32_t *__restrict__ rowptr, int32_t n, int64_t r0)
 {
-    const int64_t i = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
+    StageRange g{0, 0, false};
+    if (r0 < n) {
+        const int64_t r1 = min((int64_t)n, r0 + kCvStageRows);
+        g.base = rowptr[r0];
+        g.cnt = rowptr[r1] - g.base;
+    }
+    g.staged = g.cnt <= kCvStageNnz;
+    return g;
+}
+
+template <typename V>
+__device__ __forceinline__ void stage_in(const int32_t *__restrict__ col, const V *__restrict__ val,
+                                         const StageRange &g, int32_t *s_col, V *s_val)
+{
+    for (int32_t j = threadIdx.x; j < g.cnt; j += kCvStageRows) {
+        s_col[j] = col[g.base + j];
+        s_val[j] = val[g.base + j];
+    }
+    __syncthreads();
+}
+
+template <typename V>
+__device__ __forceinline__ void stage_out(int32_t *__restrict__ col, V *__restrict__ val, const StageRange &g,
+                                          const int32_t *s_col, const V *s_val)
+{
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < g.cnt; j += kCvStageRows) {
+        col[g.base + j] = s_col[j];
+        val[g.base + j] = s_val[j];
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kCvStageRows) void csr_to_ell_kernel(const int32_t *__restrict__ rowptr,
+                                                                 const int32_t *__restrict__ col,
+                                                                 const V *__restrict__ val, int32_t n, int32_t K,
+                                                                 int64_t ld, int32_t *__restrict__ ecol,
+                                                                 V *__restrict__ eval)
+{
+    __shared__ int32_t s_col[kCvStageNnz];
+    __shared__ V s_val[kCvStageNnz];
+    const int64_t r0 = (int64_t)blockIdx.x * kCvStageRows;
+    const int64_t i = r0 + threadIdx.x;
+    const StageRange g = stage_range(rowptr, n, r0);
+    if (g.staged) stage_in(col, val, g, s_col, s_val);
     if (i >= ld) return;
     const int32_t a = (i < n) ? rowptr[i] : 0;
     const int32_t len = (i < n) ? rowptr[i + 1] - a : 0;
     for (int32_t k = 0; k < K; ++k) {
         const int64_t q = (int64_t)k * ld + i;
         if (k < len) {
-            ecol[q] = col[a + k];
-            eval[q] = val[a + k];
+            ecol[q] = g.staged ? s_col[a - g.base + k] : col[a + k];
+            eval[q] = g.staged ? s_val[a - g.base + k] : val[a + k];
         } else {
             ecol[q] = -1;
             eval[q] = V(0);
@@ -282,34 +333,43 @@ __global__ __launch_bounds__(kCvThreads) void ell_count_kernel(const int32_t *__
 // Row i of the CSR result: the row's ELL entries (slot order, padding
 // dropped) merged with its COO entries (if any), ascending by column.
 template <typename V>
-__global__ __launch_bounds__(kCvThreads) void ell_hyb_to_csr_kernel(
+__global__ __launch_bounds__(kCvStageRows) void ell_hyb_to_csr_kernel(
     const int32_t *__restrict__ ecol, const V *__restrict__ eval, int32_t n, int32_t K, int64_t ld,
     const int32_t *__restrict__ coo_rp, const int32_t *__restrict__ ccol, const V *__restrict__ cval,
     const int32_t *__restrict__ rowptr, int32_t *__restrict__ col, V *__restrict__ val)
 {
-    const int64_t i = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    if (i >= n) return;
-    int32_t o = rowptr[i];
-    int32_t cb = coo_rp ? coo_rp[i] : 0;
-    const int32_t ce = coo_rp ? coo_rp[i + 1] : 0;
-    for (int32_t k = 0; k < K; ++k) {
-        const int64_t q = (int64_t)k * ld + i;
-        const int32_t c = ecol[q];
-        if (c < 0) continue;
-        while (cb < ce && ccol[cb] < c) {  // COO entries with a smaller column come first
-            col[o] = ccol[cb];
-            val[o] = cval[cb];
-            ++o;
-            ++cb;
+    __shared__ int32_t s_col[kCvStageNnz];
+    __shared__ V s_val[kCvStageNnz];
+    const int64_t r0 = (int64_t)blockIdx.x * kCvStageRows;
+    const int64_t i = r0 + threadIdx.x;
+    const StageRange g = stage_range(rowptr, n, r0);
+    // entry o of the CSR result goes to LDS slot o - base when staged
+    auto put = [&](int32_t o, int32_t c, V v) {
+        if (g.staged) {
+            s_col[o - g.base] = c;
+            s_val[o - g.base] = v;
+        } else {
+            col[o] = c;
+            val[o] = v;
         }
-        col[o] = c;
-        val[o] = eval[q];
-        ++o;
+    };
+    if (i < n) {
+        int32_t o = rowptr[i];
+        int32_t cb = coo_rp ? coo_rp[i] : 0;
+        const int32_t ce = coo_rp ? coo_rp[i + 1] : 0;
+        for (int32_t k = 0; k < K; ++k) {
+            const int64_t q = (int64_t)k * ld + i;
+            const int32_t c = ecol[q];
+            if (c < 0) continue;
+            while (cb < ce && ccol[cb] < c) {  // COO entries with a smaller column come first
+                put(o++, ccol[cb], cval[cb]);
+                ++cb;
+            }
+            put(o++, c, eval[q]);
+        }
+        for (; cb < ce; ++cb) put(o++, ccol[cb], cval[cb]);
     }
-    for (; cb < ce; ++cb, ++o) {
-        col[o] = ccol[cb];
-        val[o] = cval[cb];
-    }
+    if (g.staged) stage_out(col, val, g, s_col, s_val);
 }
 
 // ------------------------------------------------------------------ casts
@@ -401,23 +461,28 @@ __global__ __launch_bounds__(kCvThreads) void sellp_width_kernel(const int32_t *
 // One thread per (slice, lane): row s*C + l written slot by slot (lanes of a
 // slice are adjacent, so each slot column is written coalesced).
 template <typename V>
-__global__ __launch_bounds__(kCvThreads) void csr_to_sellp_kernel(const int32_t *__restrict__ rowptr,
-                                                                 const int32_t *__restrict__ col,
-                                                                 const V *__restrict__ val, int32_t n, int32_t C,
-                                                                 int64_t nslices, const int32_t *__restrict__ sets,
-                                                                 int32_t *__restrict__ scol, V *__restrict__ sval)
+__global__ __launch_bounds__(kCvStageRows) void csr_to_sellp_kernel(const int32_t *__restrict__ rowptr,
+                                                                   const int32_t *__restrict__ col,
+                                                                   const V *__restrict__ val, int32_t n, int32_t C,
+                                                                   int64_t nslices, const int32_t *__restrict__ sets,
+                                                                   int32_t *__restrict__ scol, V *__restrict__ sval)
 {
-    const int64_t t = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    if (t >= nslices * C) return;
-    const int64_t s = t / C, l = t % C, r = s * C + l;
+    __shared__ int32_t s_col[kCvStageNnz];
+    __shared__ V s_val[kCvStageNnz];
+    const int64_t r0 = (int64_t)blockIdx.x * kCvStageRows;
+    const int64_t r = r0 + threadIdx.x;  // = slice * C + lane
+    const StageRange g = stage_range(rowptr, n, r0);
+    if (g.staged) stage_in(col, val, g, s_col, s_val);
+    if (r >= nslices * C) return;
+    const int64_t s = r / C, l = r % C;
     const int32_t a = (r < n) ? rowptr[r] : 0;
     const int32_t len = (r < n) ? rowptr[r + 1] - a : 0;
     const int32_t k0 = sets[s], w = sets[s + 1] - k0;
     for (int32_t k = 0; k < w; ++k) {
         const int64_t q = ((int64_t)k0 + k) * C + l;
         if (k < len) {
-            scol[q] = col[a + k];
-            sval[q] = val[a + k];
+            scol[q] = g.staged ? s_col[a - g.base + k] : col[a + k];
+            sval[q] = g.staged ? s_val[a - g.base + k] : val[a + k];
         } else {
             scol[q] = -1;
             sval[q] = V(0);
@@ -440,25 +505,36 @@ __global__ __launch_bounds__(kCvThreads) void sellp_count_kernel(const int32_t *
 }
 
 template <typename V>
-__global__ __launch_bounds__(kCvThreads) void sellp_to_csr_kernel(const int32_t *__restrict__ sets,
-                                                                 const int32_t *__restrict__ scol,
-                                                                 const V *__restrict__ sval, int32_t n, int32_t C,
-                                                                 const int32_t *__restrict__ rowptr,
-                                                                 int32_t *__restrict__ col, V *__restrict__ val)
+__global__ __launch_bounds__(kCvStageRows) void sellp_to_csr_kernel(const int32_t *__restrict__ sets,
+                                                                   const int32_t *__restrict__ scol,
+                                                                   const V *__restrict__ sval, int32_t n, int32_t C,
+                                                                   const int32_t *__restrict__ rowptr,
+                                                                   int32_t *__restrict__ col, V *__restrict__ val)
 {
-    const int64_t r = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    if (r >= n) return;
-    const int64_t s = r / C, l = r % C;
-    const int32_t k0 = sets[s], w = sets[s + 1] - k0;
-    int32_t o = rowptr[r];
-    for (int32_t k = 0; k < w; ++k) {
-        const int64_t q = ((int64_t)k0 + k) * C + l;
-        if (scol[q] >= 0) {
-            col[o] = scol[q];
-            val[o] = sval[q];
-            ++o;
+    __shared__ int32_t s_col[kCvStageNnz];
+    __shared__ V s_val[kCvStageNnz];
+    const int64_t r0 = (int64_t)blockIdx.x * kCvStageRows;
+    const int64_t r = r0 + threadIdx.x;
+    const StageRange g = stage_range(rowptr, n, r0);
+    if (r < n) {
+        const int64_t s = r / C, l = r % C;
+        const int32_t k0 = sets[s], w = sets[s + 1] - k0;
+        int32_t o = rowptr[r];
+        for (int32_t k = 0; k < w; ++k) {
+            const int64_t q = ((int64_t)k0 + k) * C + l;
+            if (scol[q] >= 0) {
+                if (g.staged) {
+                    s_col[o - g.base] = scol[q];
+                    s_val[o - g.base] = sval[q];
+                } else {
+                    col[o] = scol[q];
+                    val[o] = sval[q];
+                }
+                ++o;
+            }
         }
     }
+    if (g.staged) stage_out(col, val, g, s_col, s_val);
 }
 
 // ------------------------------------------------------------------ host side
@@ -682,7 +758,7 @@ static spx_status convert_typed(const spx_matrix &src, spx_matrix &dst, void *ws
     }
     if (src.fmt == SPX_CSR && (dst.fmt == SPX_ELL || dst.fmt == SPX_HYB)) {
         if (dst.ell_width > 0 && dst.ell_ld > 0) {
-            csr_to_ell_kernel<V><<<(unsigned)ceil_div(dst.ell_ld, kCvThreads), kCvThreads, 0, stream>>>(
+            csr_to_ell_kernel<V><<<(unsigned)ceil_div(dst.ell_ld, kCvStageRows), kCvStageRows, 0, stream>>>(
                 src.rowptr, src.colidx, static_cast<const V *>(src.vals), n, dst.ell_width, dst.ell_ld, dst.ell_col,
                 static_cast<V *>(dst.ell_val));
             SPX_LAUNCHED();
@@ -713,7 +789,7 @@ static spx_status convert_typed(const spx_matrix &src, spx_matrix &dst, void *ws
         ell_count_kernel<<<gr, kCvThreads, 0, stream>>>(src.ell_col, n, src.ell_width, src.ell_ld, coo_rp, dst.rowptr);
         SPX_LAUNCHED();
         SPX_CHECK(inclusive_scan<int32_t>(dst.rowptr + 1, n, scan_ws, stream));
-        ell_hyb_to_csr_kernel<V><<<gr, kCvThreads, 0, stream>>>(
+        ell_hyb_to_csr_kernel<V><<<(unsigned)ceil_div(n, kCvStageRows), kCvStageRows, 0, stream>>>(
             src.ell_col, static_cast<const V *>(src.ell_val), n, src.ell_width, src.ell_ld, coo_rp, src.colidx,
             static_cast<const V *>(src.vals), dst.rowptr, dst.colidx, static_cast<V *>(dst.vals));
         SPX_LAUNCHED();
@@ -727,7 +803,7 @@ static spx_status convert_typed(const spx_matrix &src, spx_matrix &dst, void *ws
         SPX_LAUNCHED();
         if (ns > 0) {
             SPX_CHECK(inclusive_scan<int32_t>(dst.slice_sets + 1, ns, ws, stream));
-            csr_to_sellp_kernel<V><<<(unsigned)ceil_div(ns * C, kCvThreads), kCvThreads, 0, stream>>>(
+            csr_to_sellp_kernel<V><<<(unsigned)ceil_div(ns * C, kCvStageRows), kCvStageRows, 0, stream>>>(
                 src.rowptr, src.colidx, static_cast<const V *>(src.vals), n, C, ns, dst.slice_sets, dst.ell_col,
                 static_cast<V *>(dst.ell_val));
             SPX_LAUNCHED();
@@ -739,10 +815,9 @@ static spx_status convert_typed(const spx_matrix &src, spx_matrix &dst, void *ws
         sellp_count_kernel<<<gr, kCvThreads, 0, stream>>>(src.slice_sets, src.ell_col, n, src.slice_size, dst.rowptr);
         SPX_LAUNCHED();
         SPX_CHECK(inclusive_scan<int32_t>(dst.rowptr + 1, n, ws, stream));
-        sellp_to_csr_kernel<V><<<gr, kCvThreads, 0, stream>>>(src.slice_sets, src.ell_col,
-                                                               static_cast<const V *>(src.ell_val), n,
-                                                               src.slice_size, dst.rowptr, dst.colidx,
-                                                               static_cast<V *>(dst.vals));
+        sellp_to_csr_kernel<V><<<(unsigned)ceil_div(n, kCvStageRows), kCvStageRows, 0, stream>>>(
+            src.slice_sets, src.ell_col, static_cast<const V *>(src.ell_val), n, src.slice_size, dst.rowptr,
+            dst.colidx, static_cast<V *>(dst.vals));
         SPX_LAUNCHED();
         return SPX_OK;
     }
