@@ -104,6 +104,9 @@ def _declare(L):
     L.orc_residual.argtypes = [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, ctypes.c_void_p]
     L.orc_residual.restype = _f64
     L.orc_jacobi_setup.argtypes = [_i32, _i32p, _i32p, _f64p, _f64p]
+    L.orc_block_jacobi_setup.argtypes = [_i32, _i32p, _i32p, _f64p, _i32, _f64p]
+    L.orc_block_jacobi_apply.argtypes = [_i32, _i32, _f64p, _f64p, _f64p]
+    L.orc_block_jacobi_apply.restype = None
     solver = [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _i32]
     L.orc_cg.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
     L.orc_bicgstab.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
@@ -351,7 +354,27 @@ def _solve(fn, A, b, x0, extra):
     return x, info.as_dict()
 
 
+def block_jacobi(A, bs):
+    """Inverted diagonal blocks (nblocks, bs, bs) of A, or raises on a
+    singular block."""
+    nb = -(-A.n // bs)
+    inv = np.empty(max(nb, 1) * bs * bs, np.float64)
+    rp, c, v = _csr(A)
+    st = lib().orc_block_jacobi_setup(A.n, rp, c, v, bs, inv)
+    if st != 0:
+        raise ValueError(f"block_jacobi_setup failed: {st}")
+    return inv[: nb * bs * bs].reshape(nb, bs, bs)
+
+
+def block_jacobi_apply(inv, r):
+    nb, bs, _ = inv.shape
+    z = np.empty(len(r), np.float64)
+    lib().orc_block_jacobi_apply(len(r), bs, _c(inv.ravel(), np.float64), _c(r, np.float64), z)
+    return z
+
+
 def cg(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):
+    """precond: 0 none, 1 scalar Jacobi, bs >= 2 block Jacobi (bs x bs blocks)."""
     return _solve(lib().orc_cg, A, b, x0, [tol, maxit, precond, 1 if x0 is None else 0])
 
 

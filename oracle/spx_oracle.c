@@ -609,6 +609,112 @@ static void apply_prec(int32_t n, const double *diag, const double *r, double *z
     for (int32_t i = 0; i < n; ++i) z[i] = diag ? r[i] / diag[i] : r[i];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Block-Jacobi preconditioner (the paper's Section 1 names block-Jacobi     */
+/* among the library's preconditioners; scalar Jacobi is its 1x1 case).      */
+/* Block k holds rows and columns [k*bs, min(n, (k+1)*bs)); its dense        */
+/* diagonal submatrix D_k is inverted by Gauss-Jordan elimination with       */
+/* partial pivoting (largest |pivot|, first row on ties): for each pivot     */
+/* column j, swap the pivot row into place, divide row j of [D | I] by the   */
+/* pivot, then subtract a_rj * (row j) from every other row r. inv holds     */
+/* nblocks blocks of bs*bs doubles, row-major; a last, smaller block of m    */
+/* rows uses the leading m x m part. Returns ORC_ZERO_DIAG for a zero or     */
+/* non-finite pivot.                                                         */
+/* ------------------------------------------------------------------------ */
+int orc_block_jacobi_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t bs,
+                           double *inv)
+{
+    if (bs < 1) return ORC_EARG;
+    int32_t nb = (n + bs - 1) / bs;
+    double *a = malloc(sizeof(double) * (size_t)bs * 2 * bs);
+    if (!a) return ORC_ENOMEM;
+    int status = ORC_OK;
+    for (int32_t k = 0; k < nb && status == ORC_OK; ++k) {
+        int32_t i0 = k * bs, m = (n - i0 < bs) ? n - i0 : bs, w = 2 * m;
+        memset(a, 0, sizeof(double) * (size_t)m * w);
+        for (int32_t r = 0; r < m; ++r) {
+            for (int32_t p = rowptr[i0 + r]; p < rowptr[i0 + r + 1]; ++p)
+                if (col[p] >= i0 && col[p] < i0 + m) a[r * w + (col[p] - i0)] = val[p];
+            a[r * w + m + r] = 1.0;
+        }
+        for (int32_t j = 0; j < m; ++j) {
+            int32_t piv = j;
+            for (int32_t r = j + 1; r < m; ++r)
+                if (fabs(a[r * w + j]) > fabs(a[piv * w + j])) piv = r;
+            double d = a[piv * w + j];
+            if (d == 0.0 || !isfinite(d)) { status = ORC_ZERO_DIAG; break; }
+            if (piv != j)
+                for (int32_t c = 0; c < w; ++c) {
+                    double t = a[j * w + c];
+                    a[j * w + c] = a[piv * w + c];
+                    a[piv * w + c] = t;
+                }
+            for (int32_t c = 0; c < w; ++c) a[j * w + c] /= d;
+            for (int32_t r = 0; r < m; ++r) {
+                if (r == j) continue;
+                double f = a[r * w + j];
+                for (int32_t c = 0; c < w; ++c) a[r * w + c] -= f * a[j * w + c];
+            }
+        }
+        for (int32_t r = 0; r < bs; ++r)
+            for (int32_t c = 0; c < bs; ++c)
+                inv[(size_t)k * bs * bs + (size_t)r * bs + c] = (r < m && c < m) ? a[r * w + m + c] : 0.0;
+    }
+    free(a);
+    return status;
+}
+
+/* z = blockdiag(D_k^{-1}) r, each entry summed over the block's columns in
+ * order. */
+void orc_block_jacobi_apply(int32_t n, int32_t bs, const double *inv, const double *r, double *z)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t k = i / bs, i0 = k * bs, m = (n - i0 < bs) ? n - i0 : bs;
+        double s = 0.0;
+        for (int32_t j = 0; j < m; ++j) s += inv[(size_t)k * bs * bs + (size_t)(i - i0) * bs + j] * r[i0 + j];
+        z[i] = s;
+    }
+}
+
+/* A preconditioner: none (kind 0), scalar Jacobi (kind 1, diag), or block
+ * Jacobi with kind x kind blocks (kind >= 2, inv). */
+typedef struct {
+    int32_t kind;
+    double *diag, *inv;
+} orc_prec;
+
+static int prec_setup(orc_prec *P, int32_t kind, int32_t n, const int32_t *rowptr, const int32_t *col,
+                      const double *val)
+{
+    P->kind = kind;
+    P->diag = NULL;
+    P->inv = NULL;
+    if (kind == 1) {
+        P->diag = malloc(sizeof(double) * (n > 0 ? n : 1));
+        if (!P->diag) return ORC_ENOMEM;
+        return orc_jacobi_setup(n, rowptr, col, val, P->diag);
+    }
+    if (kind >= 2) {
+        int32_t nb = (n + kind - 1) / kind;
+        P->inv = malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1) * kind * kind);
+        if (!P->inv) return ORC_ENOMEM;
+        return orc_block_jacobi_setup(n, rowptr, col, val, kind, P->inv);
+    }
+    return ORC_OK;
+}
+
+static void prec_apply(const orc_prec *P, int32_t n, const double *r, double *z)
+{
+    if (P->kind >= 2) orc_block_jacobi_apply(n, P->kind, P->inv, r, z);
+    else apply_prec(n, P->diag, r, z);
+}
+
+static void prec_free(orc_prec *P)
+{
+    free(P->diag);
+    free(P->inv);
+}
+
 typedef struct {
     int32_t status, iters, spmv_count, outer_iters;
     double relres_recursive, relres_true;
@@ -621,7 +727,8 @@ typedef struct {
 /* the residual relative to ||b||; when the recursive residual passes, the   */
 /* true residual b - A x decides, and a miss restarts the recurrences from   */
 /* it. Iterations count the products q = A p.                                */
-/* precond: 0 none, 1 scalar Jacobi. x holds x0 on entry unless x0_zero.     */
+/* precond: 0 none, 1 scalar Jacobi, b >= 2 block Jacobi with b x b blocks.  */
+/* x holds x0 on entry unless x0_zero.                                       */
 /* ------------------------------------------------------------------------ */
 int orc_cg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
            const double *b, double *x, double tol, int32_t maxit, int32_t precond, int32_t x0_zero,
@@ -630,9 +737,10 @@ int orc_cg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
     memset(info, 0, sizeof(*info));
     double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
-    double *diag = precond ? malloc(sizeof(double) * n) : NULL;
-    if (!r || !z || !p || !q || (precond && !diag)) { info->status = ORC_ENOMEM; goto out; }
-    if (precond && orc_jacobi_setup(n, rowptr, col, val, diag) != ORC_OK) {
+    orc_prec P;
+    int ps = prec_setup(&P, precond, n, rowptr, col, val);
+    if (!r || !z || !p || !q || ps == ORC_ENOMEM) { info->status = ORC_ENOMEM; goto out; }
+    if (ps != ORC_OK) {
         info->status = ORC_ZERO_DIAG;
         goto out;
     }
@@ -657,7 +765,7 @@ int orc_cg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
     }
     while (info->status == ORC_NOT_CONVERGED) {
         if (restart) {
-            apply_prec(n, diag, r, z);
+            prec_apply(&P, n, r, z);
             memcpy(p, z, sizeof(double) * n);
             rho = dot(n, r, z);
             restart = 0;
@@ -681,7 +789,7 @@ int orc_cg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
             restart = 1;
             continue;
         }
-        apply_prec(n, diag, r, z);
+        prec_apply(&P, n, r, z);
         double rho_new = dot(n, r, z);
         double beta = rho_new / rho;
         rho = rho_new;
@@ -689,7 +797,8 @@ int orc_cg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
     }
     info->relres_true = orc_residual(n, rowptr, col, val, b, x, NULL) / bn;
 out:
-    free(r); free(z); free(p); free(q); free(diag);
+    free(r); free(z); free(p); free(q);
+    prec_free(&P);
     return info->status;
 }
 
