@@ -317,6 +317,13 @@ def bench_solvers(spx, S, torch, dev):
                                  "us_per_iter": round(it_us, 2),
                                  "GBs": round(cg_iter_bytes(A.n, A.nnz, 8, True) / it_us / 1e3, 1),
                                  "relres_true": info["relres_true"]}
+    # block Jacobi (8 x 8 and 32 x 32 diagonal blocks) on the same system
+    for bs in (8, 32):
+        spx.cg_solve(Ad, bd, tol=1e-10, precond=bs, maxit=5000)
+        x, info = spx.cg_solve(Ad, bd, tol=1e-10, precond=bs, maxit=5000)
+        out[f"cg_blockjacobi{bs}_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
+                                               "us_per_iter": round(1e3 * info["device_ms"] / max(info["iters"], 1), 2),
+                                               "relres_true": info["relres_true"]}
     # the same solve on the SELL-P form of the matrix (the paper runs CG on Sellp)
     Ps = spx.convert(Ad, spx.SELLP)
     spx.cg_solve(Ps, bd, tol=1e-10, precond=1, maxit=5000)

@@ -215,7 +215,11 @@ typedef struct {
     double tol;          /* relative residual target (e.g. 1e-10)                 */
     int32_t maxit;       /* iteration limit (GMRES: Arnoldi steps)                 */
     int32_t restart;     /* GMRES restart length m (1..62), e.g. 30                */
-    int32_t precond;     /* 0 none, 1 scalar Jacobi M = diag(A)                    */
+    int32_t precond;     /* 0 none, 1 scalar Jacobi M = diag(A); CG on CSR also
+                            bs = 2, 4, 8, 16, 32: block Jacobi, M = the bs x bs
+                            diagonal blocks (inverted by Gauss-Jordan with
+                            partial pivoting; a singular block gives
+                            SPX_ERR_ZERO_DIAG)                                    */
     int32_t x0_zero;     /* 1: start from x = 0 (x is write-only)                  */
     int32_t check_every; /* iterations per graph replay between host checks (0 = 16) */
     int32_t reserved;

@@ -1,0 +1,150 @@
+// block_jacobi.hip -- block-Jacobi preconditioner for CG.
+//
+// Block-Jacobi is among the preconditioners the paper lists for the library
+// (Section 1); the scalar Jacobi is its 1x1 case. Block k covers rows and
+// columns [k*bs, min(n, (k+1)*bs)), bs a power of two <= 32. Setup: one
+// wavefront per block gathers the dense diagonal block from the CSR rows into
+// LDS next to an identity and runs Gauss-Jordan elimination with partial
+// pivoting (largest |pivot|, lowest row on ties); the inverse is stored
+// column-major per block (inv[k*bs*bs + j*bs + i] = (D_k^{-1})_{ij}) so that
+// the threads of a block read it coalesced when applying it. A zero or
+// non-finite pivot sets the solver flag to breakdown.
+#include "solver_common.hpp"
+#include "solvers.hpp"
+
+namespace spx {
+
+constexpr int kBjMax = 32;
+constexpr int kBjStride = 2 * kBjMax;  // LDS row stride of the augmented block
+
+template <typename V>
+__global__ __launch_bounds__(kWave) void bj_setup_kernel(const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const V *__restrict__ val, int32_t n, int32_t bs,
+                                                        double *__restrict__ inv, KState *st)
+{
+    __shared__ double a[kBjMax * kBjStride];
+    const int64_t k = blockIdx.x;
+    const int64_t i0 = k * bs;
+    const int m = (int)min((int64_t)bs, n - i0);
+    const int w = 2 * m;
+    const int lane = threadIdx.x;
+    for (int t = lane; t < kBjMax * kBjStride; t += kWave) a[t] = 0.0;
+    __syncthreads();
+    if (lane < m) {
+        for (int32_t p = rowptr[i0 + lane]; p < rowptr[i0 + lane + 1]; ++p) {
+            const int32_t c = col[p];
+            if (c >= i0 && c < i0 + m) a[lane * kBjStride + (c - i0)] = (double)val[p];
+        }
+        a[lane * kBjStride + m + lane] = 1.0;
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int j = 0; j < m; ++j) {
+        // pivot: largest |a_rj| over r >= j, lowest r on ties (wavefront argmax)
+        double v = (lane >= j && lane < m) ? fabs(a[lane * kBjStride + j]) : -1.0;
+        int idx = lane;
+        for (int off = kWave / 2; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(v, off);
+            const int oi = __shfl_xor(idx, off);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        const int piv = idx;
+        const double d = a[piv * kBjStride + j];
+        if (d == 0.0 || !__builtin_isfinite(d)) {
+            ok = false;
+            break;
+        }
+        if (piv != j && lane < w) {
+            const double t = a[j * kBjStride + lane];
+            a[j * kBjStride + lane] = a[piv * kBjStride + lane];
+            a[piv * kBjStride + lane] = t;
+        }
+        __syncthreads();
+        if (lane < w) a[j * kBjStride + lane] /= d;
+        __syncthreads();
+        for (int r = 0; r < m; ++r) {
+            if (r == j) continue;
+            const double f = a[r * kBjStride + j];
+            __syncthreads();  // every lane has f before lane j overwrites a_rj
+            if (lane < w) a[r * kBjStride + lane] -= f * a[j * kBjStride + lane];
+            __syncthreads();
+        }
+    }
+    if (!ok) {
+        if (lane == 0) atomicMax(&st->flag, (int32_t)kBreakdown);
+        return;
+    }
+    // column-major inverse; rows / columns past m of a last, smaller block are 0
+    for (int t = lane; t < bs * bs; t += kWave) {
+        const int j = t / bs, i = t % bs;
+        inv[k * bs * bs + t] = (i < m && j < m) ? a[i * kBjStride + m + j] : 0.0;
+    }
+}
+
+// z = blockdiag(D_k^{-1}) r (each entry summed over its block's columns in
+// order), optionally p = z, and the work-group partial of sum r_i z_i at
+// partials[row * gridDim.x + blockIdx.x] (the layout of the vector kernels).
+// check_flag: skip once the solve has stopped (inside iteration graphs).
+template <typename X>
+__global__ __launch_bounds__(kVecThreads) void bj_apply_kernel(int64_t n, int32_t bs,
+                                                              const double *__restrict__ inv,
+                                                              const X *__restrict__ r, X *__restrict__ z,
+                                                              X *__restrict__ p, X *__restrict__ partials, int row,
+                                                              const KState *st, int check_flag)
+{
+    if (check_flag && st->flag != kRunning) return;
+    __shared__ X s_red[kVecThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kVecChunk;
+    X rz = X(0);
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+        const int64_t i = base + threadIdx.x + u * kVecThreads;
+        if (i < n) {
+            const int64_t k = i / bs, i0 = k * bs;
+            const int m = (int)min((int64_t)bs, n - i0);
+            const double *blk = inv + k * bs * bs + (i - i0);
+            X s = X(0);
+            for (int j = 0; j < m; ++j) s += (X)blk[j * bs] * r[i0 + j];
+            z[i] = s;
+            if (p) p[i] = s;
+            rz += r[i] * s;
+        }
+    }
+    X v[1] = {block_sum<X, kVecThreads>(rz, s_red)};
+    write_partials<X, 1>(v, partials + (int64_t)row * gridDim.x, gridDim.x, blockIdx.x);
+}
+
+template <typename V>
+spx_status bj_setup(const spx_matrix &A, int32_t bs, double *inv, KState *st, hipStream_t stream)
+{
+    const int64_t nb = ceil_div(A.nrows, bs);
+    if (nb == 0) return SPX_OK;
+    bj_setup_kernel<V><<<(unsigned)nb, kWave, 0, stream>>>(A.rowptr, A.colidx, static_cast<const V *>(A.vals),
+                                                           A.nrows, bs, inv, st);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+template <typename X>
+spx_status bj_apply(int64_t n, int32_t bs, const double *inv, const X *r, X *z, X *p, X *partials, int row,
+                    const KState *st, bool check_flag, hipStream_t stream)
+{
+    bj_apply_kernel<X><<<(unsigned)vec_blocks(n), kVecThreads, 0, stream>>>(n, bs, inv, r, z, p, partials, row, st,
+                                                                            check_flag ? 1 : 0);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+template spx_status bj_setup<double>(const spx_matrix &, int32_t, double *, KState *, hipStream_t);
+template spx_status bj_setup<float>(const spx_matrix &, int32_t, double *, KState *, hipStream_t);
+template spx_status bj_setup<_Float16>(const spx_matrix &, int32_t, double *, KState *, hipStream_t);
+template spx_status bj_apply<double>(int64_t, int32_t, const double *, const double *, double *, double *, double *,
+                                     int, const KState *, bool, hipStream_t);
+template spx_status bj_apply<float>(int64_t, int32_t, const double *, const float *, float *, float *, float *, int,
+                                    const KState *, bool, hipStream_t);
+
+}  // namespace spx

@@ -6,7 +6,7 @@
 using namespace spx;
 
 static spx_status check_solve(const spx_matrix *A, const void *b, const void *x, const spx_solve_opts *opts,
-                              const spx_solve_info *info, const char *who)
+                              const spx_solve_info *info, const char *who, bool block_jacobi = false)
 {
     SPX_CHECK(check_matrix(A, who));
     SPX_REQUIRE(opts != nullptr && info != nullptr, SPX_ERR_ARG, "%s: null opts or info", who);
@@ -14,7 +14,15 @@ static spx_status check_solve(const spx_matrix *A, const void *b, const void *x,
     SPX_REQUIRE(A->nrows == 0 || (b != nullptr && x != nullptr), SPX_ERR_ARG, "%s: null vector", who);
     SPX_REQUIRE(opts->tol >= 0.0, SPX_ERR_ARG, "%s: negative tolerance", who);
     SPX_REQUIRE(opts->maxit >= 0, SPX_ERR_ARG, "%s: negative maxit", who);
-    SPX_REQUIRE(opts->precond == 0 || opts->precond == 1, SPX_ERR_ARG, "%s: precond must be 0 or 1", who);
+    const int32_t pc = opts->precond;
+    if (block_jacobi && pc >= 2) {
+        SPX_REQUIRE(pc <= 32 && (pc & (pc - 1)) == 0, SPX_ERR_ARG,
+                    "%s: block-Jacobi block size %d is not a power of two <= 32", who, pc);
+        SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "%s: block Jacobi needs a CSR matrix", who);
+        return SPX_OK;
+    }
+    SPX_REQUIRE(pc == 0 || pc == 1, SPX_ERR_ARG, "%s: precond must be 0 or 1%s", who,
+                block_jacobi ? " or a block size 2..32" : "");
     return SPX_OK;
 }
 
@@ -46,7 +54,7 @@ extern "C" spx_status spx_cg_solve(const spx_matrix *A, const double *b, double 
                                    void *ws, size_t ws_bytes, spx_solve_info *info, hipStream_t stream)
 {
     clear_error();
-    SPX_CHECK(check_solve(A, b, x, opts, info, "spx_cg_solve"));
+    SPX_CHECK(check_solve(A, b, x, opts, info, "spx_cg_solve", true));
     SPX_REQUIRE(A->val_type == SPX_F64, SPX_ERR_ARG, "spx_cg_solve: matrix values must be SPX_F64");
     if (A->nrows == 0) {
         *info = spx_solve_info{};

@@ -151,6 +151,7 @@ __global__ void zero_kernel(int64_t n, X *__restrict__ x)
 template <typename V, typename X>
 struct CgBufs {
     X *r, *z, *p, *q, *d, *dinv, *partials;
+    double *inv;  // block-Jacobi inverse blocks
     KState *st;
     int32_t *part;
 };
@@ -165,8 +166,9 @@ static CgBufs<V, X> cg_carve(Carve &c, const spx_matrix &A, int precond)
     w.p = c.take<X>(n);
     w.q = c.take<X>(n);
     w.z = precond ? c.take<X>(n) : w.r;
-    w.d = precond ? c.take<X>(n) : nullptr;
-    w.dinv = precond ? c.take<X>(n) : nullptr;
+    w.d = precond == 1 ? c.take<X>(n) : nullptr;
+    w.dinv = precond == 1 ? c.take<X>(n) : nullptr;
+    w.inv = precond >= 2 ? c.take<double>(ceil_div(n, precond) * precond * precond) : nullptr;
     w.partials = c.take<X>(3 * partial_slots(A));
     w.part = (A.fmt == SPX_CSR && A.csr_part == nullptr) ? c.take<int32_t>(csr_partition_bytes(A.nnz) / 4) : nullptr;
     return w;
@@ -204,11 +206,13 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
     }
     SPX_CHECK(state_init(w.st, sp.tol, sp.maxit, s));
     KState hs;
+    const int32_t bs = sp.precond >= 2 ? sp.precond : 0;  // block-Jacobi block size
     if (sp.precond) {
-        SPX_CHECK((jacobi_setup<V, X>(A, w.d, w.dinv, w.st, s)));
+        if (bs) SPX_CHECK(bj_setup<V>(A, bs, w.inv, w.st, s));
+        else SPX_CHECK((jacobi_setup<V, X>(A, w.d, w.dinv, w.st, s)));
         SPX_CHECK(read_state(env, w.st, &hs));
         if (hs.flag != kRunning) {
-            set_error("cg: zero, missing or non-finite diagonal entry");
+            set_error(bs ? "cg: singular or non-finite diagonal block" : "cg: zero, missing or non-finite diagonal entry");
             return SPX_ERR_ZERO_DIAG;
         }
     }
@@ -221,6 +225,8 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
         cg_init_kernel<X><<<gv, kVecThreads, 0, s>>>(n, b, w.q, w.dinv, w.r, w.z, w.p, w.partials, w.st);
     }
     SPX_LAUNCHED();
+    // block Jacobi: z = M^{-1} r, p = z and the r.z partials (row 1 of the init sums)
+    if (bs) SPX_CHECK(bj_apply<X>(n, bs, w.inv, w.r, w.z, w.p, w.partials, 1, w.st, false, s));
     SPX_CHECK(launch_finish<X>(w.partials, gv, 3, w.st, kOpCgInit, s));
     SPX_CHECK(read_state(env, w.st, &hs));
 
@@ -240,6 +246,8 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
                                                                      sp.precond ? w.z : nullptr, w.dinv, w.partials,
                                                                      w.st);
             }
+            // block Jacobi: z = M^{-1} r and the r.z partials replace row 0
+            if (bs) SPX_CHECK(bj_apply<X>(n, bs, w.inv, w.r, w.z, nullptr, w.partials, 0, w.st, true, s));
             SPX_CHECK(launch_finish<X>(w.partials, gv, 2, w.st, kOpCgRho, s));
             cg_p_kernel<X, true><<<gv, kVecThreads, 0, s>>>(n, w.z, w.p, w.st);
             SPX_LAUNCHED();
@@ -279,6 +287,7 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
             // restart the recurrences from the true residual (already in r)
             cg_restart_kernel<X><<<gv, kVecThreads, 0, s>>>(n, w.r, w.dinv, w.z, w.p, w.partials, w.st);
             SPX_LAUNCHED();
+            if (bs) SPX_CHECK(bj_apply<X>(n, bs, w.inv, w.r, w.z, w.p, w.partials, 0, w.st, false, s));
             SPX_CHECK(launch_finish<X>(w.partials, gv, 1, w.st, kOpCgRestart, s));
             SPX_CHECK(read_state(env, w.st, &hs));
             have_true = false;

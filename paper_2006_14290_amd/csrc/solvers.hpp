@@ -5,15 +5,26 @@
 
 namespace spx {
 
+struct KState;
+
 struct SolveSpec {
     double tol;
     int32_t maxit;
     int32_t restart;      // GMRES m
-    int32_t precond;      // 0 none, 1 scalar Jacobi
+    int32_t precond;      // 0 none, 1 scalar Jacobi, bs >= 2 block Jacobi (CG only)
     int32_t x0_zero;
     int32_t check_every;  // iterations per captured graph launch
     int32_t confirm_true; // confirm convergence with the true residual
 };
+
+// Block-Jacobi (block size bs, a power of two <= 32; CSR matrices): the
+// inverted diagonal blocks, column-major per block, in inv[nblocks*bs*bs].
+template <typename V>
+spx_status bj_setup(const spx_matrix &A, int32_t bs, double *inv, KState *st, hipStream_t stream);
+// z = M^{-1} r, optionally p = z, partial sums of r.z at partials row `row`.
+template <typename X>
+spx_status bj_apply(int64_t n, int32_t bs, const double *inv, const X *r, X *z, X *p, X *partials, int row,
+                    const KState *st, bool check_flag, hipStream_t stream);
 
 template <typename V, typename X>
 size_t cg_workspace(const spx_matrix &A, int precond);

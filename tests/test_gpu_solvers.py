@@ -283,3 +283,47 @@ def test_ir_ell_inner(low):
     xc, ic = spx.cg_solve(E64, dev(b), tol=1e-10, precond=1)
     assert ic["status"] == spx.OK
     assert _true_relres(A, b, host(xc)) <= 1e-10
+
+
+# ---------------------------------------------------------------- block Jacobi
+@pytest.mark.parametrize("bs", [2, 8, 32])
+def test_cg_block_jacobi_matches_oracle(bs):
+    A = S.poisson3d_7pt(23, 1.0, 0.01, 0.01)  # n = 12,167: the last block is partial
+    xs, b = _problem(A, seed=4)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), tol=1e-10, precond=bs)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    _, io = O.cg(A, b, tol=1e-10, precond=bs)
+    assert io["status"] == O.OK
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
+
+
+def test_cg_block_jacobi_block_diagonal_one_iteration():
+    rng = np.random.default_rng(3)
+    bs, n = 8, 8 * 200
+    d = np.zeros((n, n))
+    for i0 in range(0, n, bs):
+        g = rng.uniform(-1, 1, (bs, bs))
+        d[i0:i0 + bs, i0:i0 + bs] = g @ g.T + bs * np.eye(bs)
+    A = S.from_dense(d)
+    b = rng.uniform(-1, 1, n)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), tol=1e-12, precond=bs)
+    assert info["status"] == spx.OK and info["iters"] == 1
+    np.testing.assert_allclose(host(x), np.linalg.solve(d, b), rtol=1e-11, atol=1e-12)
+
+
+def test_cg_block_jacobi_errors():
+    d = np.eye(64)
+    d[2:4, 2:4] = [[1.0, 2.0], [2.0, 4.0]]  # a singular 2 x 2 block
+    with pytest.raises(spx.SpxError, match="ZERO_DIAG"):
+        spx.cg_solve(spx.csr_from_host(S.from_dense(d)), dev(np.ones(64)), precond=2)
+    A = S.poisson2d(12)
+    Ad = spx.csr_from_host(A)
+    b = dev(np.ones(A.n))
+    for bad in (3, 64):
+        with pytest.raises(spx.SpxError, match="ERR_ARG"):
+            spx.cg_solve(Ad, b, precond=bad)
+    with pytest.raises(spx.SpxError, match="ERR_ARG"):
+        spx.bicgstab_solve(Ad, b, precond=4)
+    with pytest.raises(spx.SpxError, match="ERR_ARG"):
+        spx.cg_solve(spx.convert(Ad, spx.ELL), b, precond=4)
