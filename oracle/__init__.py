@@ -2,8 +2,9 @@
 
 Plain, sequential float64 reference implementations of what the library's GPU
 path computes: sparse matrix-vector products in CSR/COO/ELL, format
-conversions, value casts, the scalar Jacobi preconditioner, CG, BiCGSTAB,
-restarted GMRES and mixed-precision iterative refinement. The arithmetic lives
+conversions and the CSR transpose, value casts, scalar and block Jacobi
+preconditioners, CG, pipelined CG, BiCG, BiCGSTAB, restarted GMRES and
+mixed-precision iterative refinement. The arithmetic lives
 in ``spx_oracle.c`` (plain C, compiled with gcc); this module only marshals
 numpy arrays to it.
 
@@ -111,6 +112,9 @@ def _declare(L):
     L.orc_cg.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
     L.orc_bicgstab.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
     L.orc_gmres.argtypes = solver + [_i32, _i32, _i32, ctypes.POINTER(Info)]
+    L.orc_bicg.argtypes = solver + [_i32, _i32, ctypes.c_void_p, _i32, ctypes.POINTER(Info)]
+    L.orc_pipecg.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
+    L.orc_csr_transpose.argtypes = [_i32, _i32, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
     L.orc_arnoldi.argtypes = [_i32, _i32p, _i32p, _f64p, _f64p, _i32, _i32, _f64p, _f64p]
     L.orc_ir.argtypes = [_i32, _i32p, _i32p, _f64p, _f32p, _f64p, _f64p, _f64, _f64, _i32, _i32,
                          ctypes.POINTER(Info)]
@@ -380,6 +384,38 @@ def cg(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):
 
 def bicgstab(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):
     return _solve(lib().orc_bicgstab, A, b, x0, [tol, maxit, precond, 1 if x0 is None else 0])
+
+
+def bicg(A, b, tol=1e-10, maxit=10000, precond=0, x0=None, nhist=0):
+    """Preconditioned BiCG (precond 0 none, 1 scalar Jacobi). With nhist > 0
+    also returns the residuals r_k and shadow residuals rt_k at the start of
+    the first nhist iterations, as two (nhist, n) arrays."""
+    hist = np.zeros((max(nhist, 1), 2, A.n))
+    x, info = _solve(lib().orc_bicg, A, b, x0,
+                     [tol, maxit, precond, 1 if x0 is None else 0,
+                      hist.ctypes.data_as(ctypes.c_void_p) if nhist > 0 else None, nhist])
+    if nhist > 0:
+        return x, info, hist[:, 0, :].copy(), hist[:, 1, :].copy()
+    return x, info
+
+
+def pipecg(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):
+    """Pipelined preconditioned CG (precond 0 none, 1 scalar Jacobi)."""
+    return _solve(lib().orc_pipecg, A, b, x0, [tol, maxit, precond, 1 if x0 is None else 0])
+
+
+def csr_transpose(A, ncols=None):
+    """Transpose of A (n rows, ncols columns, default square): returns
+    (rowptr_t [ncols+1], col_t, val_t)."""
+    nc = A.n if ncols is None else ncols
+    rp, c, v = _csr(A)
+    rpt = np.empty(nc + 1, np.int32)
+    ct = np.empty(max(A.nnz, 1), np.int32)
+    vt = np.empty(max(A.nnz, 1), np.float64)
+    st = lib().orc_csr_transpose(A.n, nc, rp, c, v, rpt, ct, vt)
+    if st != 0:
+        raise ValueError(f"csr_transpose failed: {st}")
+    return rpt, ct[: A.nnz].copy(), vt[: A.nnz].copy()
 
 
 def gmres(A, b, tol=1e-10, maxit=10000, restart=30, precond=0, x0=None):

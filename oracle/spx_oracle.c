@@ -901,6 +901,251 @@ out:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Transpose of an nrows x ncols CSR matrix: (A^T)_{ji} = A_{ij}. A counting */
+/* sort by column: count each column's entries, prefix-sum the counts into   */
+/* the row pointer of A^T (ncols + 1 entries), then walk A's rows in         */
+/* increasing order appending every entry to its column, so the rows of A^T  */
+/* come out sorted by column index.                                          */
+/* ------------------------------------------------------------------------ */
+int orc_csr_transpose(int32_t nrows, int32_t ncols, const int32_t *rowptr, const int32_t *col,
+                      const double *val, int32_t *rowptr_t, int32_t *col_t, double *val_t)
+{
+    if (nrows < 0 || ncols < 0) return ORC_EARG;
+    int32_t *next = malloc(sizeof(int32_t) * (ncols > 0 ? ncols : 1));
+    if (!next) return ORC_ENOMEM;
+    for (int32_t j = 0; j <= ncols; ++j) rowptr_t[j] = 0;
+    for (int32_t p = 0; p < rowptr[nrows]; ++p) {
+        if (col[p] < 0 || col[p] >= ncols) {
+            free(next);
+            return ORC_ERANGE;
+        }
+        rowptr_t[col[p] + 1] += 1;
+    }
+    for (int32_t j = 0; j < ncols; ++j) rowptr_t[j + 1] += rowptr_t[j];
+    for (int32_t j = 0; j < ncols; ++j) next[j] = rowptr_t[j];
+    for (int32_t i = 0; i < nrows; ++i)
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int32_t d = next[col[p]]++;
+            col_t[d] = i;
+            val_t[d] = val[p];
+        }
+    free(next);
+    return ORC_OK;
+}
+
+/* y = A^T x from the definition y_j = sum_i a_ij x_i: y = 0, then A's rows  */
+/* in increasing i add a_ij x_i to y_j (A square, n x n).                   */
+static void csr_spmv_t(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                       const double *x, double *y)
+{
+    for (int32_t j = 0; j < n; ++j) y[j] = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) y[col[p]] += val[p] * x[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned BiCG (Fletcher 1976, in the form of Barrett et al.,        */
+/* "Templates", 1994); the paper lists BiCG among the library's solvers      */
+/* (Section 1). The shadow residual starts as r~ = r. With M = diag(A)       */
+/* (Jacobi) M^{-T} = M^{-1}. One iteration:                                 */
+/*   z = M^{-1} r, z~ = M^{-T} r~, rho = z . r~ (zero: breakdown);           */
+/*   p = z, p~ = z~ on the first step, else with beta = rho / rho_prev       */
+/*   p = z + beta p, p~ = z~ + beta p~;                                      */
+/*   q = A p, q~ = A^T p~, alpha = rho / (p~ . q) (zero: breakdown);         */
+/*   x += alpha p, r -= alpha q, r~ -= alpha q~.                             */
+/* Stopping as orc_cg; a true residual that misses restarts from it with     */
+/* r~ = r. Each iteration counts two products (A and A^T). hist, if not      */
+/* NULL, receives r and r~ at the start of iterations 1 .. nhist (2n doubles */
+/* per iteration: r, then r~).                                               */
+/* ------------------------------------------------------------------------ */
+int orc_bicg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+             const double *b, double *x, double tol, int32_t maxit, int32_t precond, int32_t x0_zero,
+             double *hist, int32_t nhist, orc_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    size_t nb = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = malloc(nb), *rt = malloc(nb), *z = malloc(nb), *zt = malloc(nb);
+    double *p = malloc(nb), *pt = malloc(nb), *q = malloc(nb), *qt = malloc(nb);
+    double *diag = precond ? malloc(nb) : NULL;
+    if (!r || !rt || !z || !zt || !p || !pt || !q || !qt || (precond && !diag)) {
+        info->status = ORC_ENOMEM;
+        goto out;
+    }
+    if (precond && orc_jacobi_setup(n, rowptr, col, val, diag) != ORC_OK) {
+        info->status = ORC_ZERO_DIAG;
+        goto out;
+    }
+    if (x0_zero) memset(x, 0, sizeof(double) * n);
+    double bn = nrm2(n, b);
+    if (!isfinite(bn)) { info->status = ORC_NONFINITE; goto out; }
+    if (bn == 0.0) { memset(x, 0, sizeof(double) * n); info->status = ORC_OK; goto out; }
+    orc_csr_spmv(n, rowptr, col, val, x, q, 1.0, 0.0);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    info->status = ORC_NOT_CONVERGED;
+    if (nrm2(n, r) <= tol * bn) {
+        info->status = ORC_OK;
+        goto done;
+    }
+    int restart = 1, first = 1;
+    double rho_prev = 1.0;
+    while (info->iters < maxit) {
+        if (restart) {
+            memcpy(rt, r, sizeof(double) * n);
+            restart = 0;
+            first = 1;
+        }
+        if (hist && info->iters < nhist) {
+            memcpy(hist + (size_t)2 * n * info->iters, r, sizeof(double) * n);
+            memcpy(hist + (size_t)2 * n * info->iters + n, rt, sizeof(double) * n);
+        }
+        apply_prec(n, diag, r, z);
+        apply_prec(n, diag, rt, zt);
+        double rho = dot(n, z, rt);
+        if (!isfinite(rho)) { info->status = ORC_NONFINITE; break; }
+        if (rho == 0.0) { info->status = ORC_BREAKDOWN; break; }
+        if (first) {
+            memcpy(p, z, sizeof(double) * n);
+            memcpy(pt, zt, sizeof(double) * n);
+            first = 0;
+        } else {
+            double beta = rho / rho_prev;
+            for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            for (int32_t i = 0; i < n; ++i) pt[i] = zt[i] + beta * pt[i];
+        }
+        rho_prev = rho;
+        orc_csr_spmv(n, rowptr, col, val, p, q, 1.0, 0.0);
+        csr_spmv_t(n, rowptr, col, val, pt, qt);
+        info->iters += 1;
+        info->spmv_count += 2;
+        double ptq = dot(n, pt, q);
+        if (!isfinite(ptq)) { info->status = ORC_NONFINITE; break; }
+        if (ptq == 0.0) { info->status = ORC_BREAKDOWN; break; }
+        double alpha = rho / ptq;
+        for (int32_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        for (int32_t i = 0; i < n; ++i) rt[i] -= alpha * qt[i];
+        double rn = nrm2(n, r);
+        info->relres_recursive = rn / bn;
+        if (!isfinite(rn)) { info->status = ORC_NONFINITE; break; }
+        if (rn <= tol * bn) {
+            double tn = orc_residual(n, rowptr, col, val, b, x, r);
+            if (tn <= tol * bn) { info->status = ORC_OK; break; }
+            restart = 1;
+        }
+    }
+done:
+    info->relres_true = orc_residual(n, rowptr, col, val, b, x, NULL) / bn;
+out:
+    free(r); free(rt); free(z); free(zt); free(p); free(pt); free(q); free(qt); free(diag);
+    return info->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pipelined preconditioned CG (Ghysels & Vanroose, "Hiding global           */
+/* synchronization latency in the preconditioned Conjugate Gradient          */
+/* algorithm", Parallel Computing 40(7), 2014). The iterates of orc_cg in    */
+/* exact arithmetic, rearranged so that an iteration has a single reduction  */
+/* phase which can overlap the product with A. Kept alongside x and r:       */
+/* u = M^{-1} r, w = A u, and the directions p, s = A p, q = M^{-1} s,       */
+/* z = A q. Iteration i (M = diag(A) or the identity):                      */
+/*   gamma = r . u, delta = w . u;  m = M^{-1} w, nv = A m;                 */
+/*   i = 0: beta = 0, alpha = gamma / delta;                                */
+/*   else   beta = gamma / gamma_prev,                                      */
+/*          alpha = gamma / (delta - beta gamma / alpha_prev);              */
+/*   (a denominator <= 0 is a breakdown: it equals p . A p);                */
+/*   z = nv + beta z, q = m + beta q, s = w + beta s, p = u + beta p;       */
+/*   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z.                */
+/* Stopping as orc_cg on ||r||; a true residual that misses restarts the     */
+/* recurrences from it (u = M^{-1} r, w = A u, i = 0). One product per       */
+/* iteration plus one per (re)start.                                        */
+/* ------------------------------------------------------------------------ */
+int orc_pipecg(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+               const double *b, double *x, double tol, int32_t maxit, int32_t precond, int32_t x0_zero,
+               orc_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    size_t nb = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = malloc(nb), *u = malloc(nb), *w = malloc(nb), *m = malloc(nb), *nv = malloc(nb);
+    double *z = malloc(nb), *q = malloc(nb), *s = malloc(nb), *p = malloc(nb);
+    double *diag = precond ? malloc(nb) : NULL;
+    if (!r || !u || !w || !m || !nv || !z || !q || !s || !p || (precond && !diag)) {
+        info->status = ORC_ENOMEM;
+        goto out;
+    }
+    if (precond && orc_jacobi_setup(n, rowptr, col, val, diag) != ORC_OK) {
+        info->status = ORC_ZERO_DIAG;
+        goto out;
+    }
+    if (x0_zero) memset(x, 0, sizeof(double) * n);
+    double bn = nrm2(n, b);
+    if (!isfinite(bn)) { info->status = ORC_NONFINITE; goto out; }
+    if (bn == 0.0) { memset(x, 0, sizeof(double) * n); info->status = ORC_OK; goto out; }
+    orc_csr_spmv(n, rowptr, col, val, x, nv, 1.0, 0.0);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - nv[i];
+    info->status = ORC_NOT_CONVERGED;
+    if (nrm2(n, r) <= tol * bn) {
+        info->status = ORC_OK;
+        goto done;
+    }
+    int restart = 1, step = 0;
+    double gamma_prev = 1.0, alpha_prev = 1.0;
+    while (info->iters < maxit) {
+        if (restart) {
+            apply_prec(n, diag, r, u);
+            orc_csr_spmv(n, rowptr, col, val, u, w, 1.0, 0.0);
+            info->spmv_count += 1;
+            restart = 0;
+            step = 0;
+        }
+        double gamma = dot(n, r, u), delta = dot(n, w, u);
+        apply_prec(n, diag, w, m);
+        orc_csr_spmv(n, rowptr, col, val, m, nv, 1.0, 0.0);
+        info->iters += 1;
+        info->spmv_count += 1;
+        if (!isfinite(gamma) || !isfinite(delta)) { info->status = ORC_NONFINITE; break; }
+        double beta = 0.0, den = delta;
+        if (step > 0) {
+            beta = gamma / gamma_prev;
+            den = delta - beta * gamma / alpha_prev;
+        }
+        if (!isfinite(den)) { info->status = ORC_NONFINITE; break; }
+        if (den <= 0.0) { info->status = ORC_BREAKDOWN; break; }
+        double alpha = gamma / den;
+        if (step == 0) {
+            memcpy(z, nv, nb);
+            memcpy(q, m, nb);
+            memcpy(s, w, nb);
+            memcpy(p, u, nb);
+        } else {
+            for (int32_t i = 0; i < n; ++i) z[i] = nv[i] + beta * z[i];
+            for (int32_t i = 0; i < n; ++i) q[i] = m[i] + beta * q[i];
+            for (int32_t i = 0; i < n; ++i) s[i] = w[i] + beta * s[i];
+            for (int32_t i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
+        }
+        for (int32_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] -= alpha * s[i];
+        for (int32_t i = 0; i < n; ++i) u[i] -= alpha * q[i];
+        for (int32_t i = 0; i < n; ++i) w[i] -= alpha * z[i];
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+        step += 1;
+        double rn = nrm2(n, r);
+        info->relres_recursive = rn / bn;
+        if (!isfinite(rn)) { info->status = ORC_NONFINITE; break; }
+        if (rn <= tol * bn) {
+            double tn = orc_residual(n, rowptr, col, val, b, x, r);
+            if (tn <= tol * bn) { info->status = ORC_OK; break; }
+            restart = 1;
+        }
+    }
+done:
+    info->relres_true = orc_residual(n, rowptr, col, val, b, x, NULL) / bn;
+out:
+    free(r); free(u); free(w); free(m); free(nv); free(z); free(q); free(s); free(p); free(diag);
+    return info->status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Arnoldi with modified Gram-Schmidt (Saad, "Iterative Methods for Sparse   */
 /* Linear Systems", 2nd ed., 2003, Ch. 6). Column j of V (length n, column-  */
 /* major, n x (m+1)) is the j-th basis vector; H is (m+1) x m column-major.  */
