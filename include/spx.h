@@ -186,6 +186,20 @@ spx_status spx_convert(const spx_matrix *src, spx_matrix *dst, void *ws, size_t 
  * value overflowed to infinity (the values are still written). */
 spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hipStream_t stream);
 
+/* ------------------------------------------------------------ transpose
+ * At = A^T for a CSR matrix A (nrows x ncols, any value type), the product
+ * BiCG needs (Section 1 lists BiCG among the library's solvers). The caller
+ * fills At: fmt SPX_CSR, nrows = A->ncols, ncols = A->nrows, nnz = A->nnz,
+ * the same val_type, and device arrays it owns: rowptr (A->ncols + 1 int32),
+ * colidx (nnz int32), vals (nnz values); At->csr_part may be NULL. Rows of
+ * At come out sorted by column (A's row index) and values are copied bit for
+ * bit; the result does not depend on scheduling. Column indices of A must
+ * lie in [0, ncols) (else At is wrong but every access stays in bounds).
+ * Needs spx_csr_transpose_workspace bytes of device workspace; asynchronous
+ * on stream. Errors: SPX_ERR_ARG (descriptors, shapes, workspace). */
+spx_status spx_csr_transpose_workspace(const spx_matrix *A, size_t *bytes);
+spx_status spx_csr_transpose(const spx_matrix *A, spx_matrix *At, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------ Krylov solvers
  * Solve A x = b to the relative residual ||b - A x||_2 <= tol * ||b||_2
  * (Section 4 runs CG; Section 1 lists CG, BiCG-type and GMRES solvers with
@@ -209,7 +223,13 @@ spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hipStream_t s
  * SPX_ERR_BREAKDOWN (CG: p'Ap <= 0; BiCGSTAB: rhat'r = 0, rhat'v = 0, t't = 0
  * or omega = 0), SPX_ERR_NONFINITE (NaN/Inf in a residual norm),
  * SPX_ERR_NOT_CONVERGED (maxit reached; x holds the last iterate). */
-typedef enum { SPX_SOLVER_CG = 0, SPX_SOLVER_BICGSTAB = 1, SPX_SOLVER_GMRES = 2 } spx_solver;
+typedef enum {
+    SPX_SOLVER_CG = 0,
+    SPX_SOLVER_BICGSTAB = 1,
+    SPX_SOLVER_GMRES = 2,
+    SPX_SOLVER_BICG = 3,
+    SPX_SOLVER_PIPECG = 4
+} spx_solver;
 
 typedef struct {
     double tol;          /* relative residual target (e.g. 1e-10)                 */
@@ -241,6 +261,26 @@ spx_status spx_bicgstab_solve(const spx_matrix *A, const double *b, double *x, c
 
 spx_status spx_gmres_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
                            size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
+
+/* Preconditioned BiCG (Section 1 lists BiCG among the library's solvers; the
+ * form of Barrett et al., "Templates", 1994): shadow residual rt = r at the
+ * start, precond 0 or 1 (scalar Jacobi; M^-T = M^-1). Each iteration
+ * multiplies by A and by A^T; A^T is built in the workspace at the start of
+ * every solve (spx_csr_transpose), so A must be CSR. info->spmv_count counts
+ * both products. Breakdown: rho = (M^-1 r).rt = 0 or pt.(A p) = 0. Otherwise
+ * as spx_cg_solve (BLOCKING, same errors). */
+spx_status spx_bicg_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
+                          size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
+
+/* Pipelined preconditioned CG (Ghysels & Vanroose, Parallel Computing
+ * 40(7), 2014): CG's iterates in exact arithmetic with one reduction phase
+ * per iteration that does not wait for the product with A; three launches
+ * per iteration against CG's five, more vector traffic. precond 0 or 1, any
+ * matrix format. info->spmv_count includes the product w = A u of every
+ * (re)start. Breakdown: p.Ap <= 0 (the step's denominator). Otherwise as
+ * spx_cg_solve (BLOCKING, same errors). */
+spx_status spx_pipecg_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts, void *ws,
+                            size_t ws_bytes, spx_solve_info *info, hipStream_t stream);
 
 /* ------------------------------------------------------------ mixed-precision iterative refinement
  * Solve A x = b to ||b - A x|| <= tol ||b|| in float64 with float32 inner

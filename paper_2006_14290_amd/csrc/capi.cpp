@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "convert.hpp"
+#include "transpose.hpp"
 #include "spmv.hpp"
 #include "spmv_csr.hpp"
 
@@ -194,6 +195,29 @@ extern "C" spx_status spx_convert(const spx_matrix *src, spx_matrix *dst, void *
                 SPX_ERR_ARG, "spx_convert: dst shape or dtype differs from src");
     SPX_REQUIRE(dst->fmt != SPX_COO || dst->nnz == src->nnz, SPX_ERR_ARG, "spx_convert: dst nnz differs from plan");
     return convert_run(*src, *dst, ws, ws_bytes, stream);
+}
+
+extern "C" spx_status spx_csr_transpose_workspace(const spx_matrix *A, size_t *bytes)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_csr_transpose_workspace"));
+    SPX_REQUIRE(bytes != nullptr, SPX_ERR_ARG, "spx_csr_transpose_workspace: null bytes");
+    SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "spx_csr_transpose_workspace: the matrix must be CSR");
+    *bytes = (size_t)transpose_ws_bytes(A->nnz);
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_csr_transpose(const spx_matrix *A, spx_matrix *At, void *ws, size_t ws_bytes,
+                                        hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_csr_transpose"));
+    SPX_CHECK(check_matrix(At, "spx_csr_transpose (At)"));
+    SPX_REQUIRE(A->fmt == SPX_CSR && At->fmt == SPX_CSR, SPX_ERR_ARG, "spx_csr_transpose: both matrices must be CSR");
+    SPX_REQUIRE(At->nrows == A->ncols && At->ncols == A->nrows && At->nnz == A->nnz && At->val_type == A->val_type,
+                SPX_ERR_ARG, "spx_csr_transpose: At must be ncols x nrows with the same nnz and val_type");
+    SPX_REQUIRE(A->ncols <= INT32_MAX && A->nrows <= INT32_MAX, SPX_ERR_ARG, "spx_csr_transpose: too many rows");
+    return transpose_run(*A, *At, ws, ws_bytes, stream);
 }
 
 extern "C" spx_status spx_cast_values(const spx_matrix *src, spx_matrix *dst, hipStream_t stream)

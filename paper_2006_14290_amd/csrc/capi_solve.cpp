@@ -44,6 +44,8 @@ extern "C" spx_status spx_solve_workspace(int32_t solver, const spx_matrix *A, c
         SPX_REQUIRE(opts->restart >= 1 && opts->restart <= 62, SPX_ERR_ARG, "GMRES restart must be in [1, 62]");
         *bytes = gmres_workspace(*A, opts->precond, opts->restart);
         return SPX_OK;
+    case SPX_SOLVER_BICG: *bytes = bicg_workspace(*A, opts->precond); return SPX_OK;
+    case SPX_SOLVER_PIPECG: *bytes = pipecg_workspace(*A, opts->precond); return SPX_OK;
     default: break;
     }
     set_error("spx_solve_workspace: unknown solver %d", solver);
@@ -128,4 +130,31 @@ extern "C" spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow
     }
     return ir_run(*A64, *Alow, b, x, opts->tol, opts->inner_tol, opts->max_outer, opts->inner_maxit,
                   opts->check_every, ws, ws_bytes, info, stream);
+}
+
+extern "C" spx_status spx_bicg_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts,
+                                     void *ws, size_t ws_bytes, spx_solve_info *info, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_solve(A, b, x, opts, info, "spx_bicg_solve"));
+    SPX_REQUIRE(A->val_type == SPX_F64, SPX_ERR_ARG, "spx_bicg_solve: matrix values must be SPX_F64");
+    SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "spx_bicg_solve: the matrix must be CSR (A^T is built from it)");
+    if (A->nrows == 0) {
+        *info = spx_solve_info{};
+        return SPX_OK;
+    }
+    return bicg_run(*A, b, x, spec_of(opts), ws, ws_bytes, info, stream);
+}
+
+extern "C" spx_status spx_pipecg_solve(const spx_matrix *A, const double *b, double *x, const spx_solve_opts *opts,
+                                       void *ws, size_t ws_bytes, spx_solve_info *info, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_solve(A, b, x, opts, info, "spx_pipecg_solve"));
+    SPX_REQUIRE(A->val_type == SPX_F64, SPX_ERR_ARG, "spx_pipecg_solve: matrix values must be SPX_F64");
+    if (A->nrows == 0) {
+        *info = spx_solve_info{};
+        return SPX_OK;
+    }
+    return pipecg_run(*A, b, x, spec_of(opts), ws, ws_bytes, info, stream);
 }

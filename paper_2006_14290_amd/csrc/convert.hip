@@ -181,6 +181,14 @@ __global__ __launch_bounds__(kCvThreads) void csr_rows_kernel(const int32_t *__r
     }
 }
 
+spx_status csr_rows_launch(const int32_t *rowptr, int32_t n, int32_t *row_out, hipStream_t stream)
+{
+    if (n <= 0) return SPX_OK;
+    csr_rows_kernel<<<(unsigned)ceil_div(n, kCvThreads), kCvThreads, 0, stream>>>(rowptr, n, row_out);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
 // ------------------------------------------------------------------ COO -> CSR
 __global__ __launch_bounds__(kCvThreads) void coo_rowptr_kernel(const int32_t *__restrict__ row, int64_t nnz,
                                                                int32_t n, int32_t *__restrict__ rowptr)

@@ -40,6 +40,11 @@ enum KOp : int32_t {
     kOpNorm2,      // t0 = w.w -> tmp[0]
     kOpCgRestart,  // t0 = r.z: restart the recurrences from the current r
     kOpBiRestart,  // t0 = r.r: restart BiCGSTAB with rhat = r
+    kOpBicgAlpha,  // t0 = pt.q (BiCG)
+    kOpBicgRho,    // t0 = (M^-1 r).rt, t1 = r.r (BiCG)
+    kOpPipeInit,   // t0 = b.b, t1 = r.r (pipelined CG start)
+    kOpPipeRestart,  // t0 = r.r: restart pipelined CG from the current r
+    kOpPipeStep,   // t0 = r.u, t1 = w.u, t2 = r.r (pipelined CG iteration)
 };
 
 constexpr int kMaxDots = 64;  // GMRES restart length + 2 (multi-dot width)
@@ -133,6 +138,74 @@ __device__ inline void finish_op(int op, const double *t, KState *st)
             if (st->iters >= st->maxit) st->flag = kMaxit;
         }
         break;
+    case kOpBicgAlpha:
+        if (!finite(t[0])) st->flag = kNonfinite;
+        else if (t[0] == 0.0 || st->rho == 0.0) st->flag = kBreakdown;
+        else st->alpha = st->rho / t[0];
+        break;
+    case kOpBicgRho:
+        st->iters += 1;
+        st->spmv_count += 2;
+        st->rr = t[1];
+        if (!finite(t[1]) || !finite(t[0])) {
+            st->flag = kNonfinite;
+        } else if (t[1] <= st->tol2 * st->bb) {
+            st->flag = kConverged;
+        } else if (t[0] == 0.0) {
+            st->flag = kBreakdown;
+        } else {
+            st->beta = t[0] / st->rho;
+            st->rho = t[0];
+            if (st->iters >= st->maxit) st->flag = kMaxit;
+        }
+        break;
+    case kOpPipeInit:
+        st->bb = t[0];
+        st->rr = t[1];
+        st->restart_j = 0;
+        if (!finite(t[0]) || !finite(t[1])) st->flag = kNonfinite;
+        else if (t[0] == 0.0) st->flag = kZeroRhs;
+        else if (t[1] <= st->tol2 * t[0]) st->flag = kConverged;
+        break;
+    case kOpPipeRestart:
+        st->rr = t[0];
+        st->restart_j = 0;
+        st->flag = finite(t[0]) ? kRunning : kNonfinite;
+        break;
+    case kOpPipeStep: {
+        // t0 = gamma = r.u, t1 = delta = w.u of the current residual; the
+        // previous gamma and alpha are in rho and alpha; restart_j counts
+        // steps since the (re)start
+        st->rr = t[2];
+        if (!finite(t[0]) || !finite(t[1]) || !finite(t[2])) {
+            st->flag = kNonfinite;
+            break;
+        }
+        if (t[2] <= st->tol2 * st->bb) {
+            st->flag = kConverged;
+            break;
+        }
+        if (st->iters >= st->maxit) {
+            st->flag = kMaxit;
+            break;
+        }
+        double beta = 0.0, den = t[1];
+        if (st->restart_j > 0) {
+            beta = t[0] / st->rho;
+            den = t[1] - beta * t[0] / st->alpha;
+        }
+        if (!finite(den)) st->flag = kNonfinite;
+        else if (den <= 0.0) st->flag = kBreakdown;
+        else {
+            st->alpha = t[0] / den;
+            st->beta = beta;
+            st->rho = t[0];
+            st->restart_j += 1;
+            st->iters += 1;
+            st->spmv_count += 1;
+        }
+        break;
+    }
     case kOpNorm2:
         st->tmp[0] = t[0];
         break;
@@ -184,7 +257,8 @@ __device__ __forceinline__ void write_partials(const T (&v)[NV], T *__restrict__
 // (their producing kernels skipped too); setup ops always run.
 __device__ __forceinline__ bool op_runs_when_stopped(int op)
 {
-    return op == kOpCgInit || op == kOpBiInit || op == kOpNorm2 || op == kOpCgRestart || op == kOpBiRestart;
+    return op == kOpCgInit || op == kOpBiInit || op == kOpNorm2 || op == kOpCgRestart || op == kOpBiRestart ||
+           op == kOpPipeInit || op == kOpPipeRestart;
 }
 
 constexpr int kFinThreads = 256;

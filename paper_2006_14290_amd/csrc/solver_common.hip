@@ -81,6 +81,27 @@ __global__ __launch_bounds__(kVecThreads) void fill_vec_kernel(X *a, int64_t n, 
     if (i < n) a[i] = v;
 }
 
+template <typename X>
+spx_status fill_vector(X *a, int64_t n, X v, hipStream_t stream)
+{
+    if (n <= 0) return SPX_OK;
+    fill_vec_kernel<X><<<(unsigned)ceil_div(n, kVecThreads), kVecThreads, 0, stream>>>(a, n, v);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+template spx_status fill_vector<double>(double *, int64_t, double, hipStream_t);
+template spx_status fill_vector<float>(float *, int64_t, float, hipStream_t);
+
+template <typename V, typename X>
+spx_status spmv_st(const spx_matrix &A, const X *x, X *y, KState *st, hipStream_t stream)
+{
+    if (A.fmt == SPX_CSR) return csr_spmv_launch<V, X>(A, x, y, X(1), X(0), nullptr, nullptr, stream, 0, st);
+    if (A.fmt == SPX_SELLP) return sellp_spmv_launch<V, X>(A, x, y, X(1), X(0), stream, 0, nullptr, nullptr, st);
+    if (A.fmt == SPX_ELL) return ell_spmv_launch<V, X>(A, x, y, X(1), X(0), stream, 0, nullptr, nullptr, st);
+    return spmv_dispatch(A, x, y, 1.0, 0.0, stream);
+}
+template spx_status spmv_st<double, double>(const spx_matrix &, const double *, double *, KState *, hipStream_t);
+
 template <typename V, typename X>
 __global__ __launch_bounds__(kVecThreads) void diag_csr_kernel(const int32_t *__restrict__ rowptr,
                                                               const int32_t *__restrict__ col,

@@ -65,6 +65,15 @@ spx_status read_state(SolveEnv *env, const KState *dst, KState *out);
 spx_status state_init(KState *st, double tol, int32_t maxit, hipStream_t stream);
 spx_status state_set_flag(KState *st, int32_t flag, hipStream_t stream);
 
+// a[0..n) = v (a kernel, so it can be captured).
+template <typename X>
+spx_status fill_vector(X *a, int64_t n, X v, hipStream_t stream);
+
+// y = A x for any format; with a solver state, a set flag skips the product
+// (CSR, ELL and SELL-P kernels; other formats always run).
+template <typename V, typename X>
+spx_status spmv_st(const spx_matrix &A, const X *x, X *y, KState *st, hipStream_t stream);
+
 // dinv = 1 / diag(A) for any format; sets st->flag = kBreakdown on a zero,
 // missing or non-finite diagonal entry (checked by the caller after a read).
 template <typename V, typename X>

@@ -40,6 +40,14 @@ size_t gmres_workspace(const spx_matrix &A, int precond, int restart);
 spx_status gmres_run(const spx_matrix &A, const double *b, double *x, const SolveSpec &sp, void *ws,
                      size_t ws_bytes, spx_solve_info *info, hipStream_t user_stream);
 
+size_t bicg_workspace(const spx_matrix &A, int precond);
+spx_status bicg_run(const spx_matrix &A, const double *b, double *x, const SolveSpec &sp, void *ws,
+                    size_t ws_bytes, spx_solve_info *info, hipStream_t user_stream);
+
+size_t pipecg_workspace(const spx_matrix &A, int precond);
+spx_status pipecg_run(const spx_matrix &A, const double *b, double *x, const SolveSpec &sp, void *ws,
+                      size_t ws_bytes, spx_solve_info *info, hipStream_t user_stream);
+
 size_t ir_workspace(const spx_matrix &A64, const spx_matrix &Alow);
 spx_status ir_run(const spx_matrix &A64, const spx_matrix &Alow, const double *b, double *x, double tol,
                   double inner_tol, int32_t max_outer, int32_t inner_maxit, int32_t check_every, void *ws,

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kThreads) void csr_spmv_kernel(
     X alpha, X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, const int32_t *__restrict__ part,
     KState *__restrict__ st, int op)
 {
-    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    if (st != nullptr && st->flag != kRunning) return;
     const int64_t k = xcd_remap(blockIdx.x, grid_padded);
     if (k >= ntiles) return;
     csr_tile<V, X, kEpi, kThreads, kTile, kVec, kLate>(k, nrows, nnz, ntiles, rowptr, col, val, x, y, alpha, beta,
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kRowThreads) void csr_rows_kernel(
     const int32_t *__restrict__ col, const V *__restrict__ val, const X *__restrict__ x, X *__restrict__ y, X alpha,
     X beta, const X *__restrict__ dot_with, X *__restrict__ dot_partials, KState *__restrict__ st)
 {
-    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    if (st != nullptr && st->flag != kRunning) return;
     constexpr int kSubs = kRowThreads / kSub;
     constexpr int64_t kStep = (int64_t)kSubs * kRowU;  // rows per block iteration
     const int64_t blk = xcd_remap(blockIdx.x, grid_padded);

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, in
                                                                const X *__restrict__ dot_with,
                                                                X *__restrict__ partials, const KState *st)
 {
-    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    if (st != nullptr && st->flag != kRunning) return;
     typedef int32_t CR __attribute__((ext_vector_type(kR)));
     typedef V VR __attribute__((ext_vector_type(kR)));
     const int64_t nblocks = ((int64_t)nrows + kEllThreads * kR - 1) / (kEllThreads * kR);
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows,
                                                                  const X *__restrict__ dot_with,
                                                                  X *__restrict__ partials, const KState *st)
 {
-    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    if (st != nullptr && st->flag != kRunning) return;
     __shared__ X part[kSellThreads];
     const int64_t s = xcd_remap(blockIdx.x, grid_padded);
     if (s >= nslices) return;
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kSellThreads) void sellp64_spmv_kernel(int32_t nrow
                                                                    X alpha, X beta, const X *__restrict__ dot_with,
                                                                    X *__restrict__ partials, const KState *st)
 {
-    if (kEpi > 0 && st != nullptr && st->flag != kRunning) return;
+    if (st != nullptr && st->flag != kRunning) return;
     constexpr int kSlices = kSellThreads / kWave;  // slices per work-group
     const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
     const int64_t nblocks = (nslices + kSlices - 1) / kSlices;

@@ -73,6 +73,8 @@ _sig("spx_csr_analyse", [_MP, _vp, ctypes.c_size_t, _vp])
 _sig("spx_convert_plan", [_MP, _i32, _i32, _i64, _MP, ctypes.POINTER(ctypes.c_size_t), _vp])
 _sig("spx_convert", [_MP, _MP, _vp, ctypes.c_size_t, _vp])
 _sig("spx_cast_values", [_MP, _MP, _vp])
+_sig("spx_csr_transpose_workspace", [_MP, ctypes.POINTER(ctypes.c_size_t)])
+_sig("spx_csr_transpose", [_MP, _MP, _vp, ctypes.c_size_t, _vp])
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32),
@@ -93,11 +95,11 @@ class IrOpts(ctypes.Structure):
                 ("inner_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-SOLVER_CG, SOLVER_BICGSTAB, SOLVER_GMRES = 0, 1, 2
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_GMRES, SOLVER_BICG, SOLVER_PIPECG = 0, 1, 2, 3, 4
 _SOP = ctypes.POINTER(SolveOpts)
 _SIP = ctypes.POINTER(SolveInfo)
 _sig("spx_solve_workspace", [_i32, _MP, _SOP, ctypes.POINTER(ctypes.c_size_t)])
-for _nm in ("spx_cg_solve", "spx_bicgstab_solve", "spx_gmres_solve"):
+for _nm in ("spx_cg_solve", "spx_bicgstab_solve", "spx_gmres_solve", "spx_bicg_solve", "spx_pipecg_solve"):
     _sig(_nm, [_MP, _vp, _vp, _SOP, _vp, ctypes.c_size_t, _SIP, _vp])
 _sig("spx_ir_workspace", [_MP, _MP, ctypes.POINTER(ctypes.c_size_t)])
 _sig("spx_ir_solve", [_MP, _MP, _vp, _vp, ctypes.POINTER(IrOpts), _vp, ctypes.c_size_t, _SIP, _vp])
@@ -353,7 +355,8 @@ def spmv(A: Matrix, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: fl
 
 
 # ------------------------------------------------------------------ solvers
-_SOLVER_FN = {SOLVER_CG: "spx_cg_solve", SOLVER_BICGSTAB: "spx_bicgstab_solve", SOLVER_GMRES: "spx_gmres_solve"}
+_SOLVER_FN = {SOLVER_CG: "spx_cg_solve", SOLVER_BICGSTAB: "spx_bicgstab_solve", SOLVER_GMRES: "spx_gmres_solve",
+              SOLVER_BICG: "spx_bicg_solve", SOLVER_PIPECG: "spx_pipecg_solve"}
 _ws_cache = {}
 
 
@@ -401,6 +404,33 @@ def bicgstab_solve(A, b, x=None, **kw):
 
 def gmres_solve(A, b, x=None, **kw):
     return solve(SOLVER_GMRES, A, b, x, **kw)
+
+
+def bicg_solve(A, b, x=None, **kw):
+    return solve(SOLVER_BICG, A, b, x, **kw)
+
+
+def pipecg_solve(A, b, x=None, **kw):
+    return solve(SOLVER_PIPECG, A, b, x, **kw)
+
+
+def csr_transpose(A: Matrix, stream=None) -> Matrix:
+    """A^T of a CSR matrix as a new device CSR matrix (asynchronous on stream)."""
+    if A.fmt != CSR:
+        raise SpxError(ERR_ARG, "csr_transpose: the matrix must be CSR")
+    dev = A.rowptr.device
+    At = Matrix(CSR, A.dtype, A.ncols, A.nrows, A.nnz,
+                rowptr=torch.empty(A.ncols + 1, dtype=torch.int32, device=dev),
+                colidx=torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev),
+                vals=torch.empty(max(A.nnz, 1), dtype=A.vals.dtype, device=dev))
+    d, dt = A.desc(), At.desc()
+    nbytes = ctypes.c_size_t(0)
+    check(_lib.spx_csr_transpose_workspace(ctypes.byref(d), ctypes.byref(nbytes)), "spx_csr_transpose_workspace")
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+    check(_lib.spx_csr_transpose(ctypes.byref(d), ctypes.byref(dt), _ptr(ws), ws.numel(), _stream(stream)),
+          "spx_csr_transpose")
+    At._ws = ws  # keep the workspace alive until the stream has used it
+    return At
 
 
 def ir_solve(A64: Matrix, Alow: Matrix, b: torch.Tensor, tol: float = 1e-10, inner_tol: float = 1e-3,
