@@ -283,6 +283,23 @@ def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
     out = {"spmv": spmv_lat, "single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
                       "relres_true": info["relres_true"]}}
+    # the same blocking solves with pipelined CG (three launches per
+    # iteration against five: the small system is launch-bound)
+    for _ in range(3):
+        spx.pipecg_solve(Ad, bd, tol=1e-10)
+    torch.cuda.synchronize()
+    plat = []
+    t0 = time.perf_counter()
+    for _ in range(nsolves):
+        t1 = time.perf_counter()
+        x, pinfo = spx.pipecg_solve(Ad, bd, tol=1e-10)
+        plat.append(time.perf_counter() - t1)
+        assert pinfo["status"] == 0 and pinfo["relres_true"] <= 1e-10, pinfo
+    ptot = time.perf_counter() - t0
+    plat = np.array(plat) * 1e3
+    out["single_pipecg"] = {"solves_per_s": round(nsolves / ptot, 2), "p50_ms": round(float(np.percentile(plat, 50)), 3),
+                            "p99_ms": round(float(np.percentile(plat, 99)), 3), "iters": pinfo["iters"],
+                            "solves": nsolves, "relres_true": pinfo["relres_true"]}
     if nbatch > 0:
         bs = [rhs(spx, S, torch, Ad, seed=s) for s in range(nbatch)]
         spx.cg_batch([Ad] * nbatch, bs, tol=1e-10)
@@ -317,6 +334,15 @@ def bench_solvers(spx, S, torch, dev):
                                  "us_per_iter": round(it_us, 2),
                                  "GBs": round(cg_iter_bytes(A.n, A.nnz, 8, True) / it_us / 1e3, 1),
                                  "relres_true": info["relres_true"]}
+    t_cg = info["device_ms"]
+    # pipelined CG on the same system: one reduction phase per iteration,
+    # more vector traffic
+    spx.pipecg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+    x, info = spx.pipecg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
+    out["pipecg_jacobi_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
+                                     "us_per_iter": round(1e3 * info["device_ms"] / max(info["iters"], 1), 2),
+                                     "time_vs_cg": round(info["device_ms"] / t_cg, 3),
+                                     "relres_true": info["relres_true"]}
     # block Jacobi (8 x 8 and 32 x 32 diagonal blocks) on the same system
     for bs in (8, 32):
         spx.cg_solve(Ad, bd, tol=1e-10, precond=bs, maxit=5000)
@@ -335,7 +361,22 @@ def bench_solvers(spx, S, torch, dev):
     A = S.convdiff3d_upwind(128)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
     bd = rhs(spx, S, torch, Ad)
-    for nm, fn in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve), ("gmres30_jacobi_convdiff128", spx.gmres_solve)):
+    # device transpose (BiCG builds A^T once per solve)
+    spx.csr_transpose(Ad)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tms = []
+    for _ in range(10):
+        e0.record()
+        spx.csr_transpose(Ad)
+        e1.record()
+        torch.cuda.synchronize()
+        tms.append(e0.elapsed_time(e1))
+    tmin = 2 * (4 * (A.n + 1) + 12 * A.nnz)  # read A, write A^T
+    out["csr_transpose_convdiff128"] = {"ms_p50": round(float(np.median(tms)), 3), "nnz": A.nnz,
+                                        "GBs_min_bytes": round(tmin / float(np.median(tms)) / 1e6, 1)}
+    for nm, fn in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve), ("gmres30_jacobi_convdiff128", spx.gmres_solve),
+                   ("bicg_jacobi_convdiff128", spx.bicg_solve)):
         fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
         x, info = fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
         out[nm] = {"ms": round(info["device_ms"], 2), "iters": info["iters"], "spmv": info["spmv_count"],

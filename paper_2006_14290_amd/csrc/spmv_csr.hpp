@@ -7,6 +7,7 @@ namespace spx {
 
 constexpr int kCsrThreads = 256;  // work-group size (4 wavefronts)
 constexpr int kCsrTile = 2048;    // nonzeros per tile and per LDS pass
+constexpr int kCsrSlack = 64;     // a pass may run this many entries past its tile
 constexpr bool kCsrLateGather = true;  // gather x while reducing rows (see csr_spmv_kernel)
 constexpr int kRowThreads = 256;  // row-per-subwarp kernel: work-group size
 constexpr int kRowU = 4;          // rows per subwarp in the row-per-subwarp kernel

@@ -4,6 +4,7 @@
 
 #include "common.hpp"
 #include "krylov.hpp"
+#include "spmv_csr.hpp"
 #include "wave.hpp"
 
 namespace spx {
@@ -65,11 +66,17 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
     // the rows are reduced (a subwarp's lanes then sit on neighbouring rows,
     // so a gather instruction touches few cache lines on banded matrices);
     // otherwise the products are formed while staging.
-    constexpr size_t kLdsBytes = kLate ? (size_t)kTile * (sizeof(int32_t) + sizeof(V)) : (size_t)kTile * sizeof(A);
+    // kSlack extra entries let a pass run up to kSlack entries past the
+    // tile, so the row that crosses into the next tile usually finishes in
+    // the same pass instead of costing a second round of loads
+    constexpr int kSlack = kCsrSlack;
+    constexpr int kStage = kTile + kSlack;
+    static_assert(kSlack % kVec == 0 && kSlack / kVec <= kThreads, "slack must split into whole vectors");
+    constexpr size_t kLdsBytes = kLate ? (size_t)kStage * (sizeof(int32_t) + sizeof(V)) : (size_t)kStage * sizeof(A);
     __shared__ __align__(16) unsigned char s_raw[kLdsBytes];
     A *prod = reinterpret_cast<A *>(s_raw);
     V *s_val = reinterpret_cast<V *>(s_raw);
-    int32_t *s_col = reinterpret_cast<int32_t *>(s_raw + (size_t)kTile * sizeof(V));
+    int32_t *s_col = reinterpret_cast<int32_t *>(s_raw + (size_t)kStage * sizeof(V));
     __shared__ int32_t s_rp[kThreads + 1];
     __shared__ int64_t s_b[4];
     __shared__ A s_carry;
@@ -118,7 +125,7 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
         // are loaded only as far as they share a vector with ours, and are
         // never summed.
         const int64_t a0 = w0 & ~(int64_t)(kVec - 1);
-        const int64_t w1 = (e - a0 > kTile) ? a0 + kTile : e;
+        const int64_t w1 = (e - a0 > kStage) ? a0 + kTile : e;
         const bool last = (w1 == e);
         __syncthreads();  // s_carry / prod / s_rp of the previous pass are consumed
         const A carry_in = s_carry;
@@ -141,6 +148,19 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
                 }
             }
         }
+        // the slack entries [a0 + kTile, w1), one vector per thread
+        CV cs;
+        VV vs;
+        const int64_t sbase = a0 + kTile + (int64_t)tid * kVec;
+        const bool slack = tid < kSlack / kVec && sbase < w1;
+        if (slack) {
+#pragma unroll
+            for (int j = 0; j < kVec; ++j) {
+                const bool ok = sbase + j < w1;
+                cs[j] = ok ? col[sbase + j] : 0;
+                vs[j] = ok ? val[sbase + j] : V(0);
+            }
+        }
         int64_t row_t = r + tid;
         int32_t rp_t = 0, rp_t1 = 0;
         if (row_t < rb) {
@@ -159,6 +179,18 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
 #pragma unroll
                 for (int j = 0; j < kVec; ++j) pv[j] = (base + j < w1) ? widen(vv[u][j]) * x[cc[u][j]] : A(0);
                 *reinterpret_cast<AV *>(&prod[(u * kThreads + tid) * kVec]) = pv;
+            }
+        }
+        if (slack) {
+            if constexpr (kLate) {
+                *reinterpret_cast<VV *>(&s_val[kTile + tid * kVec]) = vs;
+                *reinterpret_cast<CV *>(&s_col[kTile + tid * kVec]) = cs;
+            } else {
+                typedef A AV __attribute__((ext_vector_type(kVec)));
+                AV pv;
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) pv[j] = (sbase + j < w1) ? widen(vs[j]) * x[cs[j]] : A(0);
+                *reinterpret_cast<AV *>(&prod[kTile + tid * kVec]) = pv;
             }
         }
         // rows of this pass, in batches of up to kThreads rows
