@@ -13,6 +13,8 @@ spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alp
 constexpr int kCooThreads = 256;
 constexpr int kCooTiles = 4;                      // 64-entry tiles per wavefront chunk
 constexpr int kCooChunk = 64 * kCooTiles;          // entries per wavefront chunk
+constexpr int64_t kCooTargetSpans = 16384;         // wavefront spans to aim for
+constexpr int64_t kCooMaxSpan = 8;                 // chunks per span at most
 constexpr int kEllThreads = 256;
 constexpr int kSellThreads = 256;
 

@@ -1,14 +1,15 @@
 // spmv_formats.hip -- COO, ELL and hybrid ELL+COO products for gfx950.
 //
 // COO (Section 4: the Coo product "relies on atomic operations"): entries
-// sorted by row are cut into wavefront chunks of kCooChunk entries. A
-// wavefront walks its chunk in 64-entry tiles: coalesced loads of row, column
-// and value, gathered x, then one segmented inclusive scan across the 64
-// lanes (DPP row shifts + row broadcasts, wave.hpp) keyed by the row index.
-// The last segment of a tile is carried in registers into the next tile.
-// A row wholly inside a chunk is written with a plain store; a row that
-// crosses a chunk boundary is accumulated with a float atomic add after a
-// small pre-pass has set it to beta*y (the only non-deterministic order).
+// sorted by row are cut into wavefront spans of a few chunks of kCooChunk
+// entries. A wavefront walks its span chunk by chunk (all loads of a chunk
+// issued first) in 64-entry tiles: coalesced loads of row, column and value,
+// gathered x, then one segmented inclusive scan across the 64 lanes (DPP row
+// shifts + row broadcasts, wave.hpp) keyed by the row index. The last segment
+// of a tile is carried in registers into the next tile and chunk. A row
+// wholly inside a span is written with a plain store; a row that crosses a
+// span boundary is accumulated with a float atomic add after a small pre-pass
+// has set it to beta*y (the only non-deterministic order).
 // Rows without entries (gaps between consecutive row indices) are written
 // beta*y by the chunk that sees the gap.
 //
@@ -36,17 +37,17 @@ __device__ __forceinline__ X scaled(X v, X beta)
 // Pre-pass: a row crossing a chunk boundary is set to beta*y exactly once,
 // by the first boundary that falls strictly inside it.
 template <typename X>
-__global__ __launch_bounds__(256) void coo_split_init_kernel(int64_t nnz, int64_t nchunks,
+__global__ __launch_bounds__(256) void coo_split_init_kernel(int64_t nnz, int64_t nspans, int64_t span,
                                                             const int32_t *__restrict__ row, X *__restrict__ y,
                                                             X beta)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;  // boundary k*chunk, k >= 1
-    if (k >= nchunks) return;
-    const int64_t b = k * kCooChunk;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;  // boundary k*span, k >= 1
+    if (k >= nspans) return;
+    const int64_t b = k * span;
     const int32_t r = row[b];
-    if (row[b - 1] != r) return;                       // boundary between rows: no split
-    if (k >= 2 && row[b - kCooChunk - 1] == r) return;  // an earlier boundary is inside r too
-    y[r] = scaled(y[r], beta);
+    if (row[b - 1] != r) return;                  // boundary between rows: no split
+    if (k >= 2 && row[b - span - 1] == r) return;  // an earlier boundary is inside r too
+    y[r] = beta == X(0) ? X(0) : beta * y[r];
 }
 
 template <typename X>
@@ -59,7 +60,9 @@ __global__ __launch_bounds__(256) void scale_kernel(int64_t n, X *__restrict__ y
 // Complete segment (row r, sum) of chunk [c0, c1): atomics if it may share
 // its row with a neighbouring chunk. row_before / row_after are the rows of
 // the entries just outside the chunk (-1 if none).
-template <typename X, bool kAccumulate>
+// kBetaZero: beta == 0, so y is written without being read (no dependent
+// load in the tile loop).
+template <typename X, bool kAccumulate, bool kBetaZero>
 __device__ __forceinline__ void coo_write(int32_t r, X sum, bool chunk_start_seg, bool chunk_end_seg,
                                           int32_t row_before, int32_t row_after, X *__restrict__ y, X alpha, X beta)
 {
@@ -69,99 +72,112 @@ __device__ __forceinline__ void coo_write(int32_t r, X sum, bool chunk_start_seg
         unsafeAtomicAdd(y + r, alpha * sum);
     } else if (kAccumulate) {
         y[r] += alpha * sum;
+    } else if (kBetaZero) {
+        y[r] = alpha * sum;
     } else {
         y[r] = alpha * sum + scaled(y[r], beta);
     }
 }
 
-template <typename V, typename X, bool kAccumulate>
-__global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, int64_t nnz, int64_t nchunks,
-                                                               int64_t grid_padded, const int32_t *__restrict__ row,
+template <typename V, typename X, bool kAccumulate, bool kBetaZero>
+__global__ __launch_bounds__(kCooThreads) void coo_spmv_kernel(int32_t nrows, int64_t nnz, int64_t nspans,
+                                                               int64_t span, int64_t grid_padded,
+                                                               const int32_t *__restrict__ row,
                                                                const int32_t *__restrict__ col,
                                                                const V *__restrict__ val, const X *__restrict__ x,
                                                                X *__restrict__ y, X alpha, X beta)
 {
     const int lane = lane_id();
     const int64_t blk = xcd_remap(blockIdx.x, grid_padded);
-    const int64_t chunk = blk * (kCooThreads / kWave) + threadIdx.x / kWave;
-    if (chunk >= nchunks) return;
-    const int64_t c0 = chunk * kCooChunk;
-    const int64_t c1 = (c0 + kCooChunk < nnz) ? c0 + kCooChunk : nnz;
-
-    // issue every load of the chunk first (memory-level parallelism); the
-    // chunk base is wave-uniform so the loads use scalar base + 32-bit offsets
-    const int32_t *__restrict__ rowc = row + c0;
-    const int32_t *__restrict__ colc = col + c0;
-    const V *__restrict__ valc = val + c0;
-    const int cn = (int)(c1 - c0);
-    int32_t r[kCooTiles], c[kCooTiles];
-    X p[kCooTiles];
-#pragma unroll
-    for (int t = 0; t < kCooTiles; ++t) {
-        const int o = t * kWave + lane;
-        r[t] = -1;
-        c[t] = 0;
-        p[t] = X(0);
-        if (o < cn) {
-            r[t] = ld_stream(rowc + o);
-            c[t] = ld_stream(colc + o);
-            p[t] = widen(ld_stream(valc + o));
-        }
-    }
-    const int32_t row_before = c0 > 0 ? row[c0 - 1] : -1;
-    const int32_t row_after = c1 < nnz ? row[c1] : -1;
-#pragma unroll
-    for (int t = 0; t < kCooTiles; ++t)
-        if (r[t] >= 0) p[t] *= x[c[t]];
+    const int64_t w = blk * (kCooThreads / kWave) + threadIdx.x / kWave;
+    if (w >= nspans) return;
+    // this wavefront's span [s0, s1): consecutive chunks of kCooChunk entries
+    // whose open row is carried from chunk to chunk in registers; only rows
+    // crossing the span's ends need atomics
+    const int64_t s0 = w * span;
+    const int64_t s1 = (s0 + span < nnz) ? s0 + span : nnz;
+    const int32_t row_before = s0 > 0 ? row[s0 - 1] : -1;
+    const int32_t row_after = s1 < nnz ? row[s1] : -1;
 
     int32_t carry_row = -1;
     X carry_val = X(0);
-    bool carry_start = false;  // carried segment began at the chunk start
+    bool carry_start = false;  // carried segment began at the span start
+    for (int64_t c0 = s0; c0 < s1; c0 += kCooChunk) {
+        const int64_t c1 = (c0 + kCooChunk < s1) ? c0 + kCooChunk : s1;
+        // issue every load of the chunk first (memory-level parallelism); the
+        // chunk base is wave-uniform so the loads use scalar base + 32-bit offsets
+        const int32_t *__restrict__ rowc = row + c0;
+        const int32_t *__restrict__ colc = col + c0;
+        const V *__restrict__ valc = val + c0;
+        const int cn = (int)(c1 - c0);
+        int32_t r[kCooTiles], c[kCooTiles];
+        X p[kCooTiles];
 #pragma unroll
-    for (int t = 0; t < kCooTiles; ++t) {
-        const int64_t tb = c0 + t * kWave;
-        if (tb >= c1) break;
-        const int64_t e = tb + lane;
-        const bool valid = e < c1;
-        const int32_t rr = r[t];
-        const int32_t r0 = readlane(rr, 0);
-        // the carried segment ends before this tile: write it
-        if (carry_row >= 0 && r0 != carry_row) {
-            if (lane == 0)
-                coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, false, row_before, row_after, y, alpha,
-                                          beta);
-            carry_row = -1;
+        for (int t = 0; t < kCooTiles; ++t) {
+            const int o = t * kWave + lane;
+            r[t] = -1;
+            c[t] = 0;
+            p[t] = X(0);
+            if (o < cn) {
+                r[t] = ld_stream(rowc + o);
+                c[t] = ld_stream(colc + o);
+                p[t] = widen(ld_stream(valc + o));
+            }
         }
-        const bool merged = (carry_row >= 0);  // lane 0 continues the carried segment
-        const int32_t first_prev = (t == 0) ? row_before : readlane(r[t > 0 ? t - 1 : 0], kWave - 1);
-        const int32_t rprev = wave_shift_up1(rr, first_prev);
-        const bool head = !valid || lane == 0 || rr != rprev;
-        X v = p[t];
-        if (lane == 0 && merged) v += carry_val;
-        // gaps: rows strictly between the previous entry's row and this one are empty
-        if (!kAccumulate && valid && rr != rprev)
-            for (int32_t g = rprev + 1; g < rr; ++g) y[g] = scaled(y[g], beta);
-        if (!kAccumulate && valid && e == nnz - 1)
-            for (int32_t g = rr + 1; g < nrows; ++g) y[g] = scaled(y[g], beta);
-        const X s = wave_segscan(v, head);
-        // the last valid lane of the tile and the segment it closes are carried on
-        const int tail_e = (c1 - tb < kWave) ? (int)(c1 - tb - 1) : kWave - 1;
-        const lane_mask_t heads = ballot64(head && lane > 0);
-        const lane_mask_t upto_me = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
-        const bool seg0 = (heads & upto_me & ~1ull) == 0;  // my segment holds lane 0
-        const bool start_seg = seg0 && (t == 0 || (merged && carry_start));
-        // a lane closes a segment when the next lane starts a new one
-        const int32_t rn = wave_shift_down1(rr, -2);
-        if (lane < tail_e && rn != rr)
-            coo_write<X, kAccumulate>(rr, s, start_seg, false, row_before, row_after, y, alpha, beta);
-        carry_row = readlane(rr, tail_e);
-        carry_val = readlane(s, tail_e);
-        const lane_mask_t upto_tail = (tail_e == kWave - 1) ? ~0ull : ((2ull << tail_e) - 1);
-        const bool last_seg_has_lane0 = (heads & upto_tail & ~1ull) == 0;
-        carry_start = last_seg_has_lane0 && (t == 0 || (merged && carry_start));
+        const int32_t chunk_before = c0 > 0 ? row[c0 - 1] : -1;
+#pragma unroll
+        for (int t = 0; t < kCooTiles; ++t)
+            if (r[t] >= 0) p[t] *= x[c[t]];
+
+#pragma unroll
+        for (int t = 0; t < kCooTiles; ++t) {
+            const int64_t tb = c0 + t * kWave;
+            if (tb >= c1) break;
+            const int64_t e = tb + lane;
+            const bool valid = e < c1;
+            const int32_t rr = r[t];
+            const int32_t r0 = readlane(rr, 0);
+            const bool span_first = (c0 == s0) && t == 0;
+            // the carried segment ends before this tile: write it
+            if (carry_row >= 0 && r0 != carry_row) {
+                if (lane == 0)
+                    coo_write<X, kAccumulate, kBetaZero>(carry_row, carry_val, carry_start, false, row_before,
+                                                         row_after, y, alpha, beta);
+                carry_row = -1;
+            }
+            const bool merged = (carry_row >= 0);  // lane 0 continues the carried segment
+            const int32_t first_prev = (t == 0) ? chunk_before : readlane(r[t > 0 ? t - 1 : 0], kWave - 1);
+            const int32_t rprev = wave_shift_up1(rr, first_prev);
+            const bool head = !valid || lane == 0 || rr != rprev;
+            X v = p[t];
+            if (lane == 0 && merged) v += carry_val;
+            // gaps: rows strictly between the previous entry's row and this one are empty
+            if (!kAccumulate && valid && rr != rprev)
+                for (int32_t g = rprev + 1; g < rr; ++g) y[g] = kBetaZero ? X(0) : scaled(y[g], beta);
+            if (!kAccumulate && valid && e == nnz - 1)
+                for (int32_t g = rr + 1; g < nrows; ++g) y[g] = kBetaZero ? X(0) : scaled(y[g], beta);
+            const X sv = wave_segscan(v, head);
+            // the last valid lane of the tile and the segment it closes are carried on
+            const int tail_e = (c1 - tb < kWave) ? (int)(c1 - tb - 1) : kWave - 1;
+            const lane_mask_t heads = ballot64(head && lane > 0);
+            const lane_mask_t upto_me = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
+            const bool seg0 = (heads & upto_me & ~1ull) == 0;  // my segment holds lane 0
+            const bool start_seg = seg0 && (span_first || (merged && carry_start));
+            // a lane closes a segment when the next lane starts a new one
+            const int32_t rn = wave_shift_down1(rr, -2);
+            if (lane < tail_e && rn != rr)
+                coo_write<X, kAccumulate, kBetaZero>(rr, sv, start_seg, false, row_before, row_after, y, alpha,
+                                                     beta);
+            carry_row = readlane(rr, tail_e);
+            carry_val = readlane(sv, tail_e);
+            const lane_mask_t upto_tail = (tail_e == kWave - 1) ? ~0ull : ((2ull << tail_e) - 1);
+            const bool last_seg_has_lane0 = (heads & upto_tail & ~1ull) == 0;
+            carry_start = last_seg_has_lane0 && (span_first || (merged && carry_start));
+        }
     }
     if (carry_row >= 0 && lane == 0)
-        coo_write<X, kAccumulate>(carry_row, carry_val, carry_start, true, row_before, row_after, y, alpha, beta);
+        coo_write<X, kAccumulate, kBetaZero>(carry_row, carry_val, carry_start, true, row_before, row_after, y, alpha,
+                                             beta);
 }
 
 // One thread per kR consecutive rows (kR = 2 loads the two rows' slots as
@@ -224,7 +240,8 @@ __global__ __launch_bounds__(kEllThreads) void ell_spmv_kernel(int32_t nrows, in
     for (int r = 0; r < kR; ++r) {
         const int64_t i = i0 + r;
         if (i < nrows) {
-            const X out = alpha * sum[r] + scaled(y[i], beta);
+            X out = alpha * sum[r];
+            if (beta != X(0)) out += beta * y[i];  // y is not read when beta == 0
             y[i] = out;
             if constexpr (kEpi >= 1) d1 += out * dot_with[i];
             if constexpr (kEpi >= 2) d2 += out * out;
@@ -250,15 +267,26 @@ static spx_status coo_part(int32_t nrows, int64_t nnz, const int32_t *row, const
         }
         return SPX_OK;
     }
+    // chunks per wavefront span: enough spans to fill the GPU several times
+    // over, at most kCooMaxSpan chunks (fewer spans, fewer boundary atomics)
     const int64_t nchunks = ceil_div(nnz, kCooChunk);
-    if (!kAccumulate && nchunks > 1) {
-        coo_split_init_kernel<X><<<(unsigned)ceil_div(nchunks - 1, 256), 256, 0, stream>>>(nnz, nchunks, row, y, beta);
+    int64_t per = ceil_div(nchunks, kCooTargetSpans);
+    per = per < 1 ? 1 : (per > kCooMaxSpan ? kCooMaxSpan : per);
+    const int64_t span = per * kCooChunk;
+    const int64_t nspans = ceil_div(nnz, span);
+    if (!kAccumulate && nspans > 1) {
+        coo_split_init_kernel<X><<<(unsigned)ceil_div(nspans - 1, 256), 256, 0, stream>>>(nnz, nspans, span, row, y,
+                                                                                          beta);
         SPX_LAUNCHED();
     }
-    const int64_t blocks = ceil_div(nchunks, kCooThreads / kWave);
+    const int64_t blocks = ceil_div(nspans, kCooThreads / kWave);
     const int64_t grid = pad_to_xcds(blocks);
-    coo_spmv_kernel<V, X, kAccumulate><<<(unsigned)grid, kCooThreads, 0, stream>>>(nrows, nnz, nchunks, grid, row,
-                                                                                  col, val, x, y, alpha, beta);
+    if (!kAccumulate && beta == X(0))
+        coo_spmv_kernel<V, X, false, true><<<(unsigned)grid, kCooThreads, 0, stream>>>(
+            nrows, nnz, nspans, span, grid, row, col, val, x, y, alpha, beta);
+    else
+        coo_spmv_kernel<V, X, kAccumulate, false><<<(unsigned)grid, kCooThreads, 0, stream>>>(
+            nrows, nnz, nspans, span, grid, row, col, val, x, y, alpha, beta);
     SPX_LAUNCHED();
     return SPX_OK;
 }
@@ -378,7 +406,8 @@ __global__ __launch_bounds__(kSellThreads) void sellp_spmv_kernel(int32_t nrows,
     if (g == 0 && row < nrows) {
         X t = part[l];
         for (int j = 1; j < G; ++j) t += part[j * C + l];
-        const X out = alpha * t + scaled(y[row], beta);
+        X out = alpha * t;
+        if (beta != X(0)) out += beta * y[row];
         y[row] = out;
         if constexpr (kEpi >= 1) d1 = out * dot_with[row];
         if constexpr (kEpi >= 2) d2 = out * out;
@@ -439,7 +468,8 @@ __global__ __launch_bounds__(kSellThreads) void sellp64_spmv_kernel(int32_t nrow
         }
         const int64_t row = s * kWave + l;
         if (row < nrows) {
-            const X out = alpha * sum + scaled(y[row], beta);
+            X out = alpha * sum;
+            if (beta != X(0)) out += beta * y[row];
             y[row] = out;
             if constexpr (kEpi >= 1) d1 = out * dot_with[row];
             if constexpr (kEpi >= 2) d2 = out * out;
