@@ -442,7 +442,28 @@ def serve_workload(S, nreq, seed):
     return [("poisson", int(pN[i])) if kinds[i] else ("spd", int(sn[i])) for i in range(nreq)]
 
 
-def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32):
+def cpu_serve_sample(mats, reqs, nsample=200):
+    """The oracle's CG (plain C, float64, one solve per thread) on the first
+    `nsample` requests of the serving stream, as many solves at once as the
+    host has cores for this process (at most 16): sampled CPU solves/s. The
+    C calls release the interpreter lock, so threads run them in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle as O
+
+    ncores = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = reqs[: min(len(reqs), nsample)]
+    print(f"serve cpu: {len(sample)} oracle CG solves on {ncores} threads", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(ncores) as ex:
+        infos = list(ex.map(lambda r: O.cg(mats[r][0], mats[r][1], tol=1e-8, maxit=100000)[1], sample))
+    dt = time.perf_counter() - t0
+    assert all(i["status"] == O.OK for i in infos)
+    return {"value": round(len(sample) / dt, 2), "unit": "solves/s", "cores": ncores, "kind": "oracle",
+            "sample": f"first {len(sample)} requests of the stream, oracle CG to 1e-8, one solve per thread"}
+
+
+def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32, cpu=False):
     """Serving: (1) all `nreq` requests submitted at once (capacity, solves/s);
     (2) open-loop Poisson arrival streams at 0.5, 0.7 and 0.9 x that capacity
     (latency = completion - scheduled arrival, p50/p99; completion is the
@@ -511,10 +532,13 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32):
         x, info = spx.cg_solve(Ad, torch.from_numpy(b).to(dev), tol=1e-8, maxit=100000)
         assert info["status"] == 0
     seq = len(sample) / (time.perf_counter() - t1)
-    return {"burst": burst, "open_loop": streams, "sequential_cg_solves_per_s": round(seq, 2),
-            "sequential_sample": len(sample), "served_over_sequential": round(burst["solves_per_s"] / seq, 2),
-            "server": {k: st[k] for k in ("ticks", "pool_bytes_peak")}, "budget_gb": budget_gb,
-            "distinct_matrices": len(mats), "gen_s": round(gen_s, 1)}
+    out = {"burst": burst, "open_loop": streams, "sequential_cg_solves_per_s": round(seq, 2),
+           "sequential_sample": len(sample), "served_over_sequential": round(burst["solves_per_s"] / seq, 2),
+           "server": {k: st[k] for k in ("ticks", "pool_bytes_peak", "pool_bytes_total")}, "budget_gb": budget_gb,
+           "distinct_matrices": len(mats), "gen_s": round(gen_s, 1)}
+    if cpu:
+        out["cpu_oracle"] = cpu_serve_sample(mats, reqs)
+    return out
 
 
 def main():
@@ -532,6 +556,7 @@ def main():
     ap.add_argument("--cg-solves", type=int, default=50, help="solves of the 64x64 CG latency run (0 = skip)")
     ap.add_argument("--cg-batch", type=int, default=1024, help="systems in the batched 64x64 CG run (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="HBM budget of the serving run")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--subwarp", action="store_true", help="also time the subwarp reduction versus subwarp size")
     args = ap.parse_args()
@@ -597,7 +622,8 @@ def main():
 
     cg_small = bench_cg_small(spx, S, torch, dev, args.cg_solves, args.cg_batch) if args.cg_solves > 0 else None
     solvers = bench_solvers(spx, S, torch, dev) if args.solvers else None
-    serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed) if args.serve_requests > 0 else None
+    serve = (bench_serve(spx, S, torch, dev, args.serve_requests, args.seed, args.serve_budget_gb, not args.no_cpu)
+             if args.serve_requests > 0 else None)
     subwarp = subwarp_sweep(spx, torch, dev) if args.subwarp else None
 
     cpu = None
@@ -614,6 +640,17 @@ def main():
         cpu = {"value": b / cs / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"{reps} plain float64 CSR products of the full {mdesc} matrix, "
                          f"{cs * 1e3:.1f} ms each, 1 thread"}
+        if cg_small is not None:
+            # the oracle's CG on the 64x64 Poisson system (unpreconditioned, 1e-10), 1 thread
+            P = S.poisson2d(64)
+            pb = O.csr_spmv(P, S.uniform_vector(P.n, seed=0, purpose="xstar"))
+            cnt, t1 = 0, time.perf_counter()
+            while time.perf_counter() - t1 < 3.0:
+                _, oinfo = O.cg(P, pb, tol=1e-10)
+                cnt += 1
+            cg_small["cpu_oracle"] = {"value": round(cnt / (time.perf_counter() - t1), 2), "unit": "solves/s",
+                                      "cores": 1, "kind": "oracle", "iters": oinfo["iters"],
+                                      "sample": f"{cnt} oracle CG solves of the 64x64 Poisson system, 1 thread"}
 
     r = results["csr_f64"]
     line = {

@@ -13,10 +13,15 @@
 // captured once into a hipGraph and replayed, and the host reads the state
 // only between replays. When the recursive residual passes, the true residual
 // b - A x decides; a miss restarts the recurrences from it.
+// Small float64 CSR systems (at most kSmallMaxRows rows, scalar Jacobi or no
+// preconditioner) run the whole solve in one launch instead (small_cg.hip).
 // Float64 throughout for spx_cg_solve; the same driver runs in float32
 // (float32 or binary16-stored matrix values) as the inner solver of
 // mixed-precision iterative refinement.
+#include <type_traits>
+
 #include "convert.hpp"
+#include "small_cg.hpp"
 #include "solver_common.hpp"
 #include "solvers.hpp"
 
@@ -182,6 +187,44 @@ size_t cg_workspace(const spx_matrix &A, int precond)
     return c.off + 256;
 }
 
+// The one-launch solve of a small float64 CSR system (small_cg.hip) and the
+// same bookkeeping as the general driver.
+static spx_status small_cg_finish(const spx_matrix &A, const double *b, double *x, const SolveSpec &sp,
+                                  const CgBufs<double, double> &w, SolveEnv *env, spx_solve_info *info,
+                                  hipStream_t user_stream)
+{
+    hipStream_t s = env->stream;
+    const int64_t n = A.nrows;
+    SPX_CHECK(small_cg_launch(A, b, x, sp.precond ? w.dinv : nullptr, sp.x0_zero, w.st, s));
+    KState hs;
+    SPX_CHECK(read_state(env, w.st, &hs));
+    double true2 = hs.tmp[0];
+    if (true2 < 0.0 && hs.bb > 0.0) {  // stopped before a true residual was formed
+        SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));
+        SPX_CHECK(residual_norm<double>(n, b, w.q, w.r, w.partials, w.st, s));
+        KState h2;
+        SPX_CHECK(read_state(env, w.st, &h2));
+        true2 = h2.tmp[0];
+    }
+    spx_status status = status_of_flag(hs.flag);
+    if (hs.flag == kMaxit) set_error("cg: no convergence in %d iterations", sp.maxit);
+    else if (hs.flag == kBreakdown) set_error("cg: breakdown (p'Ap <= 0)");
+    else if (hs.flag == kNonfinite) set_error("cg: non-finite residual");
+    SPX_HIP(hipEventRecord(env->ev1, s));
+    SPX_HIP(hipEventSynchronize(env->ev1));
+    float ms = 0.f;
+    SPX_HIP(hipEventElapsedTime(&ms, env->ev0, env->ev1));
+    info->status = status;
+    info->iters = hs.iters;
+    info->spmv_count = hs.spmv_count;
+    info->relres_recursive = hs.bb > 0 ? sqrt(hs.rr / hs.bb) : 0.0;
+    info->relres_true = hs.bb > 0 ? sqrt(true2 / hs.bb) : 0.0;
+    info->device_ms = ms;
+    SPX_HIP(hipEventRecord(env->join, s));
+    SPX_HIP(hipStreamWaitEvent(user_stream, env->join, 0));
+    return status;
+}
+
 template <typename V, typename X>
 spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp, void *ws, size_t ws_bytes,
                   spx_solve_info *info, hipStream_t user_stream)
@@ -200,7 +243,10 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
     SPX_HIP(hipEventRecord(env->join, user_stream));
     SPX_HIP(hipStreamWaitEvent(s, env->join, 0));
     SPX_HIP(hipEventRecord(env->ev0, s));
-    if (w.part) {
+    // small float64 CSR systems: the whole solve in one work-group, one launch
+    const bool small = std::is_same<V, double>::value && std::is_same<X, double>::value && A.fmt == SPX_CSR &&
+                       n <= kSmallMaxRows && sp.precond <= 1 && sp.confirm_true;
+    if (w.part && !small) {
         SPX_CHECK(csr_partition_launch(A, w.part, s));
         A.csr_part = w.part;
     }
@@ -215,6 +261,9 @@ spx_status cg_run(const spx_matrix &A_in, const X *b, X *x, const SolveSpec &sp,
             set_error(bs ? "cg: singular or non-finite diagonal block" : "cg: zero, missing or non-finite diagonal entry");
             return SPX_ERR_ZERO_DIAG;
         }
+    }
+    if constexpr (std::is_same<V, double>::value && std::is_same<X, double>::value) {
+        if (small) return small_cg_finish(A, b, x, sp, w, env, info, user_stream);
     }
     const unsigned gv = (unsigned)vec_blocks(n);
     if (sp.x0_zero) {

@@ -88,6 +88,39 @@ def test_cg_unaligned_solution_vector():
     np.testing.assert_array_equal(host(xa).view(np.uint64), host(xu).view(np.uint64))
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_cg_small_path_agrees_with_general(precond):
+    """CSR systems of at most 4096 rows run the whole CG solve in one
+    work-group; the same system in ELL takes the general multi-launch driver:
+    both meet the tolerance with the same iteration count up to rounding."""
+    A = S.poisson2d(64)  # n = 4096: the largest system of the one-group path
+    xs, b = _problem(A, 4)
+    Ad = spx.csr_from_host(A)
+    xc, ic = spx.cg_solve(Ad, dev(b), tol=1e-10, precond=precond)
+    xe, ie = spx.cg_solve(spx.convert(Ad, spx.ELL), dev(b), tol=1e-10, precond=precond)
+    assert ic["status"] == ie["status"] == spx.OK
+    assert abs(ic["iters"] - ie["iters"]) <= 2, (ic["iters"], ie["iters"])
+    for x in (host(xc), host(xe)):
+        assert _true_relres(A, b, x) <= 1e-10
+    np.testing.assert_allclose(host(xc), host(xe), rtol=0, atol=1e-8 * np.abs(xs).max())
+    xc2, _ = spx.cg_solve(Ad, dev(b), tol=1e-10, precond=precond)
+    np.testing.assert_array_equal(host(xc).view(np.uint64), host(xc2).view(np.uint64))
+
+
+@pytest.mark.parametrize("n", [1, 777, 4096, 4097])
+def test_cg_small_path_x0_jacobi_vs_oracle(n):
+    """Jacobi CG from a nonzero x0 on both sides of the one-group size limit."""
+    A = S.spd_diag_dominant(n, kmin=1 if n < 5 else 5, seed=n)
+    xs, b = _problem(A, n)
+    x0 = S.uniform_vector(A.n, seed=n + 1)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), x=dev(x0), tol=1e-10, precond=1)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    _, io = O.cg(A, b, tol=1e-10, precond=1, x0=x0)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+    assert info["relres_true"] <= 1e-10
+
+
 def test_cg_bitwise_reproducible():
     A = S.poisson3d_7pt(20, 1, 1, 0.01)
     xs, b = _problem(A)
