@@ -25,6 +25,7 @@ enum KFlag : int32_t {
     kHalfConverged = 5,  // BiCGSTAB: ||s|| below tolerance
     kZeroRhs = 6,
     kCycleEnd = 7,       // GMRES: cycle finished (lucky breakdown or estimate converged)
+    kLongRow = 8,        // one-group CG: a row is longer than the cached form holds
 };
 
 enum KOp : int32_t {

@@ -195,9 +195,15 @@ static spx_status small_cg_finish(const spx_matrix &A, const double *b, double *
 {
     hipStream_t s = env->stream;
     const int64_t n = A.nrows;
-    SPX_CHECK(small_cg_launch(A, b, x, sp.precond ? w.dinv : nullptr, sp.x0_zero, w.st, s));
+    const bool cached = A.max_row_len > 0 && A.max_row_len <= kSmallCachedLen;
+    SPX_CHECK(small_cg_launch(A, b, x, sp.precond ? w.dinv : nullptr, sp.x0_zero, cached, w.st, s));
     KState hs;
     SPX_CHECK(read_state(env, w.st, &hs));
+    if (hs.flag == kLongRow) {  // the row-length hint was too small
+        SPX_CHECK(state_set_flag(w.st, kRunning, s));
+        SPX_CHECK(small_cg_launch(A, b, x, sp.precond ? w.dinv : nullptr, sp.x0_zero, false, w.st, s));
+        SPX_CHECK(read_state(env, w.st, &hs));
+    }
     double true2 = hs.tmp[0];
     if (true2 < 0.0 && hs.bb > 0.0) {  // stopped before a true residual was formed
         SPX_CHECK(spmv_dispatch(A, x, w.q, 1.0, 0.0, s));

@@ -121,6 +121,38 @@ def test_cg_small_path_x0_jacobi_vs_oracle(n):
     assert info["relres_true"] <= 1e-10
 
 
+def test_cg_small_path_cached_matrix_x0():
+    """Rows of at most 5 entries (5-point stencil, known from the row-length
+    hint): the one-group solve keeps the matrix in registers."""
+    A = S.poisson2d(45)
+    assert np.diff(A.rowptr).max() <= 5
+    xs, b = _problem(A, 6)
+    x0 = S.uniform_vector(A.n, seed=7)
+    Ad = spx.csr_from_host(A)
+    assert 0 < Ad.max_row_len <= 5
+    x, info = spx.cg_solve(Ad, dev(b), x=dev(x0), tol=1e-10, precond=1)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    _, io = O.cg(A, b, tol=1e-10, precond=1, x0=x0)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5
+
+
+def test_cg_small_path_row_hint_too_small():
+    """A row-length hint below the true longest row must not change the
+    result: the register-cached form hands the solve back to the streaming one."""
+    A = S.spd_diag_dominant(3000, seed=8)
+    xs, b = _problem(A, 8)
+    good = spx.csr_from_host(A)
+    bad = spx.csr_from_host(A)
+    bad.max_row_len = 3
+    xg, ig = spx.cg_solve(good, dev(b), tol=1e-10, precond=1)
+    xb, ib = spx.cg_solve(bad, dev(b), tol=1e-10, precond=1)
+    assert ig["status"] == ib["status"] == spx.OK
+    assert ig["iters"] == ib["iters"]
+    np.testing.assert_array_equal(host(xg).view(np.uint64), host(xb).view(np.uint64))
+    assert _true_relres(A, b, host(xb)) <= 1e-10
+
+
 def test_cg_bitwise_reproducible():
     A = S.poisson3d_7pt(20, 1, 1, 0.01)
     xs, b = _problem(A)
