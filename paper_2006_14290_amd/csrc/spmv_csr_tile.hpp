@@ -72,11 +72,15 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
     constexpr int kSlack = kCsrSlack;
     constexpr int kStage = kTile + kSlack;
     static_assert(kSlack % kVec == 0 && kSlack / kVec <= kThreads, "slack must split into whole vectors");
-    constexpr size_t kLdsBytes = kLate ? (size_t)kStage * (sizeof(int32_t) + sizeof(V)) : (size_t)kStage * sizeof(A);
+    // values are staged in their arithmetic type (binary16 is widened to
+    // float once, while staging, instead of at every use in the row loop)
+    using SV = typename acc_of<V>::type;
+    typedef SV SVV __attribute__((ext_vector_type(kVec)));
+    constexpr size_t kLdsBytes = kLate ? (size_t)kStage * (sizeof(int32_t) + sizeof(SV)) : (size_t)kStage * sizeof(A);
     __shared__ __align__(16) unsigned char s_raw[kLdsBytes];
     A *prod = reinterpret_cast<A *>(s_raw);
-    V *s_val = reinterpret_cast<V *>(s_raw);
-    int32_t *s_col = reinterpret_cast<int32_t *>(s_raw + (size_t)kStage * sizeof(V));
+    SV *s_val = reinterpret_cast<SV *>(s_raw);
+    int32_t *s_col = reinterpret_cast<int32_t *>(s_raw + (size_t)kStage * sizeof(SV));
     __shared__ int32_t s_rp[kThreads + 1];
     __shared__ int64_t s_b[4];
     __shared__ A s_carry;
@@ -170,7 +174,10 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
 #pragma unroll
         for (int u = 0; u < kNV; ++u) {
             if constexpr (kLate) {
-                *reinterpret_cast<VV *>(&s_val[(u * kThreads + tid) * kVec]) = vv[u];
+                SVV sv;
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) sv[j] = widen(vv[u][j]);
+                *reinterpret_cast<SVV *>(&s_val[(u * kThreads + tid) * kVec]) = sv;
                 *reinterpret_cast<CV *>(&s_col[(u * kThreads + tid) * kVec]) = cc[u];
             } else {
                 typedef A AV __attribute__((ext_vector_type(kVec)));
@@ -183,7 +190,10 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
         }
         if (slack) {
             if constexpr (kLate) {
-                *reinterpret_cast<VV *>(&s_val[kTile + tid * kVec]) = vs;
+                SVV sv;
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) sv[j] = widen(vs[j]);
+                *reinterpret_cast<SVV *>(&s_val[kTile + tid * kVec]) = sv;
                 *reinterpret_cast<CV *>(&s_col[kTile + tid * kVec]) = cs;
             } else {
                 typedef A AV __attribute__((ext_vector_type(kVec)));
@@ -226,7 +236,7 @@ __device__ __forceinline__ void csr_tile(int64_t k, int32_t nrows, int64_t nnz, 
                     const int b = (int)((s_rp[j + 1] < w1 ? s_rp[j + 1] : w1) - a0);
                     if constexpr (kLate) {
 #pragma unroll 4
-                        for (int p = a + sl; p < b; p += size) sum += widen(s_val[p]) * x[s_col[p]];
+                        for (int p = a + sl; p < b; p += size) sum += s_val[p] * x[s_col[p]];
                     } else {
                         for (int p = a + sl; p < b; p += size) sum += prod[p];
                     }
