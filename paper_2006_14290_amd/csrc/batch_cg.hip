@@ -59,7 +59,7 @@ __device__ double wg_spmv(const BatchSlot &S, const double *__restrict__ v, doub
 __device__ void run_slot(BatchSlot *slot, double *s_red)
 {
     const BatchSlot S = *slot;
-    if (S.status != kSlotRunning || S.budget <= 0) return;
+    if (S.status != kSlotRunning || S.budget <= 0 || S.n <= kBatchSmallRows) return;
     const int64_t n = S.n;
     const int tid = threadIdx.x;
     double rho = S.rho, rr = S.rr, bb = S.bb, relres = S.relres_true;
@@ -166,7 +166,253 @@ __global__ __launch_bounds__(kBatchThreads) void batch_cg_kernel(BatchSlot *slot
 
 __global__ void batch_reset_kernel(int32_t *counter)
 {
-    if (threadIdx.x == 0) *counter = 0;
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------- small systems
+// One 512-thread work-group per system of at most kBatchSmallRows rows:
+// thread t owns rows t + 512 k (k < 8). While the work-group runs the slot,
+// p lives in LDS (where the product gathers it) and x, r in registers; they
+// are loaded from the slot's vectors at the start of a launch and stored back
+// at its end, so a solve may be spread over launches. When no row has more
+// than kBSLen entries the rows' columns and values are held in registers
+// too. Same recurrences, stopping test and true-residual restart as
+// run_slot; every dot product is a fixed-order work-group reduction.
+constexpr int kBSThreads = 512;
+constexpr int kBSR = kBatchSmallRows / kBSThreads;
+constexpr int kBSWaves = kBSThreads / kWave;
+constexpr int kBSLen = 5;
+
+// Work-group sums, result in every thread (alternating LDS buffers: one
+// barrier each).
+template <int NV>
+__device__ __forceinline__ void bs_sum(double (&v)[NV], double (*s_red)[2 * kBSWaves], int &par)
+{
+    const int w = threadIdx.x / kWave, l = lane_id();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    if (l == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) s_red[par][j * kBSWaves + w] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double t = l < kBSWaves ? s_red[par][j * kBSWaves + l] : 0.0;
+        v[j] = readlane(subwave_sum<kBSWaves>(t), 0);
+    }
+    par ^= 1;
+}
+
+template <bool kCached>
+__device__ __noinline__ void run_small_slot(BatchSlot *slot, double *s_v, double (*s_red)[2 * kBSWaves])
+{
+    const BatchSlot S = *slot;
+    const int tid = threadIdx.x;
+    const int32_t n = S.n;
+    int par = 0;
+    int32_t ra[kBSR], rb[kBSR];
+#pragma unroll
+    for (int k = 0; k < kBSR; ++k) {
+        const int i = tid + k * kBSThreads;
+        ra[k] = i < n ? S.rowptr[i] : 0;
+        rb[k] = i < n ? S.rowptr[i + 1] : 0;
+    }
+    int32_t cc[kCached ? kBSR : 1][kCached ? kBSLen : 1];
+    double vv[kCached ? kBSR : 1][kCached ? kBSLen : 1];
+    int32_t ln[kCached ? kBSR : 1];
+    if constexpr (kCached) {
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            ln[k] = rb[k] - ra[k];
+#pragma unroll
+            for (int e = 0; e < kBSLen; ++e) {
+                const bool in = e < ln[k];
+                cc[k][e] = in ? S.col[ra[k] + e] : 0;
+                vv[k][e] = in ? S.val[ra[k] + e] : 0.0;
+            }
+        }
+    }
+    // row k of A times v (in LDS), entries in order
+    auto row = [&](int k, const double *v) -> double {
+        double t = 0.0;
+        if constexpr (kCached) {
+#pragma unroll
+            for (int e = 0; e < kBSLen; ++e)
+                if (e < ln[k]) t += vv[k][e] * v[cc[k][e]];
+        } else {
+#pragma unroll 2
+            for (int32_t j = ra[k]; j < rb[k]; ++j) t += S.val[j] * v[S.col[j]];
+        }
+        return t;
+    };
+    double xr[kBSR], rv[kBSR];
+    double rho = S.rho, rr = S.rr, bb = S.bb, relres = S.relres_true;
+    int32_t iters = S.iters, spmv = S.spmv, status = kSlotRunning, started = S.started;
+    if (!started) {  // x0 = 0: r = b, p = b
+        double t[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            const int i = tid + k * kBSThreads;
+            const double bi = i < n ? S.b[i] : 0.0;
+            xr[k] = 0.0;
+            rv[k] = bi;
+            s_v[i] = bi;
+            t[0] += bi * bi;
+        }
+        bs_sum<1>(t, s_red, par);  // its barrier also publishes p
+        bb = t[0];
+        rho = bb;
+        rr = bb;
+        started = 1;
+        if (!__builtin_isfinite(bb)) status = kSlotNonfinite;
+        else if (bb == 0.0) {
+            status = kSlotConverged;
+            relres = 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            const int i = tid + k * kBSThreads;
+            const bool in = i < n;
+            xr[k] = in ? S.x[i] : 0.0;
+            rv[k] = in ? S.r[i] : 0.0;
+            s_v[i] = in ? S.p[i] : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int it = 0; it < S.budget && status == kSlotRunning; ++it) {
+        double qv[kBSR];
+        double t[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            qv[k] = row(k, s_v);
+            t[0] += s_v[tid + k * kBSThreads] * qv[k];
+        }
+        bs_sum<1>(t, s_red, par);
+        spmv += 1;
+        const double pq = t[0];
+        if (!__builtin_isfinite(pq)) {
+            status = kSlotNonfinite;
+            break;
+        }
+        if (pq <= 0.0) {
+            status = kSlotBreakdown;
+            break;
+        }
+        const double alpha = rho / pq;
+        double t2[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            xr[k] += alpha * s_v[tid + k * kBSThreads];
+            rv[k] = rv[k] - alpha * qv[k];
+            t2[0] += rv[k] * rv[k];
+        }
+        bs_sum<1>(t2, s_red, par);  // its barrier: every gather of p is done
+        rr = t2[0];
+        iters += 1;
+        if (!__builtin_isfinite(rr)) {
+            status = kSlotNonfinite;
+            break;
+        }
+        if (rr <= S.tol2 * bb) {
+            // confirm with the true residual b - A x (x staged in LDS)
+#pragma unroll
+            for (int k = 0; k < kBSR; ++k) s_v[tid + k * kBSThreads] = xr[k];
+            __syncthreads();
+            double t3[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < kBSR; ++k) {
+                const int i = tid + k * kBSThreads;
+                const double bi = i < n ? S.b[i] : 0.0;
+                rv[k] = bi - row(k, s_v);
+                t3[0] += rv[k] * rv[k];
+            }
+            spmv += 1;
+            bs_sum<1>(t3, s_red, par);  // its barrier: every gather of x is done
+            const double tr = t3[0];
+            if (tr <= S.tol2 * bb) {
+                status = kSlotConverged;
+                relres = sqrt(tr / bb);
+                break;
+            }
+            // restart from it: p = r
+#pragma unroll
+            for (int k = 0; k < kBSR; ++k) s_v[tid + k * kBSThreads] = rv[k];
+            __syncthreads();
+            rho = tr;
+            rr = tr;
+            if (iters >= S.maxit) status = kSlotMaxit;
+            continue;
+        }
+        const double beta = rr / rho;
+        rho = rr;
+#pragma unroll
+        for (int k = 0; k < kBSR; ++k) {
+            const int i = tid + k * kBSThreads;
+            s_v[i] = rv[k] + beta * s_v[i];  // only this thread touches its rows here
+        }
+        __syncthreads();
+        if (iters >= S.maxit) status = kSlotMaxit;
+    }
+#pragma unroll
+    for (int k = 0; k < kBSR; ++k) {
+        const int i = tid + k * kBSThreads;
+        if (i < n) {
+            S.x[i] = xr[k];
+            S.r[i] = rv[k];
+            S.p[i] = s_v[i];
+        }
+    }
+    if (tid == 0) {
+        slot->rho = rho;
+        slot->rr = rr;
+        slot->bb = bb;
+        slot->iters = iters;
+        slot->spmv = spmv;
+        slot->started = started;
+        slot->status = status;
+        slot->relres_true = (status == kSlotConverged) ? relres : (bb > 0 ? sqrt(rr / bb) : 0.0);
+    }
+}
+
+__global__ __launch_bounds__(kBSThreads) void batch_small_kernel(BatchSlot *slots, int32_t nslots, int32_t *counter)
+{
+    __shared__ double s_v[kBatchSmallRows];
+    __shared__ double s_red[2][2 * kBSWaves];
+    __shared__ int32_t s_k;
+    while (true) {
+        if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t k = s_k;
+        __syncthreads();
+        if (k >= nslots) return;  // every work-group leaves once the slots are handed out
+        BatchSlot *slot = &slots[k];
+        if (slot->status != kSlotRunning || slot->budget <= 0 || slot->n > kBatchSmallRows) continue;
+        // the cached form when no row of this system has more than kBSLen entries
+        bool long_row = false;
+        for (int i = threadIdx.x; i < slot->n; i += kBSThreads)
+            long_row |= slot->rowptr[i + 1] - slot->rowptr[i] > kBSLen;
+        if (__syncthreads_or(long_row)) run_small_slot<false>(slot, s_v, s_red);
+        else run_small_slot<true>(slot, s_v, s_red);
+        __syncthreads();
+    }
+}
+
+int64_t batch_small_resident_groups()
+{
+    static int64_t cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        }
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_small_kernel, kBSThreads, 0) == hipSuccess && b > 0)
+            per_cu = b;
+        cached = (int64_t)cus * per_cu;
+    }
+    return cached;
 }
 
 int64_t batch_resident_groups()
@@ -189,6 +435,15 @@ int64_t batch_resident_groups()
 spx_status batch_reset_launch(int32_t *counter, hipStream_t stream)
 {
     batch_reset_kernel<<<1, 64, 0, stream>>>(counter);
+    SPX_LAUNCHED();
+    return SPX_OK;
+}
+
+spx_status batch_small_launch(BatchSlot *slots, int32_t nslots, int32_t *counter, int64_t grid, hipStream_t stream)
+{
+    if (grid > nslots) grid = nslots;
+    if (grid < 1) grid = 1;
+    batch_small_kernel<<<(unsigned)grid, kBSThreads, 0, stream>>>(slots, nslots, counter + 1);
     SPX_LAUNCHED();
     return SPX_OK;
 }

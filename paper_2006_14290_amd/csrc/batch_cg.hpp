@@ -112,11 +112,23 @@ spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const Wid
                                  const int32_t *vb_slot, const int32_t *vb_local, const int32_t *ta_slot,
                                  const int32_t *ta_local, int grid, int commit_grid, hipStream_t stream);
 
+// Systems of at most kBatchSmallRows rows are advanced by their own kernel
+// (batch_small_launch; one 512-thread work-group per system with p in LDS
+// and x, r in registers while it runs), the others by batch_cg_launch. The
+// split depends only on a system's own n, so its iterates stay bitwise the
+// same alone or in any mix.
+constexpr int kBatchSmallRows = 4096;
+
 // Advance slots[0..nslots) by at most slot.budget CG iterations each (or to
 // convergence); work-groups take slots from *counter, which must be 0 at
 // launch (batch_reset does that). grid: number of resident work-groups.
+// batch_cg_launch skips systems of at most kBatchSmallRows rows and uses
+// counter[0]; batch_small_launch takes only those and uses counter[1].
 spx_status batch_cg_launch(BatchSlot *slots, int32_t nslots, int32_t *counter, int64_t grid, hipStream_t stream);
+spx_status batch_small_launch(BatchSlot *slots, int32_t nslots, int32_t *counter, int64_t grid, hipStream_t stream);
+// Zeroes counter[0] and counter[1].
 spx_status batch_reset_launch(int32_t *counter, hipStream_t stream);
 int64_t batch_resident_groups();
+int64_t batch_small_resident_groups();
 
 }  // namespace spx

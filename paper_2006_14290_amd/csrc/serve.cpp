@@ -646,7 +646,7 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     if ((e = dev_alloc(&S->pool_base, cfg->hbm_budget_bytes)) != hipSuccess) return fail("pool");
     S->pool.init(cfg->hbm_budget_bytes);
     if ((e = dev_alloc(&S->slots_dev, ms)) != hipSuccess || (e = host_alloc(&S->slots_host, ms)) != hipSuccess ||
-        (e = dev_alloc(&S->counter, 1)) != hipSuccess || (e = dev_alloc(&S->wslots_dev, ms)) != hipSuccess ||
+        (e = dev_alloc(&S->counter, 2)) != hipSuccess || (e = dev_alloc(&S->wslots_dev, ms)) != hipSuccess ||
         (e = host_alloc(&S->wslots_host, ms)) != hipSuccess || (e = dev_alloc(&S->wstate_dev, ms)) != hipSuccess ||
         (e = host_alloc(&S->wstate_host, ms)) != hipSuccess || (e = host_alloc(&S->winit_host, ms)) != hipSuccess ||
         (e = dev_alloc(&S->wmap_dev, 1)) != hipSuccess || (e = host_alloc(&S->wmap_host, 1)) != hipSuccess ||
@@ -664,13 +664,15 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
         return fail("map");
     // narrow ticks: reset the counter, then the persistent kernel (full grid,
     // and half the grid for ticks that run wide work beside it)
-    const int64_t groups = batch_resident_groups();
+    const int64_t groups = batch_resident_groups(), sgroups = batch_small_resident_groups();
     for (int half = 0; half < 2; ++half) {
         const int64_t grid = half ? std::max<int64_t>(1, groups / 2) : groups;
+        const int64_t sgrid = half ? std::max<int64_t>(1, sgroups / 2) : sgroups;
         e = capture(
             S->s_compute,
             [&](hipStream_t st) {
                 spx_status s1 = batch_reset_launch(S->counter, st);
+                if (s1 == SPX_OK) s1 = batch_small_launch(S->slots_dev, cfg->max_slots, S->counter, sgrid, st);
                 return s1 != SPX_OK ? s1 : batch_cg_launch(S->slots_dev, cfg->max_slots, S->counter, grid, st);
             },
             half ? &S->tick_half : &S->tick);
@@ -986,6 +988,7 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
     if (nnarrow > 0) {
         SPX_HIP(hipMemcpyAsync(slots_dev, host.data(), sizeof(BatchSlot) * (size_t)count, hipMemcpyHostToDevice, stream));
         SPX_CHECK(batch_reset_launch(counter, stream));
+        SPX_CHECK(batch_small_launch(slots_dev, count, counter, batch_small_resident_groups(), stream));
         SPX_CHECK(batch_cg_launch(slots_dev, count, counter, batch_resident_groups(), stream));
         SPX_HIP(hipMemcpyAsync(host.data(), slots_dev, sizeof(BatchSlot) * (size_t)count, hipMemcpyDeviceToHost, stream));
     }
