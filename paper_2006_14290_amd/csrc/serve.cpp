@@ -1,7 +1,9 @@
 // serve.cpp -- batched CG entry point and the continuous-batching solve server.
 //
-// spx_cg_batch: a fixed set of independent CSR systems, one persistent
-// launch, one work-group per system (batch_cg.hip).
+// spx_cg_batch: a fixed set of independent CSR systems: persistent launches
+// with one work-group per system (batch_cg.hip; systems of at most
+// kBatchSmallRows rows on their own kernel) and the grid-wide phases of the
+// wide path for large systems (batch_wide.hip).
 //
 // Server: requests (host CSR + right-hand side) are queued FIFO; a worker
 // thread admits them while a slot is free and the HBM pool (one allocation of
@@ -9,9 +11,10 @@
 // its Krylov vectors, looking past a request that does not fit at most
 // kBackfill places. Admitted requests are copied to the device on a copy
 // stream while the current tick runs. A tick runs two captured hipGraphs on
-// two streams at once: the narrow graph (reset the work counter, run the
-// persistent one-group-per-system kernel over the slot table) advances every
-// small system by its iteration budget; the wide graph (kWideIters iterations
+// two streams at once: the narrow graph (reset the work counters, run the
+// persistent one-group-per-system kernels over the slot table: the
+// small-system kernel, then the general one) advances every system below
+// the wide threshold by its iteration budget; the wide graph (kWideIters iterations
 // of the four wide phases) advances every large system, launched as many
 // times as fits the tick. Between ticks the worker reads the state back,
 // copies the solutions of finished systems to the callers' buffers, frees
