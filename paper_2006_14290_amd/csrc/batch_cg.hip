@@ -56,10 +56,19 @@ __device__ double wg_spmv(const BatchSlot &S, const double *__restrict__ v, doub
     return wg_sum(acc, s_red);
 }
 
-__device__ void run_slot(BatchSlot *slot, double *s_red)
+// kLds: the system has at most kBatchLdsRows rows and its search direction
+// lives in LDS while the work-group runs it (the product gathers it there);
+// it is loaded from and stored back to the slot's p at the ends of a launch.
+template <bool kLds>
+__device__ void run_slot(BatchSlot *slot, double *s_red, double *s_p)
 {
     const BatchSlot S = *slot;
     if (S.status != kSlotRunning || S.budget <= 0 || S.n <= kBatchSmallRows) return;
+    double *P = kLds ? s_p : S.p;
+    if (kLds && S.started) {
+        for (int64_t i = threadIdx.x; i < S.n; i += kBatchThreads) s_p[i] = S.p[i];
+        __syncthreads();
+    }
     const int64_t n = S.n;
     const int tid = threadIdx.x;
     double rho = S.rho, rr = S.rr, bb = S.bb, relres = S.relres_true;
@@ -69,7 +78,7 @@ __device__ void run_slot(BatchSlot *slot, double *s_red)
         for (int64_t i = tid; i < n; i += kBatchThreads) {
             const double bi = S.b[i];
             S.r[i] = bi;
-            S.p[i] = bi;
+            P[i] = bi;
             t += bi * bi;
         }
         bb = wg_sum(t, s_red);
@@ -83,7 +92,7 @@ __device__ void run_slot(BatchSlot *slot, double *s_red)
         }
     }
     for (int it = 0; it < S.budget && status == kSlotRunning; ++it) {
-        const double pq = wg_spmv(S, S.p, S.q, true, s_red);
+        const double pq = wg_spmv(S, P, S.q, true, s_red);
         spmv += 1;
         if (!__builtin_isfinite(pq)) {
             status = kSlotNonfinite;
@@ -96,7 +105,7 @@ __device__ void run_slot(BatchSlot *slot, double *s_red)
         const double alpha = rho / pq;
         double t = 0.0;
         for (int64_t i = tid; i < n; i += kBatchThreads) {
-            S.x[i] += alpha * S.p[i];
+            S.x[i] += alpha * P[i];
             const double ri = S.r[i] - alpha * S.q[i];
             S.r[i] = ri;
             t += ri * ri;
@@ -123,7 +132,7 @@ __device__ void run_slot(BatchSlot *slot, double *s_red)
                 relres = sqrt(tr / bb);
                 break;
             }
-            for (int64_t i = tid; i < n; i += kBatchThreads) S.p[i] = S.r[i];  // restart from it
+            for (int64_t i = tid; i < n; i += kBatchThreads) P[i] = S.r[i];  // restart from it
             rho = tr;
             rr = tr;
             __syncthreads();
@@ -132,10 +141,12 @@ __device__ void run_slot(BatchSlot *slot, double *s_red)
         }
         const double beta = rr / rho;
         rho = rr;
-        for (int64_t i = tid; i < n; i += kBatchThreads) S.p[i] = S.r[i] + beta * S.p[i];
+        for (int64_t i = tid; i < n; i += kBatchThreads) P[i] = S.r[i] + beta * P[i];
         __syncthreads();
         if (iters >= S.maxit) status = kSlotMaxit;
     }
+    if (kLds)
+        for (int64_t i = threadIdx.x; i < S.n; i += kBatchThreads) S.p[i] = s_p[i];  // this thread wrote them last
     if (tid == 0) {
         slot->rho = rho;
         slot->rr = rr;
@@ -152,6 +163,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_cg_kernel(BatchSlot *slot
                                                                 int32_t *counter)
 {
     __shared__ double s_red[kBatchWaves];
+    __shared__ double s_p[kBatchLdsRows];
     __shared__ int32_t s_k;
     while (true) {
         if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
@@ -159,7 +171,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_cg_kernel(BatchSlot *slot
         const int32_t k = s_k;
         __syncthreads();
         if (k >= nslots) return;  // every work-group leaves once the slots are handed out
-        run_slot(&slots[k], s_red);
+        if (slots[k].n <= kBatchLdsRows) run_slot<true>(&slots[k], s_red, s_p);
+        else run_slot<false>(&slots[k], s_red, s_p);
         __syncthreads();
     }
 }

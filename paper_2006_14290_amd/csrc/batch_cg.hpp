@@ -118,6 +118,9 @@ spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const Wid
 // split depends only on a system's own n, so its iterates stay bitwise the
 // same alone or in any mix.
 constexpr int kBatchSmallRows = 4096;
+// Systems of at most kBatchLdsRows rows keep p in LDS in the general
+// one-group kernel (128 KB).
+constexpr int kBatchLdsRows = 16384;
 
 // Advance slots[0..nslots) by at most slot.budget CG iterations each (or to
 // convergence); work-groups take slots from *counter, which must be 0 at
