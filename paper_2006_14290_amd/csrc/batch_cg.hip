@@ -45,6 +45,7 @@ __device__ double wg_spmv(const BatchSlot &S, const double *__restrict__ v, doub
         double sum = 0.0;
         if (row < S.n) {
             const int32_t a = S.rowptr[row], b = S.rowptr[row + 1];
+#pragma unroll 4
             for (int32_t k = a + sl; k < b; k += sub) sum += S.val[k] * v[S.col[k]];
         }
         sum = subwave_sum_dyn(sum, sub);
