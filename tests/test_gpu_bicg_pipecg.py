@@ -266,3 +266,42 @@ def test_pipecg_full_aniso_128():
     assert info["status"] == spx.OK, info
     assert _true_relres(A, b, host(x)) <= 1e-10
     print("pipecg aniso 128^3:", info, flush=True)
+
+
+# ------------------------------------------------------------------ restarts
+@pytest.mark.parametrize("solver", ["cg_small", "cg_general", "pipecg", "bicg"])
+def test_unreachable_tolerance_restarts_and_stops(solver):
+    """With tol = 1e-17 the recursive residual of CG eventually passes while
+    the true residual cannot: the solver confirms, restarts from the true
+    residual, and stops at maxit with an accurate iterate. Every solver stops
+    within maxit."""
+    print(f"case restarts {solver}", flush=True)
+    A = S.poisson2d(30) if solver != "bicg" else S.convdiff3d_upwind(10)
+    xs, b = _problem(A, 3)
+    Ad = spx.csr_from_host(A)
+    if solver == "cg_general":
+        Ad = spx.convert(Ad, spx.ELL)  # the multi-launch driver
+    fn = {"cg_small": spx.cg_solve, "cg_general": spx.cg_solve, "pipecg": spx.pipecg_solve,
+          "bicg": spx.bicg_solve}[solver]
+    x, info = fn(Ad, dev(b), tol=1e-17, maxit=600, precond=1)
+    assert info["status"] in (spx.OK, spx.ERR_NOT_CONVERGED, spx.ERR_BREAKDOWN), info
+    assert info["iters"] <= 600
+    if solver in ("cg_small", "cg_general"):
+        # CG restarts until maxit and keeps an iterate at the attainable accuracy
+        assert info["status"] == spx.ERR_NOT_CONVERGED and info["iters"] == 600, info
+        assert _true_relres(A, b, host(x)) <= 1e-13
+    else:
+        # pipelined CG and BiCG end at rounding level with a breakdown (their
+        # step denominators lose their sign; the oracle's pipelined CG does the
+        # same on this system), keeping an iterate within the usual tolerance
+        assert _true_relres(A, b, host(x)) <= 1e-10
+
+
+def test_batch_unreachable_tolerance_stops():
+    A = S.poisson2d(30)
+    xs, b = _problem(A, 4)
+    Ad = spx.csr_from_host(A)
+    xb, ib = spx.cg_batch([Ad], [dev(b)], tol=1e-17, maxit=500)
+    assert ib[0]["status"] in (spx.OK, spx.ERR_NOT_CONVERGED), ib
+    assert ib[0]["iters"] <= 500
+    assert _true_relres(A, b, host(xb[0])) <= 1e-13
