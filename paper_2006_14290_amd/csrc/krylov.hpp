@@ -262,23 +262,40 @@ __device__ __forceinline__ bool op_runs_when_stopped(int op)
            op == kOpPipeInit || op == kOpPipeRestart;
 }
 
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 1024;
 
-// Stage 2: one work-group sums nv rows of partials in a fixed order and
-// applies the scalar update `op`.
+// Stage 2: one work-group sums nv (<= 4) rows of partials in a fixed order
+// and applies the scalar update `op`. Thread t adds partials t, t + 1024, ...
+// of every row in that order (four strides' loads in flight), then the
+// wavefront sums and the wavefronts' sums in order.
 template <typename T>
 __global__ __launch_bounds__(kFinThreads) void finish_kernel(const T *__restrict__ partials, int64_t nparts, int nv,
                                                             KState *st, int op)
 {
     if (st->flag != kRunning && !op_runs_when_stopped(op)) return;
-    __shared__ T s_red[kFinThreads / kWave];
-    double tot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < nv; ++k) {
-        T acc = T(0);
-        for (int64_t i = threadIdx.x; i < nparts; i += kFinThreads) acc += partials[k * nparts + i];
-        tot[k] = (double)block_sum<T, kFinThreads>(acc, s_red);
+    constexpr int kW = kFinThreads / kWave;
+    __shared__ T s_red[4][kW];
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < nparts; i += kFinThreads)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nv) acc[k] += partials[k * nparts + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T v = wave_sum(acc[k]);
+        if (lane_id() == 0) s_red[k][threadIdx.x / kWave] = v;
     }
-    if (threadIdx.x == 0) finish_op(op, tot, st);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < nv; ++k) {
+            T t = T(0);
+            for (int w = 0; w < kW; ++w) t += s_red[k][w];
+            tot[k] = (double)t;
+        }
+        finish_op(op, tot, st);
+    }
 }
 
 template <typename T>

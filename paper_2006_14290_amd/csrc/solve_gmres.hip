@@ -96,17 +96,22 @@ __global__ __launch_bounds__(kVecThreads) void gm_multidot_kernel(int64_t n, con
     }
 }
 
-// stage 2: st->dots[off + k] = sum of row k of the partials, fixed order
+// stage 2: st->dots[off + k] = sum of row k of the partials, fixed order:
+// wavefront w takes rows w, w + 16, ...; lane l adds partials l, l + 64, ...
+// of its row in that order, then the wavefront sum (no barrier).
 __global__ __launch_bounds__(kFinThreads) void gm_multidot_finish(const X *__restrict__ partials, int64_t nb, int nv,
                                                                  KState *st, int off)
 {
     if (st->flag != kRunning) return;
-    __shared__ X s_red[kFinThreads / kWave];
-    for (int k = 0; k < nv; ++k) {
+    constexpr int kW = kFinThreads / kWave;
+    const int w = threadIdx.x / kWave, l = lane_id();
+    for (int k = w; k < nv; k += kW) {
         X acc = X(0);
-        for (int64_t b = threadIdx.x; b < nb; b += kFinThreads) acc += partials[(int64_t)k * nb + b];
-        const X t = block_sum<X, kFinThreads>(acc, s_red);
-        if (threadIdx.x == 0) st->dots[off + k] = t;
+        const X *row = partials + (int64_t)k * nb;
+#pragma unroll 8
+        for (int64_t b = l; b < nb; b += kWave) acc += row[b];
+        const X t = wave_sum(acc);
+        if (l == 0) st->dots[off + k] = t;
     }
 }
 
