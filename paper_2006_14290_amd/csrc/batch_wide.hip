@@ -38,11 +38,12 @@ __device__ __forceinline__ double wide_wg_sum(double v, double *s_red)
     return t;
 }
 
-// Sum of part[0..cnt): thread t takes t, t + 256, ... in order, then the
-// fixed work-group reduction.
+// Sum of part[0..cnt): thread t takes t, t + 256, ... in order (eight
+// strides' loads in flight), then the fixed work-group reduction.
 __device__ __forceinline__ double wide_part_sum(const double *part, int32_t cnt, double *s_red)
 {
     double t = 0.0;
+#pragma unroll 8
     for (int32_t i = threadIdx.x; i < cnt; i += kWideThreads) t += part[i];
     return wide_wg_sum(t, s_red);
 }
