@@ -19,10 +19,13 @@
 
 namespace spx {
 
+// max |r_i| in two stages (no atomics): per work-group maxima into part[],
+// then one work-group forms their maximum and stores its bit pattern (a
+// non-negative double's bits are monotone in its value).
 __global__ __launch_bounds__(kVecThreads) void ir_amax_kernel(int64_t n, const double *__restrict__ r,
-                                                             unsigned long long *__restrict__ amax_bits)
+                                                             double *__restrict__ part)
 {
-    // max |r_i| as the bit pattern of a non-negative double (monotone in value)
+    __shared__ double s_m[kVecThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kVecChunk;
     double m = 0.0;
 #pragma unroll
@@ -31,7 +34,28 @@ __global__ __launch_bounds__(kVecThreads) void ir_amax_kernel(int64_t n, const d
         if (i < n) m = fmax(m, fabs(r[i]));
     }
     for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-    if (lane_id() == 0) atomicMax(amax_bits, __builtin_bit_cast(unsigned long long, m));
+    if (lane_id() == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kVecThreads / kWave; ++w) m = fmax(m, s_m[w]);
+        part[blockIdx.x] = m;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void ir_amax_finish(const double *__restrict__ part, int64_t nb,
+                                                             unsigned long long *__restrict__ amax_bits)
+{
+    __shared__ double s_m[kFinThreads / kWave];
+    double m = 0.0;
+#pragma unroll 8
+    for (int64_t i = threadIdx.x; i < nb; i += kFinThreads) m = fmax(m, part[i]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane_id() == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kFinThreads / kWave; ++w) m = fmax(m, s_m[w]);
+        *amax_bits = __builtin_bit_cast(unsigned long long, m);
+    }
 }
 
 __global__ __launch_bounds__(kVecThreads) void ir_scale_kernel(int64_t n, const double *__restrict__ r,
@@ -57,11 +81,6 @@ __global__ void ir_clear_kernel(int64_t n, double *__restrict__ x, unsigned long
     const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
     if (i < n) x[i] = 0.0;
     if (i == 0) *amax_bits = 0ull;
-}
-
-__global__ void ir_zero_bits(unsigned long long *a)
-{
-    if (threadIdx.x == 0) *a = 0ull;
 }
 
 struct IrBufs {
@@ -174,8 +193,8 @@ spx_status ir_run(const spx_matrix &A64_in, const spx_matrix &Alow_in, const dou
             set_error("ir: no convergence in %d refinement steps", max_outer);
             break;
         }
-        ir_zero_bits<<<1, 64, 0, s>>>(w.amax);
-        ir_amax_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.amax);
+        ir_amax_kernel<<<gv, kVecThreads, 0, s>>>(n, w.r, w.partials);
+        ir_amax_finish<<<1, kFinThreads, 0, s>>>(w.partials, gv, w.amax);
         ir_scale_kernel<<<ge, kVecThreads, 0, s>>>(n, w.r, w.amax, w.rf);
         SPX_LAUNCHED();
         // the inner solve need not reduce the residual (much) beyond what is
