@@ -315,7 +315,7 @@ spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const dou
  *    system's CG iterations by themselves (product, updates and fixed-order
  *    reductions inside the group);
  *  - wide systems (n >= 16384 by default): several work-groups per system,
- *    one CG iteration as four grid-wide launches over every wide system at
+ *    one CG iteration as three grid-wide launches over every wide system at
  *    once, each system cut into fixed blocks of 1024 rows whose partial sums
  *    are added in a fixed order.
  * Neither path lets one system's arithmetic depend on another's, so a

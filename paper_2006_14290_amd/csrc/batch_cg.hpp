@@ -93,8 +93,7 @@ struct WideState {
 };
 
 // Header of the virtual-block maps, device memory: {total virtual row blocks,
-// number of listed systems, total product tiles}; list[] holds the slot
-// index of each listed system.
+// number of listed systems, total product tiles}.
 struct WideMap {
     int32_t total_vb;
     int32_t nlisted;
@@ -104,13 +103,15 @@ struct WideMap {
 
 inline int32_t wide_nvb(int64_t n) { return (int32_t)((n + kWideRows - 1) / kWideRows); }
 
-// One iteration (four launches: product, update, direction, commit) for all
-// listed wide systems. grid: physical blocks of the product and vector
-// phases. ta_slot / ta_local map product tiles, vb_slot / vb_local vector
-// blocks to (system, local index).
-spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
-                                 const int32_t *vb_slot, const int32_t *vb_local, const int32_t *ta_slot,
-                                 const int32_t *ta_local, int grid, int commit_grid, hipStream_t stream);
+// One iteration (three launches: product, update, direction with commit)
+// for all listed wide systems, reading the systems' state from st and
+// writing it to st_next (callers alternate two buffers, so an even number
+// of iterations leaves the state in the first). grid: physical blocks of
+// every phase. ta_slot / ta_local map product tiles, vb_slot / vb_local
+// vector blocks to (system, local index).
+spx_status wide_iteration_launch(const WideSlot *slots, const WideState *st, WideState *st_next,
+                                 const WideMap *map, const int32_t *vb_slot, const int32_t *vb_local,
+                                 const int32_t *ta_slot, const int32_t *ta_local, int grid, hipStream_t stream);
 
 // Systems of at most kBatchSmallRows rows are advanced by their own kernel
 // (batch_small_launch; one 512-thread work-group per system with p in LDS

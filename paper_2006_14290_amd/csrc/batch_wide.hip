@@ -1,7 +1,7 @@
 // batch_wide.hip -- CG on many large systems at once, several work-groups per
 // system, no synchronisation between work-groups inside a launch.
 //
-// Unpreconditioned CG (Hestenes & Stiefel), x0 = 0, one iteration as four
+// Unpreconditioned CG (Hestenes & Stiefel), x0 = 0, one iteration as three
 // grid-wide phases over every listed system (a launch boundary is the only
 // global synchronisation):
 //   A  q = A p (or q = A x in the true-residual mode), partial sums of p.q:
@@ -9,9 +9,9 @@
 //   B  alpha = rho / p.q from the partials; x += alpha p, r -= alpha q,
 //      partial sums of r.r (true-residual mode: r = b - q; init: r = b);
 //   C  beta = r.r / rho from the partials; p = r + beta p (or p = r on a
-//      restart or at init) -- skipped once r.r passes the tolerance;
-//   D  commit: one work-group per system re-forms the same sums and updates
-//      the scalar state (rho, iteration count, mode, status).
+//      restart or at init) -- skipped once r.r passes the tolerance; the
+//      first block of each system also commits its scalar state (rho,
+//      iteration count, mode, status) into the other of two state buffers.
 // Every work-group that needs a sum forms it from the same partials in the
 // same order, so all of them take the same decisions. A system's virtual
 // blocks, partials and summation order depend only on its own size; its
@@ -112,38 +112,6 @@ __global__ __launch_bounds__(kWideThreads) void wide_b_kernel(const WideSlot *__
     }
 }
 
-__global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__restrict__ slots,
-                                                              const WideState *__restrict__ st,
-                                                              const WideMap *__restrict__ map,
-                                                              const int32_t *__restrict__ vb_slot,
-                                                              const int32_t *__restrict__ vb_local)
-{
-    __shared__ double s_red[kWideWaves];
-    const int32_t total = map->total_vb;
-    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
-        const int32_t s = vb_slot[v], lv = vb_local[v];
-        const int32_t mode = st[s].mode;
-        if (mode == kWideDone) continue;
-        const WideSlot S = slots[s];
-        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
-        const double bb = st[s].bb;
-        if (mode == kWideRun) {
-            const double pq = wide_part_sum(S.part_a, S.ntiles, s_red);
-            if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;
-            const double rr = wide_part_sum(S.part, S.nvb, s_red);
-            if (!__builtin_isfinite(rr) || rr <= S.tol2 * bb) continue;  // stop or check next
-            const double beta = rr / st[s].rho;
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i] + beta * S.p[i];
-        } else if (mode == kWideCheck) {
-            const double tr = wide_part_sum(S.part, S.nvb, s_red);
-            if (tr <= S.tol2 * bb) continue;
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];  // restart
-        } else {
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];
-        }
-    }
-}
-
 // Scalar state update of one system from the two partial sums of this
 // iteration (s1: p.q, s2: r.r or the true residual or b.b).
 __device__ void commit(WideState &W, const WideSlot &S, double s1, double s2)
@@ -208,39 +176,65 @@ __device__ void commit(WideState &W, const WideSlot &S, double s1, double s2)
     if (W.mode == kWideDone && W.status != kSlotConverged) W.relres_true = W.bb > 0 ? sqrt(W.rr / W.bb) : 0.0;
 }
 
-// Commit: one work-group per listed system.
-__global__ __launch_bounds__(kWideThreads) void wide_d_kernel(const WideSlot *__restrict__ slots,
-                                                              WideState *__restrict__ st,
+// Direction phase and commit. The first virtual block of every system also
+// forms the two sums of the iteration (the same partials in the same order
+// as every other block) and writes the system's updated state to st_next,
+// while all blocks read this iteration's state from st (the two buffers
+// alternate from one iteration to the next).
+__global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__restrict__ slots,
+                                                              const WideState *__restrict__ st,
+                                                              WideState *__restrict__ st_next,
                                                               const WideMap *__restrict__ map,
-                                                              const int32_t *__restrict__ list)
+                                                              const int32_t *__restrict__ vb_slot,
+                                                              const int32_t *__restrict__ vb_local)
 {
     __shared__ double s_red[kWideWaves];
-    const int32_t nl = map->nlisted;
-    for (int32_t k = blockIdx.x; k < nl; k += gridDim.x) {
-        const int32_t s = list[k];
-        WideState W = st[s];
-        if (W.mode == kWideDone) continue;
+    const int32_t total = map->total_vb;
+    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
+        const int32_t s = vb_slot[v], lv = vb_local[v];
+        const WideState W0 = st[s];
+        const bool lead = lv == 0;  // this block commits the system's state
+        if (W0.mode == kWideDone) {
+            if (lead && threadIdx.x == 0) st_next[s] = W0;
+            continue;
+        }
         const WideSlot S = slots[s];
-        const double s1 = wide_part_sum(S.part_a, S.ntiles, s_red);
-        const double s2 = wide_part_sum(S.part, S.nvb, s_red);
-        if (threadIdx.x == 0) {
+        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
+        const double bb = W0.bb;
+        double s1 = 0.0, s2 = 0.0;
+        if (W0.mode == kWideRun) {
+            s1 = wide_part_sum(S.part_a, S.ntiles, s_red);  // p.q
+            s2 = wide_part_sum(S.part, S.nvb, s_red);       // r.r
+            const bool step = s1 > 0.0 && __builtin_isfinite(s1) && __builtin_isfinite(s2) && !(s2 <= S.tol2 * bb);
+            if (step) {  // otherwise the solve stops or checks next
+                const double beta = s2 / W0.rho;
+                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i] + beta * S.p[i];
+            }
+        } else if (W0.mode == kWideCheck) {
+            s2 = wide_part_sum(S.part, S.nvb, s_red);  // true r.r
+            if (!(s2 <= S.tol2 * bb))
+                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];  // restart
+        } else {
+            if (lead) s2 = wide_part_sum(S.part, S.nvb, s_red);  // b.b
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];
+        }
+        if (lead && threadIdx.x == 0) {
+            WideState W = W0;
             commit(W, S, s1, s2);
-            st[s] = W;
+            st_next[s] = W;
         }
     }
 }
 
-spx_status wide_iteration_launch(const WideSlot *slots, WideState *st, const WideMap *map, const int32_t *list,
-                                 const int32_t *vb_slot, const int32_t *vb_local, const int32_t *ta_slot,
-                                 const int32_t *ta_local, int grid, int commit_grid, hipStream_t stream)
+spx_status wide_iteration_launch(const WideSlot *slots, const WideState *st, WideState *st_next,
+                                 const WideMap *map, const int32_t *vb_slot, const int32_t *vb_local,
+                                 const int32_t *ta_slot, const int32_t *ta_local, int grid, hipStream_t stream)
 {
     wide_a_kernel<<<grid, kCsrThreads, 0, stream>>>(slots, st, map, ta_slot, ta_local);
     SPX_LAUNCHED();
     wide_b_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
     SPX_LAUNCHED();
-    wide_c_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
-    SPX_LAUNCHED();
-    wide_d_kernel<<<commit_grid, kWideThreads, 0, stream>>>(slots, st, map, list);
+    wide_c_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, st_next, map, vb_slot, vb_local);
     SPX_LAUNCHED();
     return SPX_OK;
 }

@@ -48,7 +48,8 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 constexpr int kWideIters = 8;                    // wide iterations per graph launch
 constexpr int kWideGrids[3] = {256, 1024, 4096};  // physical grids of the wide graphs
-constexpr int kWideCommitGrid = 128;
+// the state alternates between two buffers; an even count ends in the first
+static_assert(kWideIters % 2 == 0, "wide iterations per graph must be even");
 constexpr int32_t kWideDefaultRows = 16384;
 
 // Extra device bytes of a wide system: vector-phase partials, product
@@ -174,8 +175,8 @@ struct spx_server {
     // wide path: descriptor table, device state, map (header, list, virtual blocks)
     WideSlot *wslots_dev = nullptr, *wslots_host = nullptr;
     WideState *wstate_dev = nullptr, *wstate_host = nullptr, *winit_host = nullptr;
+    WideState *wstate2_dev = nullptr;  // odd iterations' state (the host sees only wstate_dev)
     WideMap *wmap_dev = nullptr, *wmap_host = nullptr;
-    int32_t *wlist_dev = nullptr, *wlist_host = nullptr;
     int32_t *vb_dev = nullptr, *vb_host = nullptr;  // [2 * vb_cap]: slot, then local index
     int64_t vb_cap = 0;
     int32_t *ta_dev = nullptr, *ta_host = nullptr;  // [2 * ta_cap]: product tiles, same layout
@@ -393,7 +394,7 @@ bool rebuild_wide_map(spx_server &S)
         if (!a.live || !a.wide || a.staged || a.cancel) continue;
         const int32_t nvb = S.wslots_host[i].nvb, nt = S.wslots_host[i].ntiles;
         if (tot + nvb > S.vb_cap || tta + nt > S.ta_cap) return false;
-        S.wlist_host[nl++] = i;
+        ++nl;
         for (int32_t k = 0; k < nvb; ++k) {
             S.vb_host[tot + k] = i;
             S.vb_host[S.vb_cap + tot + k] = k;
@@ -412,8 +413,6 @@ bool rebuild_wide_map(spx_server &S)
     const size_t tb = sizeof(WideSlot) * S.active.size();
     hipError_t e = hipMemcpyAsync(S.wslots_dev, S.wslots_host, tb, hipMemcpyHostToDevice, S.s_wide);
     if (e == hipSuccess) e = hipMemcpyAsync(S.wmap_dev, S.wmap_host, sizeof(WideMap), hipMemcpyHostToDevice, S.s_wide);
-    if (e == hipSuccess && nl > 0)
-        e = hipMemcpyAsync(S.wlist_dev, S.wlist_host, sizeof(int32_t) * nl, hipMemcpyHostToDevice, S.s_wide);
     if (e == hipSuccess && tot > 0) {
         e = hipMemcpyAsync(S.vb_dev, S.vb_host, sizeof(int32_t) * tot, hipMemcpyHostToDevice, S.s_wide);
         if (e == hipSuccess)
@@ -576,11 +575,11 @@ void server_free(spx_server *S)
     if (S->ev_w0) (void)hipEventDestroy(S->ev_w0);
     if (S->ev_w1) (void)hipEventDestroy(S->ev_w1);
     for (void *p : {(void *)S->pool_base, (void *)S->slots_dev, (void *)S->counter, (void *)S->wslots_dev,
-                    (void *)S->wstate_dev, (void *)S->wmap_dev, (void *)S->wlist_dev, (void *)S->vb_dev,
+                    (void *)S->wstate_dev, (void *)S->wstate2_dev, (void *)S->wmap_dev, (void *)S->vb_dev,
                     (void *)S->ta_dev})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)S->slots_host, (void *)S->wslots_host, (void *)S->wstate_host, (void *)S->winit_host,
-                    (void *)S->wmap_host, (void *)S->wlist_host, (void *)S->vb_host, (void *)S->ta_host})
+                    (void *)S->wmap_host, (void *)S->vb_host, (void *)S->ta_host})
         if (p) (void)hipHostFree(p);
     if (S->s_compute) (void)hipStreamDestroy(S->s_compute);
     if (S->s_copy) (void)hipStreamDestroy(S->s_copy);
@@ -651,9 +650,9 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     if ((e = dev_alloc(&S->slots_dev, ms)) != hipSuccess || (e = host_alloc(&S->slots_host, ms)) != hipSuccess ||
         (e = dev_alloc(&S->counter, 2)) != hipSuccess || (e = dev_alloc(&S->wslots_dev, ms)) != hipSuccess ||
         (e = host_alloc(&S->wslots_host, ms)) != hipSuccess || (e = dev_alloc(&S->wstate_dev, ms)) != hipSuccess ||
+        (e = dev_alloc(&S->wstate2_dev, ms)) != hipSuccess ||
         (e = host_alloc(&S->wstate_host, ms)) != hipSuccess || (e = host_alloc(&S->winit_host, ms)) != hipSuccess ||
         (e = dev_alloc(&S->wmap_dev, 1)) != hipSuccess || (e = host_alloc(&S->wmap_host, 1)) != hipSuccess ||
-        (e = dev_alloc(&S->wlist_dev, ms)) != hipSuccess || (e = host_alloc(&S->wlist_host, ms)) != hipSuccess ||
         (e = dev_alloc(&S->vb_dev, 2 * (size_t)S->vb_cap)) != hipSuccess ||
         (e = host_alloc(&S->vb_host, 2 * (size_t)S->vb_cap)) != hipSuccess ||
         (e = dev_alloc(&S->ta_dev, 2 * (size_t)S->ta_cap)) != hipSuccess ||
@@ -687,10 +686,11 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
             S->s_wide,
             [&](hipStream_t st) {
                 for (int it = 0; it < kWideIters; ++it) {
-                    spx_status s1 = wide_iteration_launch(S->wslots_dev, S->wstate_dev, S->wmap_dev, S->wlist_dev,
-                                                          S->vb_dev, S->vb_dev + S->vb_cap, S->ta_dev,
-                                                          S->ta_dev + S->ta_cap, kWideGrids[gi],
-                                                          kWideCommitGrid, st);
+                    WideState *cur = (it & 1) ? S->wstate2_dev : S->wstate_dev;
+                    WideState *next = (it & 1) ? S->wstate_dev : S->wstate2_dev;
+                    spx_status s1 = wide_iteration_launch(S->wslots_dev, cur, next, S->wmap_dev, S->vb_dev,
+                                                          S->vb_dev + S->vb_cap, S->ta_dev, S->ta_dev + S->ta_cap,
+                                                          kWideGrids[gi], st);
                     if (s1 != SPX_OK) return s1;
                 }
                 return SPX_OK;
@@ -829,7 +829,7 @@ bool batch_is_wide(const spx_batch_system &s)
 // Workspace: narrow slot table, counter, wide tables, then per system r, p, q
 // (+ 2 * nvb partial sums for wide systems).
 struct BatchLayout {
-    size_t slots, counter, wslots, wstate, wmap, wlist, vb, ta, vectors, total;
+    size_t slots, counter, wslots, wstate, wmap, vb, ta, vectors, total;
     int64_t nwide, total_vb, total_ta;
 };
 
@@ -849,12 +849,10 @@ BatchLayout batch_layout(const spx_batch_system *sys, int32_t count)
     off += 256;
     L.wslots = off;
     off += align256(sizeof(WideSlot) * (size_t)L.nwide);
-    L.wstate = off;
-    off += align256(sizeof(WideState) * (size_t)L.nwide);
+    L.wstate = off;  // two buffers: even and odd iterations
+    off += align256(sizeof(WideState) * 2 * (size_t)L.nwide);
     L.wmap = off;
     off += 256;
-    L.wlist = off;
-    off += align256(sizeof(int32_t) * (size_t)L.nwide);
     L.vb = off;
     off += align256(sizeof(int32_t) * 2 * (size_t)L.total_vb);
     L.ta = off;
@@ -898,14 +896,13 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
     WideSlot *wslots_dev = reinterpret_cast<WideSlot *>(base + L.wslots);
     WideState *wstate_dev = reinterpret_cast<WideState *>(base + L.wstate);
     WideMap *wmap_dev = reinterpret_cast<WideMap *>(base + L.wmap);
-    int32_t *wlist_dev = reinterpret_cast<int32_t *>(base + L.wlist);
     int32_t *vb_dev = reinterpret_cast<int32_t *>(base + L.vb);
     int32_t *ta_dev = reinterpret_cast<int32_t *>(base + L.ta);
     size_t off = L.vectors;
     std::vector<BatchSlot> host((size_t)count);
     std::vector<WideSlot> whost;
     std::vector<WideState> wstate;
-    std::vector<int32_t> wlist, vb((size_t)(2 * L.total_vb)), ta((size_t)(2 * L.total_ta)), widx((size_t)count, -1);
+    std::vector<int32_t> vb((size_t)(2 * L.total_vb)), ta((size_t)(2 * L.total_ta)), widx((size_t)count, -1);
     int64_t tot = 0, tta = 0;
     int32_t maxit_max = 1;
     for (int32_t i = 0; i < count; ++i) {
@@ -967,7 +964,6 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
             WideState s0{};
             s0.mode = kWideInit;
             wstate.push_back(s0);
-            wlist.push_back(k);
             d.status = kSlotEmpty;  // the one-group kernel skips it
         } else {
             d.rowptr = sys[i].rowptr;
@@ -1000,7 +996,6 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
         SPX_HIP(hipMemcpyAsync(wslots_dev, whost.data(), sizeof(WideSlot) * whost.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(wstate_dev, wstate.data(), sizeof(WideState) * wstate.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(wmap_dev, &m, sizeof(m), hipMemcpyHostToDevice, stream));
-        SPX_HIP(hipMemcpyAsync(wlist_dev, wlist.data(), sizeof(int32_t) * wlist.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(vb_dev, vb.data(), sizeof(int32_t) * vb.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(ta_dev, ta.data(), sizeof(int32_t) * ta.size(), hipMemcpyHostToDevice, stream));
         const int grid = (int)std::min<int64_t>(std::max(L.total_vb, L.total_ta), 4096);
@@ -1008,10 +1003,10 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
         // followed by one, so 2 * maxit + 4 iterations finish every system
         const int64_t limit = 2 * (int64_t)maxit_max + 4;
         for (int64_t done = 0; done < limit;) {
-            for (int k = 0; k < 16; ++k, ++done)
-                SPX_CHECK(wide_iteration_launch(wslots_dev, wstate_dev, wmap_dev, wlist_dev, vb_dev,
-                                                vb_dev + L.total_vb, ta_dev, ta_dev + L.total_ta, grid,
-                                                kWideCommitGrid, stream));
+            for (int k = 0; k < 16; ++k, ++done)  // even: the state ends in the first buffer
+                SPX_CHECK(wide_iteration_launch(wslots_dev, (k & 1) ? wstate_dev + L.nwide : wstate_dev,
+                                                (k & 1) ? wstate_dev : wstate_dev + L.nwide, wmap_dev, vb_dev,
+                                                vb_dev + L.total_vb, ta_dev, ta_dev + L.total_ta, grid, stream));
             SPX_HIP(hipMemcpyAsync(wstate.data(), wstate_dev, sizeof(WideState) * wstate.size(), hipMemcpyDeviceToHost,
                                    stream));
             SPX_HIP(hipStreamSynchronize(stream));
