@@ -15,8 +15,8 @@
 // persistent one-group-per-system kernels over the slot table: the
 // small-system kernel, then the general one) advances every system below
 // the wide threshold by its iteration budget; the wide graph (kWideIters iterations
-// of the four wide phases) advances every large system, launched as many
-// times as fits the tick. Between ticks the worker reads the state back,
+// of the three wide phases, the state alternating between two buffers)
+// advances every large system, launched as many times as fits the tick. Between ticks the worker reads the state back,
 // copies the solutions of finished systems to the callers' buffers, frees
 // their memory and slots, and admits more: new requests join within a few
 // milliseconds (continuous batching). Matrices and Krylov state stay resident
