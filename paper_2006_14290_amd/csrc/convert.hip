@@ -139,45 +139,88 @@ static spx_status fill(T *a, int64_t n, T v, hipStream_t stream)
     return SPX_OK;
 }
 
-// Row-length statistics: max over rows, and the histogram of lengths.
+// Row-length statistics: max over rows, and the histogram of lengths. A
+// block takes kStatRows consecutive rows (thread t reads rows t, t + 256, ...:
+// coalesced) and combines them in LDS, so the global atomics are one per
+// block (max) or one per non-empty bin and block (histogram) instead of one
+// per wavefront or row on a handful of addresses.
+constexpr int kStatItems = 16;
+constexpr int kStatRows = kCvThreads * kStatItems;
+constexpr int kHistLdsBins = 4096;  // row lengths below this are counted in LDS
+
 __global__ __launch_bounds__(kCvThreads) void row_len_max_kernel(const int32_t *__restrict__ rowptr, int32_t n,
                                                                 int32_t *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    int32_t l = (i < n) ? rowptr[i + 1] - rowptr[i] : 0;
-    // wavefront max, then one atomic per wavefront
+    __shared__ int32_t s_max[kCvThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kStatRows;
+    int32_t l = 0;
+#pragma unroll 4
+    for (int u = 0; u < kStatItems; ++u) {
+        const int64_t i = base + (int64_t)u * kCvThreads + threadIdx.x;
+        if (i < n) {
+            const int32_t v = rowptr[i + 1] - rowptr[i];
+            l = v > l ? v : l;
+        }
+    }
     for (int off = 32; off >= 1; off >>= 1) {
         const int o = __shfl_xor(l, off);
         l = o > l ? o : l;
     }
-    if (lane_id() == 0) atomicMax(out, l);
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = s_max[0];
+        for (int w = 1; w < kCvThreads / kWave; ++w) m = s_max[w] > m ? s_max[w] : m;
+        atomicMax(out, m);
+    }
 }
 
+// hist has nb = max row length + 1 bins.
 __global__ __launch_bounds__(kCvThreads) void row_len_hist_kernel(const int32_t *__restrict__ rowptr, int32_t n,
-                                                                 unsigned long long *__restrict__ hist)
+                                                                 int64_t nb, unsigned long long *__restrict__ hist)
 {
-    const int64_t i = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    if (i < n) atomicAdd(hist + (rowptr[i + 1] - rowptr[i]), 1ull);
+    __shared__ uint32_t h[kHistLdsBins];
+    const int lds_bins = nb < kHistLdsBins ? (int)nb : kHistLdsBins;
+    for (int t = threadIdx.x; t < lds_bins; t += kCvThreads) h[t] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kStatRows;
+    for (int u = 0; u < kStatItems; ++u) {
+        const int64_t i = base + (int64_t)u * kCvThreads + threadIdx.x;
+        if (i < n) {
+            const int32_t len = rowptr[i + 1] - rowptr[i];
+            if (len < lds_bins) atomicAdd(&h[len], 1u);
+            else atomicAdd(hist + len, 1ull);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < lds_bins; t += kCvThreads)
+        if (h[t] != 0u) atomicAdd(hist + t, (unsigned long long)h[t]);
 }
 
 // ------------------------------------------------------------------ CSR -> COO
+// A block takes kCvThreads consecutive rows and writes the row index of
+// each of their entries [A, B) in entry order (consecutive threads write
+// consecutive entries); the row of entry p is found by bisection over the
+// block's row pointers in LDS (empty rows are skipped by the bisection).
 __global__ __launch_bounds__(kCvThreads) void csr_rows_kernel(const int32_t *__restrict__ rowptr, int32_t n,
                                                              int32_t *__restrict__ row_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * kCvThreads + threadIdx.x;
-    const int32_t a = (i < n) ? rowptr[i] : 0;
-    const int32_t b = (i < n) ? rowptr[i + 1] : 0;
-    const bool longrow = (b - a) > kWave;
-    if (!longrow)
-        for (int32_t p = a; p < b; ++p) row_out[p] = (int32_t)i;
-    // rows longer than a wavefront: the whole wavefront writes them, one at a time
-    lane_mask_t m = ballot64(longrow);
-    while (m) {
-        const int src = __builtin_ctzll(m);
-        m &= m - 1;
-        const int32_t ra = readlane(a, src), rb = readlane(b, src);
-        const int32_t rid = readlane((int)i, src);
-        for (int32_t p = ra + lane_id(); p < rb; p += kWave) row_out[p] = rid;
+    __shared__ int32_t s_rp[kCvThreads + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * kCvThreads;
+    const int64_t rend = r0 + kCvThreads < (int64_t)n ? r0 + kCvThreads : (int64_t)n;
+    const int nr = (int)(rend - r0);  // 1 .. kCvThreads
+    if (threadIdx.x <= nr) s_rp[threadIdx.x] = rowptr[r0 + threadIdx.x];
+    if (threadIdx.x == 0 && nr == kCvThreads) s_rp[kCvThreads] = rowptr[rend];
+    __syncthreads();
+    const int32_t A = s_rp[0], B = s_rp[nr];
+    for (int64_t p = (int64_t)A + threadIdx.x; p < B; p += kCvThreads) {
+        int lo = 0, hi = nr;  // s_rp[lo] <= p < s_rp[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_rp[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        row_out[p] = (int32_t)(r0 + lo);
     }
 }
 
@@ -572,7 +615,7 @@ spx_status csr_max_row_len(const spx_matrix &A, int32_t *out, hipStream_t stream
     int32_t *dm = static_cast<int32_t *>(d.p);
     SPX_CHECK(fill<int32_t>(dm, 1, 0, stream));
     if (A.nrows > 0) {
-        row_len_max_kernel<<<(unsigned)ceil_div(A.nrows, kCvThreads), kCvThreads, 0, stream>>>(A.rowptr, A.nrows, dm);
+        row_len_max_kernel<<<(unsigned)ceil_div(A.nrows, kStatRows), kCvThreads, 0, stream>>>(A.rowptr, A.nrows, dm);
         SPX_LAUNCHED();
     }
     return read_scalar(dm, out, stream);
@@ -588,8 +631,8 @@ static spx_status hyb_auto_width(const spx_matrix &A, int32_t maxlen, int32_t *K
     auto *hist = static_cast<unsigned long long *>(d.p);
     SPX_CHECK(fill<unsigned long long>(hist, (int64_t)nb, 0ull, stream));
     if (A.nrows > 0) {
-        row_len_hist_kernel<<<(unsigned)ceil_div(A.nrows, kCvThreads), kCvThreads, 0, stream>>>(A.rowptr, A.nrows,
-                                                                                               hist);
+        row_len_hist_kernel<<<(unsigned)ceil_div(A.nrows, kStatRows), kCvThreads, 0, stream>>>(A.rowptr, A.nrows,
+                                                                                               (int64_t)nb, hist);
         SPX_LAUNCHED();
     }
     std::vector<unsigned long long> h(nb);
