@@ -14,35 +14,41 @@
 
 namespace spx {
 
-constexpr int kBjMax = 32;
-constexpr int kBjStride = 2 * kBjMax;  // LDS row stride of the augmented block
-
-template <typename V>
+// One wavefront per block of BS rows. The augmented block [D_k | I] sits in
+// LDS with an odd row stride, so a column read by the pivot search (lane r
+// reads row r) touches distinct banks. Lane c owns column c: after the pivot
+// row is normalised, every lane c != j eliminates column j from its own
+// column (a_rc -= a_rj * a_jc for r != j). Column j itself is not updated
+// (it is never read again: later steps read only later pivot columns and the
+// right half), so no lane writes what another reads within a step and a step
+// needs no barrier per row.
+template <typename V, int BS>
 __global__ __launch_bounds__(kWave) void bj_setup_kernel(const int32_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ col,
-                                                        const V *__restrict__ val, int32_t n, int32_t bs,
+                                                        const V *__restrict__ val, int32_t n,
                                                         double *__restrict__ inv, KState *st)
 {
-    __shared__ double a[kBjMax * kBjStride];
+    constexpr int S = 2 * BS + 1;
+    __shared__ double a[BS * S];
     const int64_t k = blockIdx.x;
-    const int64_t i0 = k * bs;
-    const int m = (int)min((int64_t)bs, n - i0);
+    const int64_t i0 = k * BS;
+    const int m = (int)min((int64_t)BS, n - i0);
     const int w = 2 * m;
     const int lane = threadIdx.x;
-    for (int t = lane; t < kBjMax * kBjStride; t += kWave) a[t] = 0.0;
+    for (int t = lane; t < BS * S; t += kWave) a[t] = 0.0;
     __syncthreads();
     if (lane < m) {
         for (int32_t p = rowptr[i0 + lane]; p < rowptr[i0 + lane + 1]; ++p) {
             const int32_t c = col[p];
-            if (c >= i0 && c < i0 + m) a[lane * kBjStride + (c - i0)] = (double)val[p];
+            if (c >= i0 && c < i0 + m) a[lane * S + (c - i0)] = (double)val[p];
         }
-        a[lane * kBjStride + m + lane] = 1.0;
+        a[lane * S + m + lane] = 1.0;
     }
     __syncthreads();
     bool ok = true;
     for (int j = 0; j < m; ++j) {
         // pivot: largest |a_rj| over r >= j, lowest r on ties (wavefront argmax)
-        double v = (lane >= j && lane < m) ? fabs(a[lane * kBjStride + j]) : -1.0;
+        double v = (lane >= j && lane < m) ? fabs(a[lane * S + j]) : -1.0;
         int idx = lane;
         for (int off = kWave / 2; off >= 1; off >>= 1) {
             const double ov = __shfl_xor(v, off);
@@ -53,35 +59,35 @@ __global__ __launch_bounds__(kWave) void bj_setup_kernel(const int32_t *__restri
             }
         }
         const int piv = idx;
-        const double d = a[piv * kBjStride + j];
+        const double d = a[piv * S + j];
         if (d == 0.0 || !__builtin_isfinite(d)) {
             ok = false;
             break;
         }
+        __syncthreads();  // every lane has read d before the swap moves it
         if (piv != j && lane < w) {
-            const double t = a[j * kBjStride + lane];
-            a[j * kBjStride + lane] = a[piv * kBjStride + lane];
-            a[piv * kBjStride + lane] = t;
+            const double t = a[j * S + lane];
+            a[j * S + lane] = a[piv * S + lane];
+            a[piv * S + lane] = t;
         }
         __syncthreads();
-        if (lane < w) a[j * kBjStride + lane] /= d;
+        if (lane < w) a[j * S + lane] /= d;
         __syncthreads();
-        for (int r = 0; r < m; ++r) {
-            if (r == j) continue;
-            const double f = a[r * kBjStride + j];
-            __syncthreads();  // every lane has f before lane j overwrites a_rj
-            if (lane < w) a[r * kBjStride + lane] -= f * a[j * kBjStride + lane];
-            __syncthreads();
+        if (lane < w && lane != j) {
+            const double pj = a[j * S + lane];
+            for (int r = 0; r < m; ++r)
+                if (r != j) a[r * S + lane] -= a[r * S + j] * pj;
         }
+        __syncthreads();
     }
     if (!ok) {
         if (lane == 0) atomicMax(&st->flag, (int32_t)kBreakdown);
         return;
     }
     // column-major inverse; rows / columns past m of a last, smaller block are 0
-    for (int t = lane; t < bs * bs; t += kWave) {
-        const int j = t / bs, i = t % bs;
-        inv[k * bs * bs + t] = (i < m && j < m) ? a[i * kBjStride + m + j] : 0.0;
+    for (int t = lane; t < BS * BS; t += kWave) {
+        const int j = t / BS, i = t % BS;
+        inv[k * BS * BS + t] = (i < m && j < m) ? a[i * S + m + j] : 0.0;
     }
 }
 
@@ -123,8 +129,19 @@ spx_status bj_setup(const spx_matrix &A, int32_t bs, double *inv, KState *st, hi
 {
     const int64_t nb = ceil_div(A.nrows, bs);
     if (nb == 0) return SPX_OK;
-    bj_setup_kernel<V><<<(unsigned)nb, kWave, 0, stream>>>(A.rowptr, A.colidx, static_cast<const V *>(A.vals),
-                                                           A.nrows, bs, inv, st);
+    const V *val = static_cast<const V *>(A.vals);
+#define SPX_BJ_SETUP(BS)                                                                                             \
+    bj_setup_kernel<V, BS><<<(unsigned)nb, kWave, 0, stream>>>(A.rowptr, A.colidx, val, A.nrows, inv, st)
+    switch (bs) {
+    case 1: SPX_BJ_SETUP(1); break;
+    case 2: SPX_BJ_SETUP(2); break;
+    case 4: SPX_BJ_SETUP(4); break;
+    case 8: SPX_BJ_SETUP(8); break;
+    case 16: SPX_BJ_SETUP(16); break;
+    case 32: SPX_BJ_SETUP(32); break;
+    default: SPX_REQUIRE(false, SPX_ERR_ARG, "block-Jacobi block size %d is not a power of two <= 32", bs);
+    }
+#undef SPX_BJ_SETUP
     SPX_LAUNCHED();
     return SPX_OK;
 }
