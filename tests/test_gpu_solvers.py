@@ -377,6 +377,27 @@ def test_cg_block_jacobi_block_diagonal_one_iteration():
     np.testing.assert_allclose(host(x), np.linalg.solve(d, b), rtol=1e-11, atol=1e-12)
 
 
+@pytest.mark.parametrize("bs", [2, 4, 8, 16, 32])
+def test_cg_block_jacobi_exact_blocks_every_size(bs):
+    """A block-diagonal SPD matrix whose blocks are the preconditioner's
+    (the last one partial, bs - 1 rows): M = A, so one CG iteration solves it
+    exactly; checks every block-size instantiation of the setup kernel."""
+    rng = np.random.default_rng(10 + bs)
+    sizes = [bs] * 40 + [bs - 1]
+    n = sum(sizes)
+    d = np.zeros((n, n))
+    i0 = 0
+    for m in sizes:
+        g = rng.uniform(-1, 1, (m, m))
+        d[i0:i0 + m, i0:i0 + m] = g @ g.T + m * np.eye(m)
+        i0 += m
+    A = S.from_dense(d)
+    b = rng.uniform(-1, 1, n)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), tol=1e-12, precond=bs)
+    assert info["status"] == spx.OK and info["iters"] == 1, info
+    np.testing.assert_allclose(host(x), np.linalg.solve(d, b), rtol=1e-10, atol=1e-12)
+
+
 def test_cg_block_jacobi_errors():
     d = np.eye(64)
     d[2:4, 2:4] = [[1.0, 2.0], [2.0, 4.0]]  # a singular 2 x 2 block
