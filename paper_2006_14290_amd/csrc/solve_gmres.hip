@@ -193,16 +193,30 @@ __global__ __launch_bounds__(kFinThreads) void gm_step_finish(const X *__restric
     else if (st->rr <= st->tol2 * st->bb || hn == 0.0 || st->iters >= st->maxit || j + 1 == m) st->flag = kCycleEnd;
 }
 
-// y = H(0:jend,0:jend)^{-1} g (back substitution, one thread)
-__global__ void gm_solve_kernel(KState *st, GmState gs)
+// y = H(0:jend,0:jend)^{-1} g (back substitution)
+__global__ __launch_bounds__(kWave) void gm_solve_kernel(KState *st, GmState gs)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // the wavefront stages the triangle and g in LDS, then one lane runs
+    // the substitution (in the same order) on LDS instead of on dependent
+    // global loads
+    __shared__ double s_h[(kMaxDots - 1) * kMaxDots];
+    __shared__ double s_y[kMaxDots];
     const int jend = st->jend, m = gs.m;
-    for (int i = jend - 1; i >= 0; --i) {
-        double s = gs.g[i];
-        for (int k = i + 1; k < jend; ++k) s -= gs.H[(int64_t)k * (m + 1) + i] * gs.y[k];
-        gs.y[i] = s / gs.H[(int64_t)i * (m + 1) + i];
+    for (int t = threadIdx.x; t < jend * jend; t += kWave) {
+        const int k = t / jend, i = t % jend;
+        if (i <= k) s_h[k * kMaxDots + i] = gs.H[(int64_t)k * (m + 1) + i];
     }
+    for (int t = threadIdx.x; t < jend; t += kWave) s_y[t] = gs.g[t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = jend - 1; i >= 0; --i) {
+            double s = s_y[i];
+            for (int k = i + 1; k < jend; ++k) s -= s_h[k * kMaxDots + i] * s_y[k];
+            s_y[i] = s / s_h[i * kMaxDots + i];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < jend; t += kWave) gs.y[t] = s_y[t];
 }
 
 // x += M^{-1} V y
