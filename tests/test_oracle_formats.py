@@ -67,6 +67,51 @@ def test_hyb_round_trip_and_counts(K):
     _same_csr(A, O.hyb_to_csr(H))
 
 
+def _hand_hyb_matrix():
+    # six rows of lengths 1, 3, 0, 5, 2, 0 (columns ascending, values 1..13 in entry order)
+    rowptr = np.array([0, 1, 4, 4, 9, 11, 11], np.int32)
+    col = np.array([4, 0, 2, 5, 0, 1, 2, 3, 5, 1, 4], np.int32)
+    return S.CSR(6, rowptr, col, np.arange(1.0, 12.0))
+
+
+def test_hyb_split_hand_worked_width2():
+    """The split the Hybrid format of Section 1 implies (ELL part = each row's
+    first min(len, K) entries, COO part = the rest in row-major order),
+    written out by hand for K = 2 and a leading dimension above n."""
+    H = O.csr_to_hyb(_hand_hyb_matrix(), K=2, ld=8)
+    E = H.ell
+    assert (E.K, E.ld) == (2, 8)
+    # slot 0 then slot 1, eight rows each (rows 6 and 7 are beyond n: never written)
+    exp_col = [4, 0, -1, 0, 1, -1, -1, -1,
+               -1, 2, -1, 1, 4, -1, -1, -1]
+    exp_val = [1, 2, 0, 5, 10, 0, 0, 0,
+               0, 3, 0, 6, 11, 0, 0, 0]
+    np.testing.assert_array_equal(E.col, exp_col)
+    np.testing.assert_array_equal(_bits(E.val), _bits(np.array(exp_val, np.float64)))
+    # COO part: row 1's third entry, then row 3's last three, in row-major order
+    np.testing.assert_array_equal(H.row, [1, 3, 3, 3])
+    np.testing.assert_array_equal(H.col, [5, 2, 3, 5])
+    np.testing.assert_array_equal(H.val, [4.0, 7.0, 8.0, 9.0])
+
+
+def test_hyb_split_hand_worked_wide_and_zero():
+    A = _hand_hyb_matrix()
+    # K above every row length: everything in the ELL part, left-packed, no COO part
+    H = O.csr_to_hyb(A, K=7)
+    assert len(H.row) == 0 and H.ell.ld == 6
+    lens = [1, 3, 0, 5, 2, 0]
+    exp = np.full((7, 6), -1, np.int32)
+    for i, L in enumerate(lens):
+        exp[:L, i] = A.col[A.rowptr[i]:A.rowptr[i] + L]
+    np.testing.assert_array_equal(H.ell.col.reshape(7, 6), exp)
+    # K = 0: the COO part is the whole matrix in CSR entry order
+    H0 = O.csr_to_hyb(A, K=0)
+    assert H0.ell.col.size == 0
+    np.testing.assert_array_equal(H0.row, [0, 1, 1, 1, 3, 3, 3, 3, 3, 4, 4])
+    np.testing.assert_array_equal(H0.col, A.col)
+    np.testing.assert_array_equal(H0.val, A.val)
+
+
 def test_hyb_auto_width_hand_examples():
     # lengths [1,1,1,10], sv=8, si=4: bytes(K) = 4*K*12 + excess*16
     # K=0: 208, K=1: 48+144=192, K=2: 96+128=224 -> K=1
