@@ -17,8 +17,9 @@
  *  - Every function returns an spx_status; nothing is thrown across the ABI.
  *    spx_last_error() returns a thread-local description of the last failure.
  *  - Descriptors are checked on the host (shapes, null pointers, type
- *    combinations). Array contents are trusted by the compute calls; an
- *    out-of-range index in them is undefined behaviour.
+ *    combinations). Array contents are trusted by the compute calls (an
+ *    out-of-range index in them is undefined behaviour); spx_validate checks
+ *    them once, on the device, before a matrix is trusted.
  *  - Compute calls are stream-ordered and asynchronous on the hipStream_t
  *    given (0 = the legacy default stream) unless stated otherwise.
  */
@@ -107,6 +108,40 @@ const char *spx_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t spx_version(void);
+
+/* ------------------------------------------------------------ validation
+ * Canonical-form check of a matrix's index arrays: the layouts of the
+ * Section 1 formats (and Sellp, Section 4) that every other call assumes.
+ * The paper specifies no input validation; this is the library's own check,
+ * run once before a matrix is trusted. Reads only index arrays (never
+ * values) and returns the first failing class in this order:
+ *  SPX_ERR_FORMAT    structure: CSR rowptr[0] != 0, rowptr[nrows] != nnz or
+ *                    a decreasing row pointer; an ELL / SELL-P column after a
+ *                    padding slot (-1) of its row, or in a SELL-P padding
+ *                    row; a HYB row with COO entries whose ELL part is not
+ *                    full; stored entries (ELL, HYB, SELL-P) not adding up
+ *                    to nnz; SELL-P slice_sets[0] != 0, a negative width or
+ *                    one not a multiple of stride_factor, or
+ *                    slice_sets[nslices] != slice_cols;
+ *  SPX_ERR_RANGE     a row index outside [0, nrows) or a column outside
+ *                    [0, ncols) (padding -1 excepted);
+ *  SPX_ERR_UNSORTED  columns not strictly ascending inside a row (COO and
+ *                    the COO part of HYB: entries not in (row, col) order;
+ *                    HYB: a row's first COO column not above its last ELL
+ *                    column);
+ *  SPX_ERR_DUPLICATE the same (row, col) stored twice.
+ * spx_last_error() names the class and the smallest position (entry, row or
+ * slice) where it occurs. BLOCKING (synchronizes `stream`); allocates and
+ * frees 40 bytes of device memory. Errors besides the above: SPX_ERR_ARG
+ * (descriptor), SPX_ERR_HIP. */
+spx_status spx_validate(const spx_matrix *A, hipStream_t stream);
+
+/* The CSR checks of spx_validate on HOST arrays (rowptr[nrows+1], colidx[nnz]),
+ * with the same classes, precedence and messages; no device is touched. The
+ * solve server applies it to every request in spx_serve_submit, so no
+ * malformed system reaches the kernels that resident systems share. */
+spx_status spx_validate_csr_host(int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *rowptr,
+                                 const int32_t *colidx);
 
 /* ------------------------------------------------------------ SpMV
  * y = alpha * A x + beta * y  (Section 1: the Coo, Csr, Ell and Hybrid
@@ -367,7 +402,9 @@ typedef struct {
     int32_t tick_us;         /* adaptive budget: target tick length (0 = 2000)  */
     int32_t wide_min_rows;   /* systems with n >= this take the wide path
                                 (0 = 16384, as SPX_BATCH_AUTO; < 0 = never)      */
-    int32_t reserved;
+    int32_t debug_fail_tick; /* testing only: k > 0 makes the worker stop at its
+                                k-th tick as if a HIP call had failed (no device
+                                fault is involved); 0 = off                      */
 } spx_server_config;
 
 typedef struct {
@@ -397,10 +434,17 @@ spx_status spx_serve_submit(spx_server *server, const spx_request *req, uint64_t
  * latency in milliseconds. */
 spx_status spx_serve_poll(spx_server *server, uint64_t ticket, spx_solve_info *info);
 spx_status spx_serve_wait(spx_server *server, uint64_t ticket, double timeout_s, spx_solve_info *info);
-/* Cancels a queued or running request (its status becomes SPX_CANCELLED). */
+/* Cancels a queued or running request: if it returns SPX_OK before the
+ * request has completed, the request ends as SPX_CANCELLED. For a request
+ * that had already completed it returns SPX_OK and changes nothing. */
 spx_status spx_serve_cancel(spx_server *server, uint64_t ticket);
+/* Counters of the server. (Named _get_stats: spx_server_stats is the type.) */
 spx_status spx_server_get_stats(spx_server *server, spx_server_stats *stats);
-/* Stops the worker (queued requests are cancelled) and frees everything. */
+/* If a HIP call fails in the worker, the server stops: every queued and
+ * resident request ends with SPX_ERR_HIP (waiters are woken) and later
+ * submissions return SPX_ERR_HIP. */
+/* Stops the worker (queued and resident requests end as SPX_CANCELLED) and
+ * frees everything. */
 spx_status spx_server_destroy(spx_server *server);
 
 /* ------------------------------------------------------------ subwarp primitives

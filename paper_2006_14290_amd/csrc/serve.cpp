@@ -35,6 +35,7 @@
 
 #include "batch_cg.hpp"
 #include "common.hpp"
+#include "spmv.hpp"
 #include "spmv_csr.hpp"
 
 using namespace spx;
@@ -134,8 +135,12 @@ struct Active {
     double *x_out = nullptr;
     int64_t n = 0, nnz = 0;
     Clock::time_point t_submit;
-    bool cancel = false;
-    bool live = false;
+    // Set by spx_serve_cancel under the server mutex, read by the worker
+    // without it (hence atomic); the worker reads it again under the mutex
+    // when it retires the system, so a cancel that returned before the
+    // retirement always ends in SPX_CANCELLED.
+    std::atomic<bool> cancel{false};
+    bool live = false;  // written under the mutex (reserve, retire), read by the worker freely
     bool staged = false;  // descriptor waiting in spx_server::staged / wstaged
     bool wide = false;
     bool in_map = false;  // listed in the wide map uploaded for the current tick
@@ -213,10 +218,11 @@ int32_t budget_for(const spx_server &S, int64_t n, int64_t nnz, int32_t remainin
     return (int32_t)b;
 }
 
-void finish_ticket(spx_server &S, uint64_t ticket, spx_status st, const spx_solve_info &info)
+// Record a finished request (the caller holds S.mu).
+void finish_locked(spx_server &S, uint64_t ticket, spx_status st, const spx_solve_info &info)
 {
-    std::lock_guard<std::mutex> lk(S.mu);
     Result &r = S.results[ticket];
+    if (r.done) return;
     r.done = true;
     r.status = st;
     r.info = info;
@@ -236,20 +242,22 @@ int admit(spx_server &S)
             int free_slot = -1;
             for (int i = 0; i < (int)S.active.size(); ++i)
                 if (!S.active[i].live) {
-                    bool claimed = false;
-                    for (auto &t : take) claimed |= (t.first == i);
-                    if (!claimed) {
-                        free_slot = i;
-                        break;
-                    }
+                    free_slot = i;
+                    break;
                 }
             if (free_slot < 0) break;
             size_t off = 0;
             if (S.pool.alloc(it->bytes, &off)) {
                 Pending p = *it;
                 p.bytes = it->bytes;
-                S.active[free_slot].off = off;  // reserve
-                S.active[free_slot].bytes = it->bytes;
+                // reserve the slot where spx_serve_cancel can see the ticket
+                Active &a = S.active[free_slot];
+                a.off = off;
+                a.bytes = it->bytes;
+                a.ticket = p.ticket;
+                a.cancel.store(false);
+                a.live = true;
+                a.staged = true;
                 take.emplace_back(free_slot, p);
                 it = S.queue.erase(it);
             } else {
@@ -324,15 +332,11 @@ int admit(spx_server &S)
             std::memset(&ws, 0, sizeof(ws));
             ws.mode = kWideInit;
             (void)hipMemcpyAsync(S.wstate_dev + si, &ws, sizeof(WideState), hipMemcpyHostToDevice, S.s_copy);
-            a.ticket = p.ticket;
             a.x_dev = x;
             a.x_out = p.req.x_out;
             a.n = n;
             a.nnz = nnz;
             a.t_submit = p.t_submit;
-            a.cancel = false;
-            a.live = true;
-            a.staged = true;
             continue;
         }
         BatchSlot &d = S.staged[si];
@@ -352,15 +356,11 @@ int admit(spx_server &S)
         d.tol2 = p.req.tol * p.req.tol;
         d.maxit = p.req.maxit > 0 ? p.req.maxit : 100000;
         d.budget = 0;  // set before the tick
-        a.ticket = p.ticket;
         a.x_dev = x;
         a.x_out = p.req.x_out;
         a.n = n;
         a.nnz = nnz;
         a.t_submit = p.t_submit;
-        a.cancel = false;
-        a.live = true;
-        a.staged = true;
     }
     return (int)take.size();
 }
@@ -391,7 +391,7 @@ bool rebuild_wide_map(spx_server &S)
     for (int i = 0; i < (int)S.active.size(); ++i) {
         Active &a = S.active[i];
         a.in_map = false;
-        if (!a.live || !a.wide || a.staged || a.cancel) continue;
+        if (!a.live || !a.wide || a.staged || a.cancel.load()) continue;
         const int32_t nvb = S.wslots_host[i].nvb, nt = S.wslots_host[i].ntiles;
         if (tot + nvb > S.vb_cap || tta + nt > S.ta_cap) return false;
         ++nl;
@@ -435,14 +435,15 @@ void retire(spx_server &S)
         Active &a = S.active[i];
         if (!a.live || a.staged) continue;
         spx_solve_info info{};
-        spx_status st;
+        int32_t solver_status;
+        const bool cancel = a.cancel.load();
         if (a.wide) {
             // the host copy of the state is current only for systems that were
             // listed in this tick's launches
             const WideState &w = S.wstate_host[i];
             const bool done = a.in_map && w.mode == kWideDone;
-            if (!done && !a.cancel) continue;
-            st = a.cancel ? SPX_CANCELLED : slot_status_to_spx(w.status);
+            if (!done && !cancel) continue;
+            solver_status = w.status;
             info.iters = w.iters;
             info.spmv_count = w.spmv;
             info.relres_recursive = w.bb > 0 ? sqrt(w.rr / w.bb) : 0.0;
@@ -450,25 +451,51 @@ void retire(spx_server &S)
             S.wide_dirty = true;
         } else {
             BatchSlot &d = S.slots_host[i];
-            if (d.status == kSlotRunning && !a.cancel) continue;
-            st = a.cancel ? SPX_CANCELLED : slot_status_to_spx(d.status);
+            if (d.status == kSlotRunning && !cancel) continue;
+            solver_status = d.status;
             info.iters = d.iters;
             info.spmv_count = d.spmv;
             info.relres_recursive = d.bb > 0 ? sqrt(d.rr / d.bb) : 0.0;
             info.relres_true = d.relres_true;
             d.status = kSlotEmpty;
         }
-        if (!a.cancel && a.x_out) (void)hipMemcpy(a.x_out, a.x_dev, (size_t)a.n * 8, hipMemcpyDeviceToHost);
-        info.status = st;
+        if (!cancel && a.x_out) (void)hipMemcpy(a.x_out, a.x_dev, (size_t)a.n * 8, hipMemcpyDeviceToHost);
         info.device_ms = std::chrono::duration<double, std::milli>(Clock::now() - a.t_submit).count();
-        {
-            std::lock_guard<std::mutex> lk(S.mu);
-            S.pool.release(a.off, a.bytes);
-        }
-        a.live = false;
         a.in_map = false;
-        finish_ticket(S, a.ticket, st, info);
+        std::lock_guard<std::mutex> lk(S.mu);
+        // a cancel that arrived after the first read still wins: it returned
+        // while the system was live
+        const spx_status st = a.cancel.load() ? SPX_CANCELLED : slot_status_to_spx(solver_status);
+        info.status = st;
+        S.pool.release(a.off, a.bytes);
+        a.live = false;
+        finish_locked(S, a.ticket, st, info);
     }
+}
+
+// Stop serving: every queued and every resident request ends with `st`
+// (SPX_ERR_HIP after a failure, SPX_CANCELLED when the server is destroyed),
+// so no spx_serve_wait is left waiting.
+void fail_all(spx_server &S, spx_status st)
+{
+    std::lock_guard<std::mutex> lk(S.mu);
+    spx_solve_info info{};
+    info.status = st;
+    for (auto &p : S.queue) finish_locked(S, p.ticket, st, info);
+    S.queue.clear();
+    for (auto &a : S.active)
+        if (a.live) {
+            a.live = false;
+            S.pool.release(a.off, a.bytes);
+            finish_locked(S, a.ticket, st, info);
+        }
+    S.cv_done.notify_all();
+}
+
+void set_fatal(spx_server &S, const char *what)
+{
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.fatal = what;
 }
 
 void worker_main(spx_server *Sp)
@@ -485,12 +512,12 @@ void worker_main(spx_server *Sp)
             continue;
         }
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
-            S.fatal = "admission copy failed";
+            set_fatal(S, "admission copy failed");
             break;
         }
         apply_staged(S);
         if (S.wide_dirty && !rebuild_wide_map(S)) {
-            S.fatal = "wide map upload failed";
+            set_fatal(S, "wide map upload failed");
             break;
         }
         const int32_t nwide = S.wmap_host->nlisted;
@@ -498,7 +525,7 @@ void worker_main(spx_server *Sp)
         for (int i = 0; i < (int)S.active.size(); ++i) {
             if (!S.active[i].live || S.active[i].wide) continue;
             BatchSlot &d = S.slots_host[i];
-            if (S.active[i].cancel) {
+            if (S.active[i].cancel.load()) {
                 d.budget = 0;
                 continue;
             }
@@ -527,8 +554,10 @@ void worker_main(spx_server *Sp)
         admit(S);
         if (e == hipSuccess) e = hipStreamSynchronize(S.s_compute);
         if (e == hipSuccess) e = hipStreamSynchronize(S.s_wide);
+        if (e == hipSuccess && S.cfg.debug_fail_tick > 0 && S.stats.ticks + 1 >= S.cfg.debug_fail_tick)
+            e = hipErrorLaunchFailure;  // testing hook: the host pretends this tick failed
         if (e != hipSuccess) {
-            S.fatal = hipGetErrorString(e);
+            set_fatal(S, hipGetErrorString(e));
             break;
         }
         if (nwide > 0) {
@@ -541,7 +570,7 @@ void worker_main(spx_server *Sp)
             }
         }
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
-            S.fatal = "admission copy failed";
+            set_fatal(S, "admission copy failed");
             break;
         }
         {
@@ -551,15 +580,19 @@ void worker_main(spx_server *Sp)
         retire(S);  // before apply_staged: newly admitted systems have no state to read yet
         apply_staged(S);
     }
-    // fail whatever is left
-    std::lock_guard<std::mutex> lk(S.mu);
-    for (auto &p : S.queue) {
-        Result &r = S.results[p.ticket];
-        r.done = true;
-        r.status = SPX_CANCELLED;
+    // whatever is left ends now: failed after an error, cancelled on a stop
+    bool failed;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        failed = !S.fatal.empty();
     }
-    S.queue.clear();
-    S.cv_done.notify_all();
+    if (failed) {
+        // let in-flight copies and kernels finish before the pool is reused
+        (void)hipStreamSynchronize(S.s_compute);
+        (void)hipStreamSynchronize(S.s_wide);
+        (void)hipStreamSynchronize(S.s_copy);
+    }
+    fail_all(S, failed ? SPX_ERR_HIP : SPX_CANCELLED);
 }
 
 }  // namespace
@@ -698,7 +731,7 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
             &S->wide_tick[gi]);
         if (e != hipSuccess) return fail("wide tick capture");
     }
-    S->active.resize(ms);
+    S->active = std::vector<Active>(ms);
     S->staged.resize(ms);
     S->wstaged.resize(ms);
     S->stats.pool_bytes_total = cfg->hbm_budget_bytes;
@@ -715,6 +748,9 @@ extern "C" spx_status spx_serve_submit(spx_server *S, const spx_request *req, ui
                 SPX_ERR_ARG, "spx_serve_submit: bad request");
     SPX_REQUIRE(req->solver == SPX_SOLVER_CG, SPX_ERR_ARG, "spx_serve_submit: only CG is served");
     SPX_REQUIRE(req->tol >= 0.0, SPX_ERR_ARG, "spx_serve_submit: negative tolerance");
+    SPX_REQUIRE(req->nnz <= INT32_MAX, SPX_ERR_ARG, "spx_serve_submit: nnz exceeds int32");
+    // nothing malformed may reach the kernels that every resident system shares
+    SPX_CHECK(validate_csr_host(req->n, req->n, req->nnz, req->rowptr, req->colidx));
     const bool wide = is_wide(S->cfg.wide_min_rows, req->n);
     const size_t bytes = system_bytes(req->n, req->nnz, wide);
     std::lock_guard<std::mutex> lk(S->mu);
@@ -770,22 +806,23 @@ extern "C" spx_status spx_serve_cancel(spx_server *S, uint64_t ticket)
     for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
         if (it->ticket == ticket) {
             S->queue.erase(it);
-            Result &r = S->results[ticket];
-            r.done = true;
-            r.status = SPX_CANCELLED;
-            r.info.status = SPX_CANCELLED;
-            S->stats.completed += 1;
-            S->cv_done.notify_all();
+            spx_solve_info info{};
+            info.status = SPX_CANCELLED;
+            finish_locked(*S, ticket, SPX_CANCELLED, info);
             return SPX_OK;
         }
     }
+    // a request leaves the queue and takes its slot in one locked step, so a
+    // ticket that is neither queued nor resident has finished
     for (auto &a : S->active)
         if (a.live && a.ticket == ticket) {
-            a.cancel = true;  // retired at the end of the next tick
+            a.cancel.store(true);  // retired at the end of the current tick
             return SPX_OK;
         }
     auto it = S->results.find(ticket);
     SPX_REQUIRE(it != S->results.end(), SPX_ERR_ARG, "spx_serve_cancel: unknown ticket");
+    SPX_REQUIRE(it->second.done, SPX_ERR_ARG, "spx_serve_cancel: ticket %llu is neither queued, resident nor done",
+                (unsigned long long)ticket);
     return SPX_OK;  // already finished
 }
 

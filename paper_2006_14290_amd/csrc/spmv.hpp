@@ -7,6 +7,8 @@
 namespace spx {
 
 spx_status check_matrix(const spx_matrix *A, const char *who);
+// Canonical-form checks of host CSR arrays (spx_validate_csr_host).
+spx_status validate_csr_host(int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *rowptr, const int32_t *col);
 spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta,
                          hipStream_t stream);
 

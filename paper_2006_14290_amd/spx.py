@@ -66,6 +66,8 @@ def _sig(name, args, res=ctypes.c_int):
 _sig("spx_status_string", [ctypes.c_int], ctypes.c_char_p)
 _sig("spx_last_error", [], ctypes.c_char_p)
 _sig("spx_version", [], ctypes.c_int32)
+_sig("spx_validate", [_MP, _vp])
+_sig("spx_validate_csr_host", [_i32, _i32, _i64, _vp, _vp])
 _sig("spx_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_analysis_bytes", [_MP], ctypes.c_int64)
@@ -114,7 +116,7 @@ class BatchSystem(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("iters_per_tick", ctypes.c_int32), ("tick_us", ctypes.c_int32), ("wide_min_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("debug_fail_tick", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -339,6 +341,34 @@ def cast_values(A: Matrix, dtype: int, stream=None) -> Matrix:
     return out
 
 
+# ------------------------------------------------------------------ validation
+def validate(A: Matrix, stream=None) -> int:
+    """Canonical-form check of A's index arrays on the device (blocking).
+    Returns the status code (OK, ERR_FORMAT, ERR_RANGE, ERR_UNSORTED or
+    ERR_DUPLICATE); raises SpxError for argument and HIP errors."""
+    st = _lib.spx_validate(ctypes.byref(A.desc()), _stream(stream))
+    if st not in (OK, ERR_FORMAT, ERR_RANGE, ERR_UNSORTED, ERR_DUPLICATE):
+        raise SpxError(st, "spx_validate")
+    return st
+
+
+def validate_csr_host(nrows: int, ncols: int, rowptr: np.ndarray, col: np.ndarray, nnz: Optional[int] = None) -> int:
+    """The CSR checks of validate() on host arrays (no device involved);
+    nnz defaults to len(col)."""
+    rp = np.ascontiguousarray(rowptr, np.int32)
+    c = np.ascontiguousarray(col, np.int32)
+    if rp.size != nrows + 1:
+        raise ValueError("rowptr must have nrows + 1 entries")
+    nnz = c.size if nnz is None else int(nnz)
+    if nnz > c.size:
+        raise ValueError("nnz exceeds the column array")
+    return _lib.spx_validate_csr_host(int(nrows), int(ncols), nnz, rp.ctypes.data, c.ctypes.data if c.size else None)
+
+
+def last_error() -> str:
+    return _lib.spx_last_error().decode()
+
+
 # ------------------------------------------------------------------ SpMV
 def spmv(A: Matrix, x: torch.Tensor, y: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
          stream=None, csr_only: bool = False) -> torch.Tensor:
@@ -484,8 +514,9 @@ class Server:
     """Continuous-batching CG server (host requests, results copied back)."""
 
     def __init__(self, device: int = 0, max_slots: int = 1024, hbm_budget_bytes: int = 32 << 30,
-                 iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0):
-        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us, wide_min_rows, 0)
+                 iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0, debug_fail_tick: int = 0):
+        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us, wide_min_rows,
+                           debug_fail_tick)
         h = ctypes.c_void_p()
         check(_lib.spx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "spx_server_create")
         self._h = h

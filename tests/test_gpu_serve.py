@@ -127,10 +127,19 @@ def test_server_budget_queueing_and_cancel():
             huge = S.poisson2d(300)
             srv.submit(huge, np.ones(huge.n))
         tickets = [srv.submit(big, bbig, tol=1e-8) for _ in range(4)]
-        victim = srv.submit(small, bsmall, tol=1e-8)
+        # an unreachable tolerance keeps the victim running (or queued) until
+        # the cancel arrives, so the cancel must win
+        victim = srv.submit(small, bsmall, tol=1e-300)
+        time.sleep(0.05)
         srv.cancel(victim)
         x, info = srv.wait(victim, timeout_s=60)
-        assert info["status"] in (spx.CANCELLED, spx.OK)
+        assert info["status"] == spx.CANCELLED
+        # cancelled while still queued behind the budget
+        queued = srv.submit(big, bbig, tol=1e-8)
+        assert srv.stats()["queued"] >= 1
+        srv.cancel(queued)
+        x, info = srv.wait(queued, timeout_s=60)
+        assert info["status"] == spx.CANCELLED
         saw_queue = False
         for t in tickets:
             saw_queue |= srv.stats()["queued"] > 0
@@ -140,9 +149,38 @@ def test_server_budget_queueing_and_cancel():
         st = srv.stats()
         assert st["pool_bytes_peak"] <= st["pool_bytes_total"]
         assert st["rejected"] == 1
-        assert st["completed"] == st["submitted"] == 5
+        assert st["completed"] == st["submitted"] == 6
     finally:
         srv.close()
+
+
+def test_server_failure_ends_every_request():
+    # the host makes the worker stop at its 4th tick as if a HIP call had
+    # failed (no device fault): resident and queued requests must all end
+    # with SPX_ERR_HIP, none may stay pending, later submissions are refused
+    A, b = _system("poisson", 96, 3)
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20, iters_per_tick=2, debug_fail_tick=4)
+    try:
+        tickets = [srv.submit(A, b, tol=1e-10) for _ in range(6)]
+        for t in tickets:
+            _, info = srv.wait(t, timeout_s=60)
+            assert info["status"] == spx.ERR_HIP, info
+        with pytest.raises(spx.SpxError, match="HIP"):
+            srv.submit(A, b)
+        st = srv.stats()
+        assert st["completed"] == st["submitted"] == 6
+        assert st["active"] == 0 and st["queued"] == 0 and st["pool_bytes_in_use"] == 0
+    finally:
+        srv.close()
+
+
+def test_server_destroy_cancels_resident_requests():
+    A, b = _system("poisson", 96, 4)
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20, iters_per_tick=1)
+    for _ in range(4):
+        srv.submit(A, b, tol=1e-300)
+    time.sleep(0.05)
+    srv.close()  # must return: the worker ends every resident and queued request
 
 
 def test_server_poll_and_slot_reuse():
