@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "spx_oracle.c")
+_SRC_OMP = os.path.join(_HERE, "spx_oracle_omp.c")
 _LIB = os.path.join(_HERE, "_spx_oracle.so")
 
 # Status codes of the oracle's solvers.
@@ -33,8 +34,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc. -ffp-contract=off keeps every float
     operation as written (the Dot2 error-free transformations rely on it)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wno-unused-function", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+               "-fno-fast-math", "-Wall", "-Wno-unused-function", "-o", _LIB + ".tmp", _SRC, _SRC_OMP, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -110,6 +111,10 @@ def _declare(L):
     L.orc_block_jacobi_apply.restype = None
     solver = [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _i32]
     L.orc_cg.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
+    L.orc_cg_omp.argtypes = solver + [_i32, ctypes.POINTER(Info)]
+    L.orc_csr_spmv_omp.argtypes = [_i32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64, _f64]
+    L.orc_csr_spmv_omp.restype = None
+    L.orc_omp_threads.restype = ctypes.c_int
     L.orc_bicgstab.argtypes = solver + [_i32, _i32, ctypes.POINTER(Info)]
     L.orc_gmres.argtypes = solver + [_i32, _i32, _i32, ctypes.POINTER(Info)]
     L.orc_bicg.argtypes = solver + [_i32, _i32, ctypes.c_void_p, _i32, ctypes.POINTER(Info)]
@@ -380,6 +385,25 @@ def block_jacobi_apply(inv, r):
 def cg(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):
     """precond: 0 none, 1 scalar Jacobi, bs >= 2 block Jacobi (bs x bs blocks)."""
     return _solve(lib().orc_cg, A, b, x0, [tol, maxit, precond, 1 if x0 is None else 0])
+
+
+def omp_threads() -> int:
+    """Threads the all-core variants use (OMP_NUM_THREADS or the host's cores)."""
+    return int(lib().orc_omp_threads())
+
+
+def csr_spmv_omp(A, x, y=None, alpha=1.0, beta=0.0):
+    """csr_spmv with rows shared among OpenMP threads (bitwise the same y)."""
+    rp, c, v = _csr(A)
+    out = np.zeros(A.n) if y is None else _c(y, np.float64).copy()
+    lib().orc_csr_spmv_omp(A.n, rp, c, v, _c(x, np.float64), out, alpha, beta)
+    return out
+
+
+def cg_omp(A, b, tol=1e-10, maxit=10000, precond=0):
+    """cg from x0 = 0 with every loop shared among OpenMP threads (precond 0
+    or 1); iterates agree with cg's to rounding."""
+    return _solve(lib().orc_cg_omp, A, b, None, [tol, maxit, precond])
 
 
 def bicgstab(A, b, tol=1e-10, maxit=10000, precond=0, x0=None):

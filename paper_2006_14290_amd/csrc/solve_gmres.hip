@@ -12,9 +12,10 @@
 // the new one, updates the residual estimate |g_{j+1}| and decides whether the
 // cycle ends (estimate below tolerance, lucky breakdown, or maxit). All of
 // this stays on the device; one restart cycle (m Arnoldi steps) is a single
-// captured hipGraph, replayed per cycle. At the end of a cycle a one-thread
-// kernel solves the triangular system H y = g and x += M^{-1} V y; the next
-// cycle starts from the true residual b - A x.
+// captured hipGraph, replayed per cycle. At the end of a cycle one wavefront
+// stages the triangle of H and g in LDS and one of its lanes back-substitutes
+// H y = g there; then x += M^{-1} V y, and the next cycle starts from the true
+// residual b - A x.
 #include <cmath>
 
 #include "solver_common.hpp"

@@ -310,28 +310,40 @@ def test_ir_poisson(low, fmt):
 
 
 @pytest.mark.timeout(900)
-def test_ir_full_192_vs_fp64_cg():
+def test_ir_full_192_vs_fp64_oracle():
     """7-point Poisson 192^3 (n = 7,077,888): FP32 and FP16-value IR reach a
-    float64 true residual of 1e-10 and agree with plain float64 CG."""
+    float64 true residual of 1e-10; their error is stated and bounded against
+    the float64 oracle's CG solution (all-core variant, the same recurrences
+    as the plain oracle) and against x*."""
     print("case ir 192^3", flush=True)
     N = 192
     A = S.poisson3d_7pt(N)
     xs, b = _problem(A)
+    xo, io = O.cg_omp(A, b, tol=1e-10, maxit=5000)
+    assert io["status"] == O.OK
+    assert _true_relres(A, b, xo) <= 1e-10
+    print("oracle cg 192^3:", io, flush=True)
     A64 = spx.csr_from_host(A)
     bd = dev(b)
+    kappa = _kappa_poisson(N, (1, 1, 1))
+    bound = 2 * kappa * 1e-10  # both sides solve to a relative residual of 1e-10
     x64, i64 = spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
     assert i64["status"] == spx.OK
     x64 = host(x64)
     assert _true_relres(A, b, x64) <= 1e-10
-    kappa = _kappa_poisson(N, (1, 1, 1))
+    e64 = np.linalg.norm(x64 - xo) / np.linalg.norm(xo)
+    assert e64 <= bound
+    print(f"gpu fp64 cg vs oracle: {e64:.3e}", flush=True)
     for low in (spx.F32, spx.F16):
         Alow = spx.cast_values(A64, low)
         x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=1e-3)
         x = host(x)
         assert info["status"] == spx.OK, info
         assert _true_relres(A, b, x) <= 1e-10
-        assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 2 * kappa * 1e-10
-        print("ir 192^3", low, info, "fp64 cg", i64, flush=True)
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        errs = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+        assert err <= bound and errs <= kappa * 1e-10
+        print(f"ir 192^3 low={low}: error vs fp64 oracle {err:.3e}, vs x* {errs:.3e}", info, flush=True)
 
 
 @pytest.mark.parametrize("low", ["f32", "f16"])
@@ -413,3 +425,72 @@ def test_cg_block_jacobi_errors():
         spx.bicgstab_solve(Ad, b, precond=4)
     with pytest.raises(spx.SpxError, match="ERR_ARG"):
         spx.cg_solve(spx.convert(Ad, spx.ELL), b, precond=4)
+
+
+def _gj_swaps(B):
+    """Row swaps Gauss-Jordan with partial pivoting (largest |pivot|, first
+    row on ties) makes on B: the pivoting the block inverse must survive."""
+    a = np.array(B, dtype=np.float64)
+    m = a.shape[0]
+    swaps = 0
+    for j in range(m):
+        piv = j + int(np.argmax(np.abs(a[j:, j])))
+        if piv != j:
+            a[[j, piv]] = a[[piv, j]]
+            swaps += 1
+        a[j] /= a[j, j]
+        for r in range(m):
+            if r != j:
+                a[r] -= a[r, j] * a[j]
+    return swaps
+
+
+@pytest.mark.parametrize("bs", [2, 8, 32])
+def test_cg_block_jacobi_inverse_with_row_swaps(bs):
+    """SPD blocks B = L L^T + I with unit-diagonal L whose first columns are
+    large, so every block's partial pivoting swaps rows; the matrix is its
+    own block-Jacobi preconditioner, so one CG iteration gives A^-1 b."""
+    rng = np.random.default_rng(40 + bs)
+    blocks = []
+    if bs == 2:
+        blocks.append(np.array([[1.0, 2.0], [2.0, 5.0]]))
+    while len(blocks) < 24:
+        L = np.tril(rng.uniform(-1, 1, (bs, bs)), -1) * 0.3 + np.eye(bs)
+        L[1:, 0] = rng.uniform(2.0, 3.0, bs - 1) * rng.choice([-1, 1], bs - 1)
+        B = L @ L.T + np.eye(bs)
+        if np.linalg.cond(B) < 1e5:
+            blocks.append(B)
+    assert all(_gj_swaps(B) >= 1 for B in blocks)
+    n = bs * len(blocks)
+    d = np.zeros((n, n))
+    for k, B in enumerate(blocks):
+        d[k * bs:(k + 1) * bs, k * bs:(k + 1) * bs] = B
+    A = S.from_dense(d)
+    b = rng.uniform(-1, 1, n)
+    x, info = spx.cg_solve(spx.csr_from_host(A), dev(b), tol=1e-8, precond=bs)
+    assert info["status"] == spx.OK and info["iters"] == 1, info
+    xd = np.linalg.solve(d, b)
+    cond = max(np.linalg.cond(B) for B in blocks)
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= cond * 1e-13
+    # the oracle's block inverse (pinned against numpy) agrees as well
+    xo, io = O.cg(A, b, tol=1e-8, precond=bs)
+    assert io["iters"] == 1
+    assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) <= cond * 1e-13
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_gmres_longest_restart(precond):
+    """GMRES with the largest restart length (m = 62: the Hessenberg triangle
+    fills its whole LDS copy) on a nonsymmetric system that needs several
+    full cycles, against the oracle."""
+    A = S.convdiff3d_upwind(30, peclet=1.0)  # n = 27,000; about 165 Arnoldi steps in 3 cycles
+    xs, b = _problem(A, seed=6)
+    x, info = spx.gmres_solve(spx.csr_from_host(A), dev(b), tol=1e-10, precond=precond, restart=62, maxit=3000)
+    assert info["status"] == spx.OK, info
+    assert _true_relres(A, b, host(x)) <= 1e-10
+    xo, io = O.gmres(A, b, tol=1e-10, precond=precond, restart=62, maxit=3000)
+    assert io["status"] == O.OK
+    assert info["iters"] > 2 * 62 and io["iters"] > 2 * 62, (info, io)
+    assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+    with pytest.raises(spx.SpxError, match="ERR_ARG"):
+        spx.gmres_solve(spx.csr_from_host(A), dev(b), restart=63)

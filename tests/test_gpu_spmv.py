@@ -225,3 +225,44 @@ def test_full_size_zipf_csr_coo_hyb():
         assert_spmv_f64(y, yref, absax)
         del Ad
         torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_zipf_ell_int64_slots():
+    """The Zipf(1.5) matrix (n = 1e6, longest rows 10,000 entries) in ELL:
+    1e10 slots, so every slot offset is past 2^31 for most slot columns.
+    Device CSR -> ELL -> CSR round trip compared bitwise on the host, the
+    ELL slots of every 10,000-entry row and of a row sample checked against
+    the canonical layout, and the ELL product compared row by row with the
+    oracle."""
+    print("case zipf-1e6 ell f64 (1e10 slots)", flush=True)
+    A = S.zipf_matrix(10**6, seed=0)
+    lens = np.diff(A.rowptr)
+    long_rows = np.flatnonzero(lens == 10000)
+    assert long_rows.size > 1000
+    x = S.uniform_vector(A.n, seed=0)
+    yref, absax = O.csr_spmv_dot2(A, x)
+    Ad = spx.csr_from_host(A)
+    E = spx.convert(Ad, spx.ELL)
+    K, ld = E.ell_width, E.ell_ld
+    assert K == 10000 and K * ld > 2 ** 31
+    y = host(spx.spmv(E, dev(x)))
+    assert_spmv_f64(y, yref, absax)
+    rows = np.unique(np.concatenate([long_rows, S.rng(5, "x").choice(A.n, 4000, replace=False)]))
+    ri = torch.from_numpy(rows).cuda()
+    ecol = host(E.ell_col.view(K, ld)[:, ri])
+    evbits = host(E.ell_val.view(K, ld)[:, ri]).view(np.uint64)
+    for j, i in enumerate(rows):
+        a, L = A.rowptr[i], lens[i]
+        np.testing.assert_array_equal(ecol[:L, j], A.col[a:a + L])
+        assert np.all(ecol[L:, j] == -1)
+        np.testing.assert_array_equal(evbits[:L, j], A.val[a:a + L].view(np.uint64))
+        assert np.all(evbits[L:, j] == 0)
+    del ecol, evbits
+    B = spx.convert(E, spx.CSR)
+    del E
+    np.testing.assert_array_equal(host(B.rowptr), A.rowptr)
+    np.testing.assert_array_equal(host(B.colidx), A.col)
+    np.testing.assert_array_equal(host(B.vals).view(np.uint64), A.val.view(np.uint64))
+    del B, Ad
+    torch.cuda.empty_cache()
