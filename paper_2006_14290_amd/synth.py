@@ -202,39 +202,104 @@ def zipf_matrix(n: int, a: float = 1.5, kmax: int = 10000, seed: int = 0) -> CSR
     return _finish(n, rowptr, col, val)
 
 
-def spd_diag_dominant(n: int, kmin: int = 5, kmax: int = 30, seed: int = 0) -> CSR:
+def spd_diag_dominant(n: int, kmin: int = 5, kmax: int = 30, seed: int = 0, device=None) -> CSR:
     """Random symmetric, strictly diagonally dominant SPD matrix.
 
     Each row i draws a target length k ~ U{kmin..kmax} and (k-1)//2 partner
     columns j != i uniformly; each pair (i, j) gets one uniform[-1, 1) value
     placed at (i, j) and mirrored to (j, i) (a pair drawn twice keeps its first
-    value). The diagonal is ``sum_j |a_ij| + 1``."""
+    value). The diagonal is ``sum_j |a_ij| + 1``, summed left to right along
+    the row. With `device` (a torch device such as "cuda") the random draws
+    are the same and the sorting and assembly run in torch there: the same
+    matrix, bit for bit, much faster for large n."""
     rp = rng(seed, "pattern")
     rv = rng(seed, "values")
     k = rp.integers(kmin, kmax + 1, n)
     m = (k - 1) // 2
     src = np.repeat(np.arange(n, dtype=np.int64), m)
     dst = rp.integers(0, n - 1, src.size, dtype=np.int64)
-    dst += dst >= src  # uniform over [0, n) without i
     v = rv.uniform(-1.0, 1.0, src.size)
+    if device is not None:
+        return _spd_assemble_torch(n, src, dst, v, device)
+    dst += dst >= src  # uniform over [0, n) without i
     lo = np.minimum(src, dst)
     hi = np.maximum(src, dst)
-    pair = lo * n + hi
-    _, first = np.unique(pair, return_index=True)
-    lo, hi, v = lo[first], hi[first], v[first]
-    rows = np.concatenate([lo, hi])
-    cols = np.concatenate([hi, lo])
-    vals = np.concatenate([v, v])
-    absrow = np.zeros(n)
-    np.add.at(absrow, rows, np.abs(vals))
-    rows = np.concatenate([rows, np.arange(n, dtype=np.int64)])
-    cols = np.concatenate([cols, np.arange(n, dtype=np.int64)])
-    vals = np.concatenate([vals, absrow + 1.0])
-    order = np.argsort(rows * n + cols, kind="stable")
-    rows, cols, vals = rows[order], cols[order], vals[order]
+    # pairs in (lo, hi) order, the first draw of each kept
+    o = np.argsort(lo * n + hi, kind="stable")
+    key = (lo * n + hi)[o]
+    keep = np.ones(key.size, bool)
+    keep[1:] = key[1:] != key[:-1]
+    o = o[keep]
+    ulo, uhi, uv = lo[o], hi[o], v[o]  # upper entries (row lo, col hi), sorted by (row, col)
+    o2 = np.argsort(uhi * n + ulo, kind="stable")
+    llo, lhi, lv = ulo[o2], uhi[o2], uv[o2]  # lower entries (row hi, col lo), sorted by (row, col)
+    cnt_lo = np.bincount(lhi, minlength=n)  # entries left of the diagonal per row
+    cnt_up = np.bincount(ulo, minlength=n)
     rowptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
-    return _finish(n, rowptr, cols, vals)
+    np.cumsum(cnt_lo + 1 + cnt_up, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    col = np.empty(nnz, np.int64)
+    val = np.zeros(nnz)
+    # a row holds its lower entries, the diagonal, then its upper entries
+    lstart = np.zeros(n, np.int64)
+    np.cumsum(cnt_lo[:-1], out=lstart[1:])
+    ustart = np.zeros(n, np.int64)
+    np.cumsum(cnt_up[:-1], out=ustart[1:])
+    pl = rowptr[lhi] + (np.arange(lhi.size) - lstart[lhi])
+    pu = rowptr[ulo] + cnt_lo[ulo] + 1 + (np.arange(ulo.size) - ustart[ulo])
+    pd = rowptr[:-1] + cnt_lo
+    col[pl], val[pl] = llo, lv
+    col[pu], val[pu] = uhi, uv
+    col[pd] = np.arange(n)
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    val[pd] = np.bincount(rows, weights=np.abs(val), minlength=n) + 1.0
+    return _finish(n, rowptr, col, val)
+
+
+def _spd_assemble_torch(n, src, dst, v, device) -> CSR:
+    """The assembly steps of spd_diag_dominant in torch on `device`."""
+    import torch
+
+    dev = torch.device(device)
+    src = torch.from_numpy(src).to(dev)
+    dst = torch.from_numpy(dst).to(dev)
+    v = torch.from_numpy(v).to(dev)
+    dst = dst + (dst >= src).to(dst.dtype)
+    lo = torch.minimum(src, dst)
+    hi = torch.maximum(src, dst)
+    key, o = torch.sort(lo * n + hi, stable=True)
+    keep = torch.ones_like(key, dtype=torch.bool)
+    keep[1:] = key[1:] != key[:-1]
+    o = o[keep]
+    ulo, uhi, uv = lo[o], hi[o], v[o]
+    _, o2 = torch.sort(uhi * n + ulo, stable=True)
+    llo, lhi, lv = ulo[o2], uhi[o2], uv[o2]
+    cnt_lo = torch.bincount(lhi, minlength=n)
+    cnt_up = torch.bincount(ulo, minlength=n)
+    lens = cnt_lo + 1 + cnt_up
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    rowptr[1:] = torch.cumsum(lens, 0)
+    nnz = int(rowptr[-1])
+    col = torch.empty(nnz, dtype=torch.int64, device=dev)
+    val = torch.zeros(nnz, dtype=torch.float64, device=dev)
+    lstart = torch.cumsum(cnt_lo, 0) - cnt_lo
+    ustart = torch.cumsum(cnt_up, 0) - cnt_up
+    pl = rowptr[lhi] + (torch.arange(lhi.numel(), device=dev) - lstart[lhi])
+    pu = rowptr[ulo] + cnt_lo[ulo] + 1 + (torch.arange(ulo.numel(), device=dev) - ustart[ulo])
+    pd = rowptr[:-1] + cnt_lo
+    col[pl], val[pl] = llo, lv
+    col[pu], val[pu] = uhi, uv
+    col[pd] = torch.arange(n, device=dev)
+    # row sums of |a_ij| left to right (as the host path's bincount adds them)
+    a = val.abs()
+    acc = torch.zeros(n, dtype=torch.float64, device=dev)
+    start = rowptr[:-1]
+    for j in range(int(lens.max())):
+        idx = start + j
+        live = j < lens
+        acc += torch.where(live, a[torch.where(live, idx, 0)], torch.zeros((), dtype=a.dtype, device=dev))
+    val[pd] = acc + 1.0
+    return _finish(n, rowptr.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy())
 
 
 def uniform_vector(n: int, seed: int = 0, purpose: str = "x") -> np.ndarray:
