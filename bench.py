@@ -1,16 +1,28 @@
 #!/usr/bin/env python3
-"""Benchmark of the SpMV hot path on one MI355X.
+"""Benchmark of the SpMV + Krylov hot path on one MI355X.
 
-Workload (one "step"): y = A x on the 27-point stencil of a 100^3 grid
-(n = 1e6, nnz = 26,463,592, uniform[-1,1) values, float64, CSR), the sparse
-format sweep's regular matrix. The matrix, x and y are replicated R times so
-that R * footprint >= 1 GiB and step s uses copy s % R: the 256 MB
+Headline workload (one "step"): y = A x on the 27-point stencil of a 100^3
+grid (n = 1e6, nnz = 26,463,592, uniform[-1,1) values, float64, CSR), the
+sparse format sweep's regular matrix. The matrix, x and y are replicated R
+times so that R * footprint >= 1 GiB and step s uses copy s % R: the 256 MB
 Infinity Cache cannot hold the working set between steps.
 
-Prints ONE JSON line: SpMV GB/s (algorithmic bytes / time) and its fraction
-of the 8 TB/s HBM peak, the other formats and precisions of the sweep, a
-measured streaming-copy bandwidth, the roofline record of the CSR kernel and
-the CPU oracle's rate on the host.
+The same run also measures (each section can be switched off):
+  - the attainable streaming copy and read bandwidths;
+  - the format sweep: CSR / COO / ELL / HYB / SELL-P in float64 and float32
+    (and CSR with binary16 values) on the 27-point matrix and on the
+    Zipf(1.5) matrix (n = 1e6, rows clipped to 10,000), plus the device
+    conversions;
+  - CG on the 64x64 Poisson system (latency, one at a time and batched);
+  - the full-size solvers: Jacobi-CG on the anisotropic 7-point 128^3 grid,
+    BiCGSTAB and GMRES(30) on the convection-diffusion 128^3 grid, and
+    float32 / binary16-value iterative refinement against float64 CG on the
+    7-point 192^3 grid, with the error against the float64 oracle solution;
+  - the serving stream (Poisson arrivals, p50/p99 latency, solves/s, against
+    the same requests solved one by one);
+  - the CPU oracle on the host's cores (one thread and all cores).
+
+Prints ONE JSON line; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -18,6 +30,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -26,6 +39,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+T0 = time.time()
+
+
+def progress(msg):
+    print(f"[bench {time.time() - T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def csr_bytes(n, nnz, sv, sx, beta=False):
@@ -70,12 +88,12 @@ def cg_iter_bytes(n, nnz, sv, precond):
     return csr_bytes(n, nnz, sv, sv) + (11 if precond else 9) * n * sv
 
 
-def format_sweep(spx, torch, dev, A, x_h, args, tag):
+def format_sweep(spx, torch, dev, A, x_h, args, tag, ell=True):
     """Time y = A x in CSR, COO, ELL and HYB (automatic width), float64 and
     float32 values, plus CSR with binary16 values and CSR without the
-    precomputed partition. Each format is built on the device from the CSR
-    upload by spx_convert. GB/s counts the format's own algorithmic bytes
-    (ELL padding included); csr_equiv_GBs counts the CSR bytes of the same
+    row-length hint. Each format is built on the device from the CSR upload
+    by spx_convert. GB/s counts the format's own algorithmic bytes (ELL
+    padding included); csr_equiv_GBs counts the CSR bytes of the same
     product, for comparison across formats."""
     n, nnz = A.n, A.nnz
     out = {}
@@ -94,16 +112,19 @@ def format_sweep(spx, torch, dev, A, x_h, args, tag):
         if vt != spx.F16:
             variants.update({
                 "coo": (lambda: spx.convert(base, spx.COO), coo_bytes(n, nnz, sv, sx)),
-                "ell": (lambda: spx.convert(base, spx.ELL), ell_bytes(n, K, sv, sx)),
                 "hyb": (lambda: spx.convert(base, spx.HYB), hyb_bytes(n, hK, hC, sv, sx)),
                 "sellp": (lambda: spx.convert(base, spx.SELLP), sellp_bytes(n, scols, 64, sv, sx)),
             })
-        def load_balanced():
+            if ell:
+                variants["ell"] = (lambda: spx.convert(base, spx.ELL), ell_bytes(n, K, sv, sx))
+
+        def no_hint():
             M = spx.csr_from_host(A, vt, dev)
-            M.max_row_len = 0  # no row-length hint: the load-balanced kernel
+            M.max_row_len = 0  # no row-length hint
             return spx.csr_analyse(M)
 
-        variants["csr_lb"] = (load_balanced, csr_bytes(n, nnz, sv, sx))
+        if vt != spx.F16:
+            variants["csr_lb"] = (no_hint, csr_bytes(n, nnz, sv, sx))
         for fmt, (make, vb) in variants.items():
             name = f"{tag}_{fmt}_{vname}"
             if vb > 0.8 * free:
@@ -117,8 +138,10 @@ def format_sweep(spx, torch, dev, A, x_h, args, tag):
             steps = args.steps if vb < (4 << 30) else max(3, args.steps // 20)
             vms = time_launches(lambda i: spx.spmv(Ms[i % Rv], Xs[i % Rv], Ys[i % Rv]), steps,
                                 max(1, args.warmup // 4), torch)
-            out[name] = {"ms": vms, "GBs": vb / vms / 1e6, "bytes": vb,
-                         "csr_equiv_GBs": csr_bytes(n, nnz, sv, sx) / vms / 1e6}
+            out[name] = {"ms": round(vms, 5), "GBs": round(vb / vms / 1e6, 1), "bytes": vb,
+                         "pct_hbm_peak": round(100 * vb / vms / 1e6 / HBM_PEAK_GBS, 2),
+                         "gflops": round(2 * nnz / vms / 1e6, 1),
+                         "csr_equiv_GBs": round(csr_bytes(n, nnz, sv, sx) / vms / 1e6, 1)}
             if fmt == "hyb":
                 out[name].update(ell_width=hK, coo_nnz=hC)
             del Ms, Xs, Ys
@@ -129,9 +152,9 @@ def format_sweep(spx, torch, dev, A, x_h, args, tag):
 
 
 def conversion_sweep(spx, torch, dev, A, tag, steps=20):
-    """Device format conversion, float64 values: CSR -> COO / ELL / HYB and
-    back, timed with HIP events around spx_convert alone (outputs and
-    workspace allocated by one untimed plan + conversion). GB/s counts one
+    """Device format conversion, float64 values: CSR -> COO / ELL / HYB /
+    SELL-P and back, timed with HIP events around spx_convert alone (outputs
+    and workspace allocated by one untimed plan + conversion). GB/s counts one
     read of the source arrays and one write of the destination arrays. The
     float64 -> float32 value cast is timed around the (blocking) call."""
     import ctypes
@@ -191,7 +214,7 @@ def subwarp_sweep(spx, torch, dev):
         ms = time_launches(lambda i: spx.subwarp_sum(x, size, loops, out), 5, 2, torch)
         t[size] = ms
     base = t[1]
-    res = {str(k): {"ms": round(v, 4), "ns_per_reduction_per_wave": round((v - base) * 1e6 / (loops * n / 64 / 1), 6)}
+    res = {str(k): {"ms": round(v, 4), "ns_per_reduction_per_wave": round((v - base) * 1e6 / (loops * n / 64), 6)}
            for k, v in t.items()}
     res["ratio_4_over_64"] = round((t[4] - base) / (t[64] - base), 3)
     res["theory_4_over_64"] = round(2 / 6, 3)
@@ -211,10 +234,10 @@ def csr_kernel_name(M):
 
 
 def profile_traffic(name, algo_bytes):
-    """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter runs
-    summarised in profiles/<name>.md, or None when the kernel sources listed
-    there have changed since (their hash differs) or the launch moved a
-    different number of algorithmic bytes."""
+    """Beyond-L2 bytes per launch measured by the FETCH_SIZE / WRITE_SIZE
+    counter runs summarised in profiles/<name>.md, or None when the kernel
+    sources listed there have changed since (their hash differs) or the
+    launch moved a different number of algorithmic bytes."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", name + ".md")
@@ -280,7 +303,8 @@ def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
         assert info["status"] == 0 and info["relres_true"] <= 1e-10, info
     tot = time.perf_counter() - t0
     lat = np.array(lat) * 1e3
-    out = {"spmv": spmv_lat, "single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+    out = {"spmv": spmv_lat,
+           "single": {"solves_per_s": round(nsolves / tot, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3), "iters": iters, "solves": nsolves,
                       "relres_true": info["relres_true"]}}
     # the same blocking solves with pipelined CG (three launches per
@@ -317,51 +341,69 @@ def bench_cg_small(spx, S, torch, dev, nsolves, nbatch):
     return out
 
 
-def bench_solvers(spx, S, torch, dev):
+def _solve_rec(info, nbytes=None, **extra):
+    r = {"ms": round(info["device_ms"], 2), "iters": info["iters"], "spmv": info["spmv_count"],
+         "us_per_iter": round(1e3 * info["device_ms"] / max(info["iters"], 1), 2),
+         "relres_true": info["relres_true"], "status": info["status"]}
+    if nbytes is not None:
+        r["GBs"] = round(nbytes / (1e3 * info["device_ms"] / max(info["iters"], 1)) / 1e3, 1)
+        r["pct_hbm_peak"] = round(100 * r["GBs"] / HBM_PEAK_GBS, 2)
+    r.update(extra)
+    return r
+
+
+def bench_solvers(spx, S, torch, dev, cpu=True):
     """Krylov solvers at full size: CG+Jacobi on the anisotropic 7-point 128^3
     grid, BiCGSTAB and GMRES(30) + Jacobi on the upwind convection-diffusion
     128^3 grid, and mixed-precision IR (float32 / binary16 values) against
-    plain float64 CG on the 7-point 192^3 grid; all to 1e-10."""
+    plain float64 CG on the 7-point 192^3 grid; all to 1e-10. The float64
+    oracle (all-core CG) solves the 192^3 system on the host meanwhile; the
+    IR and CG solutions are compared with its solution."""
     out = {}
+    nrm = torch.linalg.vector_norm
+    # the host oracle's float64 CG on the 192^3 system runs while the GPU works
+    P192 = S.poisson3d_7pt(192)
+    xstar192 = S.uniform_vector(P192.n, seed=0, purpose="xstar")
+    oracle = {}
 
+    def run_oracle():
+        import oracle as O
+
+        b = O.csr_spmv_omp(P192, xstar192)
+        t = time.perf_counter()
+        x, info = O.cg_omp(P192, b, tol=1e-10, maxit=5000)
+        oracle.update(x=x, info=info, s=time.perf_counter() - t, threads=O.omp_threads())
+
+    th = threading.Thread(target=run_oracle) if cpu else None
+    if th:
+        th.start()
+
+    progress("solvers: CG + Jacobi, anisotropic 128^3")
     A = S.poisson3d_7pt(128, 1, 1, 0.01)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
     bd = rhs(spx, S, torch, Ad)
+    cg_b = cg_iter_bytes(A.n, A.nnz, 8, True)
     spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
     x, info = spx.cg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
-    it_us = 1e3 * info["device_ms"] / max(info["iters"], 1)
-    out["cg_jacobi_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
-                                 "us_per_iter": round(it_us, 2),
-                                 "GBs": round(cg_iter_bytes(A.n, A.nnz, 8, True) / it_us / 1e3, 1),
-                                 "relres_true": info["relres_true"]}
+    out["cg_jacobi_aniso128"] = _solve_rec(info, cg_b, bytes_per_iter=cg_b)
     t_cg = info["device_ms"]
-    # pipelined CG on the same system: one reduction phase per iteration,
-    # more vector traffic
     spx.pipecg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
     x, info = spx.pipecg_solve(Ad, bd, tol=1e-10, precond=1, maxit=5000)
-    out["pipecg_jacobi_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
-                                     "us_per_iter": round(1e3 * info["device_ms"] / max(info["iters"], 1), 2),
-                                     "time_vs_cg": round(info["device_ms"] / t_cg, 3),
-                                     "relres_true": info["relres_true"]}
-    # block Jacobi (8 x 8 and 32 x 32 diagonal blocks) on the same system
+    out["pipecg_jacobi_aniso128"] = _solve_rec(info, time_vs_cg=round(info["device_ms"] / t_cg, 3))
     for bs in (8, 32):
         spx.cg_solve(Ad, bd, tol=1e-10, precond=bs, maxit=5000)
         x, info = spx.cg_solve(Ad, bd, tol=1e-10, precond=bs, maxit=5000)
-        out[f"cg_blockjacobi{bs}_aniso128"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
-                                               "us_per_iter": round(1e3 * info["device_ms"] / max(info["iters"], 1), 2),
-                                               "relres_true": info["relres_true"]}
-    # the same solve on the SELL-P form of the matrix (the paper runs CG on Sellp)
+        out[f"cg_blockjacobi{bs}_aniso128"] = _solve_rec(info)
     Ps = spx.convert(Ad, spx.SELLP)
     spx.cg_solve(Ps, bd, tol=1e-10, precond=1, maxit=5000)
     x, info = spx.cg_solve(Ps, bd, tol=1e-10, precond=1, maxit=5000)
-    it_us = 1e3 * info["device_ms"] / max(info["iters"], 1)
-    out["cg_jacobi_aniso128_sellp"] = {"ms": round(info["device_ms"], 2), "iters": info["iters"],
-                                       "us_per_iter": round(it_us, 2), "relres_true": info["relres_true"]}
+    out["cg_jacobi_aniso128_sellp"] = _solve_rec(info)
     del Ad, A, Ps
+
+    progress("solvers: BiCGSTAB, GMRES(30), BiCG, convection-diffusion 128^3")
     A = S.convdiff3d_upwind(128)
     Ad = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
     bd = rhs(spx, S, torch, Ad)
-    # device transpose (BiCG builds A^T once per solve)
     spx.csr_transpose(Ad)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -375,46 +417,51 @@ def bench_solvers(spx, S, torch, dev):
     tmin = 2 * (4 * (A.n + 1) + 12 * A.nnz)  # read A, write A^T
     out["csr_transpose_convdiff128"] = {"ms_p50": round(float(np.median(tms)), 3), "nnz": A.nnz,
                                         "GBs_min_bytes": round(tmin / float(np.median(tms)) / 1e6, 1)}
-    for nm, fn in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve), ("gmres30_jacobi_convdiff128", spx.gmres_solve),
-                   ("bicg_jacobi_convdiff128", spx.bicg_solve)):
+    spmv_b = csr_bytes(A.n, A.nnz, 8, 8)
+    for nm, fn, nb in (("bicgstab_jacobi_convdiff128", spx.bicgstab_solve, 2 * spmv_b + 20 * A.n * 8),
+                       ("gmres30_jacobi_convdiff128", spx.gmres_solve, None),
+                       ("bicg_jacobi_convdiff128", spx.bicg_solve, None)):
         fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
         x, info = fn(Ad, bd, tol=1e-10, precond=1, maxit=5000)
-        out[nm] = {"ms": round(info["device_ms"], 2), "iters": info["iters"], "spmv": info["spmv_count"],
-                   "relres_true": info["relres_true"]}
+        out[nm] = _solve_rec(info, nb)
     del Ad, A
-    A = S.poisson3d_7pt(192)
+
+    progress("solvers: IR float32 / binary16 values against float64 CG, 192^3")
+    A = P192
     A64 = spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev))
-    bd = rhs(spx, S, torch, A64)
+    xstar = torch.from_numpy(xstar192).to(dev)
+    bd = spx.spmv(A64, xstar)
     spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
     x, info = spx.cg_solve(A64, bd, tol=1e-10, maxit=5000)
     t64 = info["device_ms"]
-    out["cg_fp64_poisson192"] = {"ms": round(t64, 2), "iters": info["iters"], "relres_true": info["relres_true"]}
+    cg192_b = cg_iter_bytes(A.n, A.nnz, 8, False)
+    out["cg_fp64_poisson192"] = _solve_rec(info, cg192_b)
     x64 = x.clone()
-    xstar = torch.from_numpy(S.uniform_vector(A.n, seed=0, purpose="xstar")).to(dev)
-    nrm = torch.linalg.vector_norm
     out["cg_fp64_poisson192"]["rel_err_vs_xstar"] = float(nrm(x64 - xstar) / nrm(xstar))
+    sols = {}
     for nm, low in (("ir_fp32_poisson192", spx.F32), ("ir_fp16v_poisson192", spx.F16)):
         Alow = spx.cast_values(A64, low)
         sweep = {}
-        for itol in (1e-3, 1e-4, 1e-5, 1e-6):
+        for itol in (1e-3, 1e-4, 1e-6):
             spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=itol)
             x, info = spx.ir_solve(A64, Alow, bd, tol=1e-10, inner_tol=itol)
             sweep[f"{itol:.0e}"] = {
                 "ms": round(info["device_ms"], 2), "inner_iters": info["iters"], "outer": info["outer_iters"],
-                "speedup_vs_fp64": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
-                "status": info["status"], "rel_err_vs_fp64_cg": float(nrm(x - x64) / nrm(x64)),
+                "speedup_vs_fp64_cg": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
+                "status": info["status"], "rel_err_vs_gpu_fp64_cg": float(nrm(x - x64) / nrm(x64)),
                 "rel_err_vs_xstar": float(nrm(x - xstar) / nrm(xstar))}
+            sols[(nm, f"{itol:.0e}")] = x.cpu().numpy()
         ok = {k: v for k, v in sweep.items() if v["status"] == 0}
         best = min(ok, key=lambda k: ok[k]["ms"]) if ok else None
         out[nm] = dict(ok[best], inner_tol=best) if best else {"status": "failed"}
         out[nm]["inner_tol_sweep"] = sweep
-    # the same comparison with every matrix in ELL (the fastest format on this
-    # stencil): plain float64 CG against IR with float32 / binary16 values
+        del Alow
+    # the same comparison with every matrix in ELL
     E64 = spx.convert(A64, spx.ELL)
     spx.cg_solve(E64, bd, tol=1e-10, maxit=5000)
     x, info = spx.cg_solve(E64, bd, tol=1e-10, maxit=5000)
     te = info["device_ms"]
-    out["cg_fp64_poisson192_ell"] = {"ms": round(te, 2), "iters": info["iters"], "relres_true": info["relres_true"]}
+    out["cg_fp64_poisson192_ell"] = _solve_rec(info)
     for nm, low in (("ir_fp32_poisson192_ell", spx.F32), ("ir_fp16v_poisson192_ell", spx.F16)):
         Elow = spx.cast_values(E64, low)
         spx.ir_solve(E64, Elow, bd, tol=1e-10, inner_tol=1e-6)
@@ -423,26 +470,64 @@ def bench_solvers(spx, S, torch, dev):
                    "speedup_vs_fp64_ell": round(te / info["device_ms"], 3),
                    "speedup_vs_fp64_csr": round(t64 / info["device_ms"], 3), "relres_true": info["relres_true"],
                    "status": info["status"], "rel_err_vs_xstar": float(nrm(x - xstar) / nrm(xstar))}
+        sols[(nm, "1e-06")] = x.cpu().numpy()
+        del Elow
+    x64h = x64.cpu().numpy()
+    del A64, E64
+    torch.cuda.empty_cache()
+    if th:
+        progress("solvers: waiting for the host oracle's 192^3 CG")
+        th.join()
+        xo = oracle["x"]
+        no = np.linalg.norm(xo)
+        out["oracle_fp64_cg_poisson192"] = {
+            "s": round(oracle["s"], 2), "iters": oracle["info"]["iters"], "threads": oracle["threads"],
+            "relres_true": oracle["info"]["relres_true"], "status": oracle["info"]["status"]}
+        out["cg_fp64_poisson192"]["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(x64h - xo) / no)
+        for (nm, itol), xs_ in sols.items():
+            rec = out[nm] if nm.endswith("_ell") else out[nm]["inner_tol_sweep"][itol]
+            rec["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(xs_ - xo) / no)
+        for nm in ("ir_fp32_poisson192", "ir_fp16v_poisson192"):
+            if "inner_tol" in out[nm]:
+                out[nm]["rel_err_vs_fp64_oracle"] = out[nm]["inner_tol_sweep"][out[nm]["inner_tol"]]["rel_err_vs_fp64_oracle"]
     return out
 
 
 def serve_workload(S, nreq, seed):
-    """Request mix of the serving workload: half 2D 5-point Poisson systems on
-    N x N grids with N ~ U{32..512}, half random symmetric diagonally dominant
-    SPD systems with n log-uniform in [1e3, 1e6] and 5..30 entries per row.
-    Distinct matrices are drawn from a fixed menu (Poisson N rounded to a
-    multiple of 16, SPD sizes on 24 log-spaced values) so that the host builds
-    each matrix once; every request is solved independently."""
+    """Request mix of the serving workload, every size drawn from its law:
+    half 2D 5-point Poisson systems on N x N grids with N ~ U{32..512}, half
+    random symmetric diagonally dominant SPD systems with n log-uniform in
+    [1e3, 1e6] (5..30 entries per row, the pattern seeded per request). Every
+    request has its own right-hand side b = A x* (x* seeded per request)."""
     r = S.rng(seed, "sizes")
     kinds = r.random(nreq) < 0.5
-    pN = np.clip(np.round(r.integers(32, 513, nreq) / 16) * 16, 32, 512).astype(int)
-    spd_menu = np.unique(np.round(np.logspace(3, 6, 24)).astype(int))
-    sn = spd_menu[np.clip(np.searchsorted(spd_menu, np.exp(r.uniform(np.log(1e3), np.log(1e6), nreq))), 0,
-                          len(spd_menu) - 1)]
+    pN = r.integers(32, 513, nreq)
+    sn = np.floor(np.exp(r.uniform(np.log(1e3), np.log(1e6), nreq))).astype(int)
     return [("poisson", int(pN[i])) if kinds[i] else ("spd", int(sn[i])) for i in range(nreq)]
 
 
-def cpu_serve_sample(mats, reqs, nsample=200):
+def build_requests(spx, S, torch, dev, reqs, seed):
+    """Host CSR matrices and right-hand sides of every request (Poisson
+    matrices shared by equal N; each SPD matrix generated for its request)."""
+    pois = {}
+    out = []
+    t0 = time.time()
+    for i, (kind, size) in enumerate(reqs):
+        if kind == "poisson":
+            if size not in pois:
+                pois[size] = S.poisson2d(size)
+            A = pois[size]
+        else:
+            A = S.spd_diag_dominant(size, seed=1_000_000 + seed * 100_000 + i, device=dev)
+        Ad = spx.csr_from_host(A, spx.F64, dev)
+        b = rhs(spx, S, torch, Ad, seed=seed * 100_000 + i).cpu().numpy()
+        out.append((A, b))
+        if (i + 1) % 500 == 0:
+            progress(f"serve: {i + 1}/{len(reqs)} requests built ({time.time() - t0:.1f} s)")
+    return out
+
+
+def cpu_serve_sample(systems, nsample=200):
     """The oracle's CG (plain C, float64, one solve per thread) on the first
     `nsample` requests of the serving stream, as many solves at once as the
     host has cores for this process (at most 16): sampled CPU solves/s. The
@@ -452,45 +537,40 @@ def cpu_serve_sample(mats, reqs, nsample=200):
     import oracle as O
 
     ncores = max(1, min(16, len(os.sched_getaffinity(0))))
-    sample = reqs[: min(len(reqs), nsample)]
-    print(f"serve cpu: {len(sample)} oracle CG solves on {ncores} threads", file=sys.stderr, flush=True)
+    sample = systems[: min(len(systems), nsample)]
+    progress(f"serve cpu: {len(sample)} oracle CG solves on {ncores} threads")
     t0 = time.perf_counter()
     with ThreadPoolExecutor(ncores) as ex:
-        infos = list(ex.map(lambda r: O.cg(mats[r][0], mats[r][1], tol=1e-8, maxit=100000)[1], sample))
+        infos = list(ex.map(lambda ab: O.cg(ab[0], ab[1], tol=1e-8, maxit=100000)[1], sample))
     dt = time.perf_counter() - t0
     assert all(i["status"] == O.OK for i in infos)
     return {"value": round(len(sample) / dt, 2), "unit": "solves/s", "cores": ncores, "kind": "oracle",
             "sample": f"first {len(sample)} requests of the stream, oracle CG to 1e-8, one solve per thread"}
 
 
-def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32, cpu=False):
+def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False):
     """Serving: (1) all `nreq` requests submitted at once (capacity, solves/s);
-    (2) open-loop Poisson arrival streams at 0.5, 0.7 and 0.9 x that capacity
-    (latency = completion - scheduled arrival, p50/p99; completion is the
-    server's own submit-to-done time added to the submission time); (3) a
-    sample of the same requests solved one by one with the blocking float64
-    CG (spx_cg_solve), for comparison. Tolerance 1e-8."""
+    (2) open-loop Poisson arrival streams at `fracs` x that capacity (latency
+    = completion - scheduled arrival, p50/p99; completion is the server's own
+    submit-to-done time added to the submission time); (3) a sample of the
+    same requests solved one by one with the blocking float64 CG
+    (spx_cg_solve), for comparison. Tolerance 1e-8."""
     reqs = serve_workload(S, nreq, seed)
-    mats = {}
     t0 = time.time()
-    for kind, size in sorted(set(reqs)):
-        A = S.poisson2d(size) if kind == "poisson" else S.spd_diag_dominant(size, seed=size)
-        Ad = spx.csr_from_host(A, spx.F64, dev)
-        b = rhs(spx, S, torch, Ad, seed=size).cpu().numpy()
-        mats[(kind, size)] = (A, b)
-        del Ad
+    systems = build_requests(spx, S, torch, dev, reqs, seed)
     gen_s = time.time() - t0
+    nnz = np.array([A.nnz for A, _ in systems])
+    n = np.array([A.n for A, _ in systems])
     srv = spx.Server(max_slots=2048, hbm_budget_bytes=int(budget_gb * (1 << 30)))
 
     def run(arrivals, label):
-        print(f"serve {label}: submitting {nreq} requests", file=sys.stderr, flush=True)
+        progress(f"serve {label}: submitting {nreq} requests")
         tickets, t_sched, t_sub = [], [], []
         start = time.perf_counter()
-        for i, (kind, size) in enumerate(reqs):
+        for i, (A, b) in enumerate(systems):
             if arrivals is not None:
                 while time.perf_counter() - start < arrivals[i]:
                     time.sleep(0.0002)
-            A, b = mats[(kind, size)]
             t_sub.append(time.perf_counter())
             tickets.append(srv.submit(A, b, tol=1e-8))
             t_sched.append(start + (arrivals[i] if arrivals is not None else 0.0))
@@ -498,9 +578,6 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32, cpu=False):
         for i, (t, ts, tu) in enumerate(zip(tickets, t_sched, t_sub)):
             x, info = srv.wait(t, timeout_s=900)
             assert info["status"] == 0, info
-            if (i + 1) % 500 == 0:
-                print(f"serve {label}: {i + 1}/{nreq} done, {time.perf_counter() - start:.1f} s", file=sys.stderr,
-                      flush=True)
             done = tu + info["device_ms"] * 1e-3
             last = max(last, done)
             lat.append(done - ts)
@@ -510,12 +587,13 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32, cpu=False):
         lat = np.array(lat) * 1e3
         return {"requests": nreq, "solves_per_s": round(nreq / total, 2), "wall_s": round(total, 3),
                 "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "p99_over_p50": round(float(np.percentile(lat, 99) / np.percentile(lat, 50)), 2),
                 "mean_iters": round(float(np.mean(iters)), 1), "max_relres_true": worst}
 
-    print(f"serve: {len(mats)} distinct matrices built in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    progress(f"serve: {nreq} requests built in {gen_s:.1f} s")
     burst = run(None, "burst")
     streams = {}
-    for frac in (0.5, 0.7, 0.9):
+    for frac in fracs:
         rate = frac * burst["solves_per_s"]
         r = run(S.poisson_arrivals(nreq, rate, seed=seed), f"{frac:.1f}x")
         r["rate_per_s"] = round(rate, 2)
@@ -523,22 +601,52 @@ def bench_serve(spx, S, torch, dev, nreq, seed, budget_gb=32, cpu=False):
     st = srv.stats()
     srv.close()
     # sequential blocking float64 CG on a sample of the same requests
-    sample = reqs[: min(nreq, 200)]
+    sample = systems[: min(nreq, 200)]
+    progress(f"serve: {len(sample)} sequential blocking solves")
     t1 = time.perf_counter()
-    for kind, size in sample:
-        A, b = mats[(kind, size)]
+    for A, b in sample:
         Ad = spx.csr_from_host(A, spx.F64, dev)
-        torch.cuda.synchronize()
         x, info = spx.cg_solve(Ad, torch.from_numpy(b).to(dev), tol=1e-8, maxit=100000)
         assert info["status"] == 0
     seq = len(sample) / (time.perf_counter() - t1)
+    # the served throughput over the same first requests
     out = {"burst": burst, "open_loop": streams, "sequential_cg_solves_per_s": round(seq, 2),
            "sequential_sample": len(sample), "served_over_sequential": round(burst["solves_per_s"] / seq, 2),
            "server": {k: st[k] for k in ("ticks", "pool_bytes_peak", "pool_bytes_total")}, "budget_gb": budget_gb,
-           "distinct_matrices": len(mats), "gen_s": round(gen_s, 1)}
+           "mix": {"poisson": int(sum(k == "poisson" for k, _ in reqs)), "spd": int(sum(k == "spd" for k, _ in reqs)),
+                   "n_median": int(np.median(n)), "n_max": int(n.max()), "nnz_mean": int(nnz.mean()),
+                   "nnz_max": int(nnz.max())},
+           "gen_s": round(gen_s, 1)}
     if cpu:
-        out["cpu_oracle"] = cpu_serve_sample(mats, reqs)
+        out["cpu_oracle"] = cpu_serve_sample(systems)
     return out
+
+
+def cpu_spmv_baseline(A, x_h, b, desc):
+    """The oracle's plain float64 CSR product on the host: one thread (about
+    10 s of repetitions) and all cores (the OpenMP variant, about 5 s)."""
+    import oracle as O
+
+    out = {}
+    O.csr_spmv(A, x_h)
+    reps, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < 10.0:
+        O.csr_spmv(A, x_h)
+        reps += 1
+    cs = (time.perf_counter() - t1) / reps
+    one = {"value": round(b / cs / 1e9, 2), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"{reps} plain float64 CSR products of the full {desc} matrix, {cs * 1e3:.1f} ms each, 1 thread"}
+    th = O.omp_threads()
+    O.csr_spmv_omp(A, x_h)
+    reps, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < 5.0:
+        O.csr_spmv_omp(A, x_h)
+        reps += 1
+    cs = (time.perf_counter() - t1) / reps
+    allc = {"value": round(b / cs / 1e9, 2), "unit": "GB/s", "cores": th, "kind": "oracle",
+            "sample": f"{reps} plain float64 CSR products of the full {desc} matrix, {cs * 1e3:.2f} ms each, "
+                      f"rows shared by {th} OpenMP threads"}
+    return allc, one
 
 
 def main():
@@ -549,21 +657,27 @@ def main():
     ap.add_argument("--grid", type=int, default=100, help="27-point grid edge (100 -> n = 1e6)")
     ap.add_argument("--matrix", choices=("27pt", "zipf"), default="27pt",
                     help="matrix of the headline CSR product (27-point stencil or the Zipf(1.5) rows)")
-    ap.add_argument("--sweep", action="store_true", help="also time COO/ELL/HYB and float32/binary16 (27-point)")
-    ap.add_argument("--zipf", action="store_true", help="also time every format on the Zipf(1.5) n=1e6 matrix")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--solvers", action="store_true", help="also time the full-size Krylov solvers")
+    ap.add_argument("--quick", action="store_true", help="headline product only (no sweep, solvers, serving)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the format sweep and conversions")
+    ap.add_argument("--no-zipf", action="store_true", help="skip the Zipf(1.5) formats of the sweep")
+    ap.add_argument("--zipf-ell", action="store_true", help="also time the 1e10-slot Zipf ELL (120 GB)")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the full-size Krylov solvers")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--cg-solves", type=int, default=50, help="solves of the 64x64 CG latency run (0 = skip)")
     ap.add_argument("--cg-batch", type=int, default=1024, help="systems in the batched 64x64 CG run (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-fracs", default="0.5,0.7,0.9", help="open-loop arrival rates, fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="HBM budget of the serving run")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--subwarp", action="store_true", help="also time the subwarp reduction versus subwarp size")
+    ap.add_argument("--no-subwarp", action="store_true", help="skip the subwarp reduction sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.quick:
+        args.no_sweep = args.no_solvers = args.no_subwarp = True
+        args.serve_requests = 0
 
     import torch
 
@@ -575,7 +689,7 @@ def main():
     t0 = time.time()
     if args.matrix == "zipf":
         A = S.zipf_matrix(1_000_000, seed=0)
-        mdesc, mtag = f"Zipf(1.5) rows clipped to 10,000, n=1e6", "zipf"
+        mdesc, mtag = "Zipf(1.5) rows clipped to 10,000, n=1e6", "zipf"
     else:
         A = S.stencil27_random(args.grid, seed=0)
         mdesc, mtag = f"27-point stencil {args.grid}^3", f"27pt{args.grid}"
@@ -584,6 +698,7 @@ def main():
     gen_s = time.time() - t0
 
     # replicate so that the rotated working set exceeds the Infinity Cache
+    progress(f"headline: CSR float64, {mdesc}")
     fp = csr_bytes(n, nnz, 8, 8)
     R = max(2, int(np.ceil((1 << 30) / fp)))
     mats = [spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev)) for _ in range(R)]
@@ -599,47 +714,64 @@ def main():
     ms = time_launches(csr_step, args.steps, args.warmup, torch)
     b = csr_bytes(n, nnz, 8, 8)
     results["csr_f64"] = {"ms": ms, "GBs": b / ms / 1e6, "bytes": b}
+    del mats, xs, ys
+    torch.cuda.empty_cache()
 
-    # attainable streaming bandwidth (copy of a 2 GiB buffer, read + write)
+    # attainable streaming bandwidths (1 GiB read + 1 GiB written; 2 GiB read)
     cn = (1 << 30) // 8
     src = torch.empty(cn, dtype=torch.float64, device=dev).uniform_()
     dst = torch.empty_like(src)
     cms = time_launches(lambda i: spx.stream_copy(src, dst), 20, 3, torch)
     copy_gbs = 2 * cn * 8 / cms / 1e6
-    del src, dst
+    del dst
+    src2 = torch.empty(2 * cn, dtype=torch.float64, device=dev).uniform_()
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    rms = time_launches(lambda i: spx.stream_read(src2, sink), 20, 3, torch)
+    read_gbs = 2 * cn * 8 / rms / 1e6
+    del src, src2
+    torch.cuda.empty_cache()
 
     conversions = None
-    if args.sweep:
-        del mats
-        torch.cuda.empty_cache()
-        results.update(format_sweep(spx, torch, dev, A, x_h, args, "27pt"))
-        conversions = conversion_sweep(spx, torch, dev, A, "27pt")
-    if args.zipf:
-        Z = S.zipf_matrix(1_000_000, seed=0)
-        zx = S.uniform_vector(Z.n, seed=0)
-        results.update(format_sweep(spx, torch, dev, Z, zx, args, "zipf"))
-        del Z
+    if not args.no_sweep:
+        progress("sweep: 27-point formats")
+        results.update(format_sweep(spx, torch, dev, S.stencil27_random(100, seed=0) if mtag != "27pt100" else A,
+                                    x_h if mtag == "27pt100" else S.uniform_vector(10**6, seed=0), args, "27pt"))
+        progress("sweep: conversions")
+        conversions = conversion_sweep(spx, torch, dev, A if mtag == "27pt100" else S.stencil27_random(100, seed=0),
+                                       "27pt")
+        if not args.no_zipf:
+            progress("sweep: Zipf formats")
+            Z = A if mtag == "zipf" else S.zipf_matrix(1_000_000, seed=0)
+            zx = S.uniform_vector(Z.n, seed=0)
+            results.update(format_sweep(spx, torch, dev, Z, zx, args, "zipf", ell=args.zipf_ell))
+            del Z
 
+    progress("64x64 CG")
     cg_small = bench_cg_small(spx, S, torch, dev, args.cg_solves, args.cg_batch) if args.cg_solves > 0 else None
-    solvers = bench_solvers(spx, S, torch, dev) if args.solvers else None
-    serve = (bench_serve(spx, S, torch, dev, args.serve_requests, args.seed, args.serve_budget_gb, not args.no_cpu)
-             if args.serve_requests > 0 else None)
-    subwarp = subwarp_sweep(spx, torch, dev) if args.subwarp else None
+    solvers = bench_solvers(spx, S, torch, dev, cpu=not args.no_cpu) if not args.no_solvers else None
+    serve = None
+    if args.serve_requests > 0:
+        fracs = [float(f) for f in args.serve_fracs.split(",") if f]
+        serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed, fracs, args.serve_budget_gb,
+                            not args.no_cpu)
+    subwarp = None
+    if not args.no_subwarp:
+        progress("subwarp sweep")
+        subwarp = subwarp_sweep(spx, torch, dev)
 
     cpu = None
     if not args.no_cpu:
         import oracle as O
 
-        # the oracle's plain float64 CSR product, single thread, repeated for ~10 s
-        O.csr_spmv(A, x_h)
-        reps, t1 = 0, time.perf_counter()
-        while time.perf_counter() - t1 < 10.0:
-            O.csr_spmv(A, x_h)
-            reps += 1
-        cs = (time.perf_counter() - t1) / reps
-        cpu = {"value": b / cs / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} plain float64 CSR products of the full {mdesc} matrix, "
-                         f"{cs * 1e3:.1f} ms each, 1 thread"}
+        progress("cpu baseline: oracle CSR product")
+        cpu, cpu1 = cpu_spmv_baseline(A, x_h, b, mdesc)
+        cpu["single_thread"] = cpu1
+        if solvers is not None and "oracle_fp64_cg_poisson192" in solvers:
+            o = solvers["oracle_fp64_cg_poisson192"]
+            cpu["solver_cg_poisson192"] = {
+                "value": o["s"], "unit": "s to 1e-10", "cores": o["threads"], "kind": "oracle",
+                "iters": o["iters"], "gpu_fp64_cg_s": round(solvers["cg_fp64_poisson192"]["ms"] / 1e3, 4),
+                "sample": "one oracle CG solve (all-core variant) of the 7-point 192^3 system, run beside the GPU"}
         if cg_small is not None:
             # the oracle's CG on the 64x64 Poisson system (unpreconditioned, 1e-10), 1 thread
             P = S.poisson2d(64)
@@ -671,7 +803,9 @@ def main():
         "pct_hbm_peak": round(100 * r["GBs"] / HBM_PEAK_GBS, 2),
         "gflops": round(2 * nnz / r["ms"] / 1e6, 2),
         "copy_GBs": round(copy_gbs, 1),
+        "read_GBs": round(read_gbs, 1),
         "pct_of_copy": round(100 * r["GBs"] / copy_gbs, 2),
+        "pct_of_read": round(100 * r["GBs"] / read_gbs, 2),
         "roofline": {"bound": "hbm", "achieved": round(r["GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": kname, "bytes_per_launch": b},
@@ -684,11 +818,13 @@ def main():
         "subwarp": subwarp,
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
+        "wall_s": round(time.time() - T0, 1),
     }
     traffic = profile_traffic(f"csr_spmv_f64_{mtag}", b)
     if traffic is not None:
         line["roofline"]["traffic"] = traffic
         line["roofline"]["traffic_over_algorithmic"] = round(traffic / b, 4)
+        line["roofline"]["traffic_kind"] = "beyond-L2 bytes (FETCH_SIZE, WRITE_SIZE counters, copy-calibrated)"
     print(json.dumps(line), flush=True)
 
 

@@ -468,11 +468,15 @@ spx_status spx_subwarp_vote(const int32_t *pred, uint64_t *ballot, int32_t *any,
 spx_status spx_wave_segscan(const double *in, const int32_t *head, double *out, int64_t n,
                             hipStream_t stream);
 
-/* ------------------------------------------------------------ measurement helper
- * dst[i] = src[i] for n float64 values with the streaming-load pattern of
- * the SpMV kernels; used to measure the attainable HBM copy bandwidth next
- * to the SpMV rates. Asynchronous. */
+/* ------------------------------------------------------------ measurement helpers
+ * The attainable HBM bandwidth next to the SpMV rates (not part of the
+ * paper's method): every thread keeps eight 16-byte non-temporal loads in
+ * flight. spx_stream_copy: dst[i] = src[i] for n float64 values (16-byte
+ * aligned pointers). spx_stream_read: reads n float64 values (n even,
+ * 16-byte aligned) and writes nothing to sink[0] for finite data (it is there
+ * to keep the loads). Asynchronous. */
 spx_status spx_stream_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
+spx_status spx_stream_read(const double *src, int64_t n, double *sink, hipStream_t stream);
 
 #ifdef __cplusplus
 }

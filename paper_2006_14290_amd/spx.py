@@ -149,6 +149,7 @@ _sig("spx_subwarp_sum", [_vp, _vp, _i64, _i32, _i32, _vp])
 _sig("spx_subwarp_vote", [_vp, _vp, _vp, _vp, _i64, _i32, _vp])
 _sig("spx_wave_segscan", [_vp, _vp, _vp, _i64, _vp])
 _sig("spx_stream_copy", [_vp, _vp, _i64, _vp])
+_sig("spx_stream_read", [_vp, _i64, _vp, _vp])
 
 
 def check(status: int, where: str):
@@ -601,6 +602,10 @@ def wave_segscan(x: torch.Tensor, head: torch.Tensor, stream=None) -> torch.Tens
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
     check(_lib.spx_stream_copy(_ptr(src), _ptr(dst), src.numel(), _stream(stream)), "spx_stream_copy")
+
+
+def stream_read(src: torch.Tensor, sink: torch.Tensor, stream=None):
+    check(_lib.spx_stream_read(_ptr(src), src.numel(), _ptr(sink), _stream(stream)), "spx_stream_read")
 
 
 def version() -> int:

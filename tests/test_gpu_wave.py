@@ -67,9 +67,18 @@ def test_segscan_exact_on_integers_and_close_on_floats():
     assert np.all(np.abs(out - ref) <= 64 * 2.0 ** -53 * absref)
 
 
-def test_stream_copy():
-    x = torch.randn(1_000_003, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 1_000_003])
+def test_stream_copy(n):
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.full_like(x, float("nan"))
     spx.stream_copy(x, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+def test_stream_read_writes_nothing():
+    x = torch.randn(1_000_002, dtype=torch.float64, device="cuda")
+    sink = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    spx.stream_read(x, sink)
+    torch.cuda.synchronize()
+    assert float(sink[0]) == 7.0
