@@ -385,13 +385,19 @@ spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t w
 /* Continuous-batching server. Requests carry HOST arrays (kept alive by the
  * caller until the ticket completes); the server copies them into its HBM
  * pool (one allocation of hbm_budget_bytes, made at creation) when a slot and
- * memory are free, keeps each system and its CG state resident, and advances
- * all admitted systems together, tick after tick: the small ones in the
- * persistent one-work-group-per-system kernel, the wide ones in blocks of
- * wide iterations, each captured in a hipGraph and run concurrently on two
- * streams. Admission and retirement happen between ticks. A finished
- * request's solution is copied to x_out; it is bitwise the solution that
- * spx_cg_batch gives for the same system alone with the same path. */
+ * memory are free, keeps each system and its Krylov state resident, and
+ * advances all admitted systems together, tick after tick: the small ones in
+ * the persistent one-work-group-per-system kernel, the wide ones in blocks
+ * of wide iterations, each captured in a hipGraph and run concurrently on two
+ * streams. Admission and retirement happen between ticks. Symmetric positive
+ * definite systems are solved by CG; nonsymmetric ones by BiCGSTAB (the BiCG
+ * family the paper lists among the library's solvers, Section 1), request
+ * field solver = SPX_SOLVER_BICGSTAB, unpreconditioned, from x = 0, with the
+ * true-residual confirmation of spx_bicgstab_solve; BiCGSTAB systems always
+ * run one work-group each (never the wide path). A finished CG request's
+ * solution is bitwise the solution that spx_cg_batch gives for the same
+ * system alone with the same path; every request's result is bitwise the
+ * same alone or in any mix. */
 typedef struct spx_server spx_server;
 
 typedef struct {
@@ -409,7 +415,7 @@ typedef struct {
 
 typedef struct {
     int32_t n;
-    int32_t solver;          /* SPX_SOLVER_CG                                   */
+    int32_t solver;          /* SPX_SOLVER_CG or SPX_SOLVER_BICGSTAB            */
     int64_t nnz;
     const int32_t *rowptr;   /* HOST CSR, float64, canonical                    */
     const int32_t *colidx;
@@ -427,7 +433,10 @@ typedef struct {
 } spx_server_stats;
 
 spx_status spx_server_create(const spx_server_config *cfg, spx_server **out);
-/* Queues a request. SPX_ERR_BUDGET if it can never fit the HBM budget. */
+/* Queues a request after checking its CSR arrays with spx_validate_csr_host
+ * (SPX_ERR_FORMAT / RANGE / UNSORTED / DUPLICATE: nothing is queued).
+ * SPX_ERR_BUDGET if it can never fit the HBM budget; SPX_ERR_ARG for a
+ * solver other than CG or BiCGSTAB. */
 spx_status spx_serve_submit(spx_server *server, const spx_request *req, uint64_t *ticket);
 /* SPX_PENDING while queued or running; afterwards the request's status, and
  * *info (if not NULL) with iterations, residuals and device_ms = submit-to-done

@@ -3,7 +3,8 @@
 // A persistent grid of resident work-groups takes systems ("slots") from an
 // atomic counter; the work-group that takes a slot runs up to slot.budget
 // iterations of unpreconditioned CG on it (the textbook recurrences of
-// Hestenes & Stiefel) entirely by itself: the CSR product with adaptive
+// Hestenes & Stiefel), or of BiCGSTAB for a nonsymmetric slot, entirely by
+// itself: the CSR product with adaptive
 // subwarps (DPP reductions), the vector updates, and every dot product as a
 // fixed-order work-group reduction. There is no synchronisation between
 // work-groups at all, so nothing waits on another group and each system's
@@ -19,6 +20,27 @@
 namespace spx {
 
 constexpr int kBatchWaves = kBatchThreads / kWave;
+
+// Work-group sums of NV values, fixed order, results in every thread
+// (s_red holds NV * kBatchWaves doubles).
+template <int NV>
+__device__ __forceinline__ void wg_sums(double (&v)[NV], double *s_red)
+{
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    if (lane_id() == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) s_red[j * kBatchWaves + w] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double t = 0.0;
+        for (int k = 0; k < kBatchWaves; ++k) t += s_red[j * kBatchWaves + k];
+        v[j] = t;
+    }
+    __syncthreads();
+}
 
 // Work-group sum, fixed order, result in every thread.
 __device__ __forceinline__ double wg_sum(double v, double *s_red)
@@ -55,6 +77,207 @@ __device__ double wg_spmv(const BatchSlot &S, const double *__restrict__ v, doub
         }
     }
     return wg_sum(acc, s_red);
+}
+
+// q = A v over all rows; d[0] = sum_i q_i w_i and, if KD == 2, d[1] = sum_i
+// q_i^2 (all threads).
+template <int KD>
+__device__ void wg_spmv_dots(const BatchSlot &S, const double *__restrict__ v, double *__restrict__ q,
+                             const double *__restrict__ w, double (&d)[KD], double *s_red)
+{
+    const int sub = S.sub;
+    const int g = threadIdx.x / sub, sl = threadIdx.x % sub;
+    const int G = kBatchThreads / sub;
+#pragma unroll
+    for (int j = 0; j < KD; ++j) d[j] = 0.0;
+    for (int64_t row0 = 0; row0 < S.n; row0 += G) {  // uniform trip count: DPP needs whole groups
+        const int64_t row = row0 + g;
+        double sum = 0.0;
+        if (row < S.n) {
+            const int32_t a = S.rowptr[row], b = S.rowptr[row + 1];
+#pragma unroll 4
+            for (int32_t k = a + sl; k < b; k += sub) sum += S.val[k] * v[S.col[k]];
+        }
+        sum = subwave_sum_dyn(sum, sub);
+        if (row < S.n && sl == 0) {
+            q[row] = sum;
+            d[0] += sum * w[row];
+            if constexpr (KD == 2) d[1] += sum * sum;
+        }
+    }
+    wg_sums<KD>(d, s_red);
+}
+
+// Unpreconditioned BiCGSTAB (van der Vorst 1992, in the form of Barrett et
+// al., "Templates", 1994) on one slot from x0 = 0, resumable across
+// launches: s overwrites r, v is kept in q. Convergence of ||s|| (half step)
+// or ||r|| (full step) is confirmed with the true residual b - A x (A x is
+// formed in t); a miss restarts the recurrences from it with r_hat = r.
+// Iterations count full steps (two products each).
+__device__ void run_slot_bicgstab(BatchSlot *slot, double *s_red)
+{
+    const BatchSlot S = *slot;
+    if (S.status != kSlotRunning || S.budget <= 0) return;
+    const int64_t n = S.n;
+    const int tid = threadIdx.x;
+    double *__restrict__ x = S.x;
+    double *__restrict__ r = S.r;
+    double *__restrict__ rh = S.rh;
+    double *__restrict__ p = S.p;
+    double *__restrict__ v = S.q;
+    double *__restrict__ t = S.t;
+    double rho = S.rho, rho0 = S.rho0, alpha = S.alpha, omega = S.omega, rr = S.rr, bb = S.bb,
+           relres = S.relres_true;
+    int32_t iters = S.iters, spmv = S.spmv, status = kSlotRunning, started = S.started, first = S.first;
+    if (!started) {  // x0 = 0: r = b, r_hat = r
+        double sum[1] = {0.0};
+        for (int64_t i = tid; i < n; i += kBatchThreads) {
+            const double bi = S.b[i];
+            r[i] = bi;
+            rh[i] = bi;
+            sum[0] += bi * bi;
+        }
+        wg_sums<1>(sum, s_red);
+        bb = sum[0];
+        rr = bb;
+        rho = bb;  // r_hat . r with r_hat = r
+        rho0 = alpha = omega = 1.0;
+        first = 1;
+        started = 1;
+        if (!__builtin_isfinite(bb)) status = kSlotNonfinite;
+        else if (bb == 0.0) {
+            status = kSlotConverged;
+            relres = 0.0;
+        }
+    }
+    // true residual r = b - A x (A x in t); converged, or restart from it
+    auto confirm = [&]() -> bool {
+        double d[1];
+        wg_spmv_dots<1>(S, x, t, x, d, s_red);  // the dot is not used
+        spmv += 1;
+        double tr[1] = {0.0};
+        for (int64_t i = tid; i < n; i += kBatchThreads) {
+            const double ri = S.b[i] - t[i];
+            r[i] = ri;
+            rh[i] = ri;
+            tr[0] += ri * ri;
+        }
+        wg_sums<1>(tr, s_red);
+        if (tr[0] <= S.tol2 * bb) {
+            relres = sqrt(tr[0] / bb);
+            return true;
+        }
+        rr = tr[0];
+        rho = tr[0];
+        rho0 = alpha = omega = 1.0;
+        first = 1;
+        return false;
+    };
+    for (int it = 0; it < S.budget && status == kSlotRunning; ++it) {
+        if (iters >= S.maxit) {
+            status = kSlotMaxit;
+            break;
+        }
+        iters += 1;
+        if (!__builtin_isfinite(rho)) {
+            status = kSlotNonfinite;
+            break;
+        }
+        if (rho == 0.0) {
+            status = kSlotBreakdown;
+            break;
+        }
+        if (first) {
+            for (int64_t i = tid; i < n; i += kBatchThreads) p[i] = r[i];
+            first = 0;
+        } else {
+            const double beta = (rho / rho0) * (alpha / omega);
+            for (int64_t i = tid; i < n; i += kBatchThreads) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        __syncthreads();  // p complete before the product gathers it
+        double d1[1];
+        wg_spmv_dots<1>(S, p, v, rh, d1, s_red);  // v = A p, r_hat . v
+        spmv += 1;
+        const double rhv = d1[0];
+        if (rhv == 0.0 || !__builtin_isfinite(rhv)) {
+            status = __builtin_isfinite(rhv) ? kSlotBreakdown : kSlotNonfinite;
+            break;
+        }
+        alpha = rho / rhv;
+        double ss[1] = {0.0};
+        for (int64_t i = tid; i < n; i += kBatchThreads) {
+            const double si = r[i] - alpha * v[i];
+            r[i] = si;
+            ss[0] += si * si;
+        }
+        wg_sums<1>(ss, s_red);  // its barriers also complete s before the next product
+        rr = ss[0];
+        if (ss[0] <= S.tol2 * bb) {
+            for (int64_t i = tid; i < n; i += kBatchThreads) x[i] += alpha * p[i];
+            __syncthreads();
+            if (confirm()) {
+                status = kSlotConverged;
+                break;
+            }
+            continue;
+        }
+        double d2[2];
+        wg_spmv_dots<2>(S, r, t, r, d2, s_red);  // t = A s, t . s, t . t
+        spmv += 1;
+        const double ts = d2[0], tt = d2[1];
+        if (!__builtin_isfinite(tt)) {
+            status = kSlotNonfinite;
+            break;
+        }
+        if (tt == 0.0) {
+            status = kSlotBreakdown;
+            break;
+        }
+        omega = ts / tt;
+        double nr[2] = {0.0, 0.0};
+        for (int64_t i = tid; i < n; i += kBatchThreads) {
+            const double si = r[i];
+            x[i] += alpha * p[i] + omega * si;
+            const double ri = si - omega * t[i];
+            r[i] = ri;
+            nr[0] += ri * ri;
+            nr[1] += rh[i] * ri;
+        }
+        wg_sums<2>(nr, s_red);
+        rr = nr[0];
+        rho0 = rho;
+        rho = nr[1];
+        if (!__builtin_isfinite(rr)) {
+            status = kSlotNonfinite;
+            break;
+        }
+        if (rr <= S.tol2 * bb) {
+            if (confirm()) {
+                status = kSlotConverged;
+                break;
+            }
+            continue;
+        }
+        if (omega == 0.0) {
+            status = kSlotBreakdown;
+            break;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        slot->rho = rho;
+        slot->rho0 = rho0;
+        slot->alpha = alpha;
+        slot->omega = omega;
+        slot->rr = rr;
+        slot->bb = bb;
+        slot->iters = iters;
+        slot->spmv = spmv;
+        slot->started = started;
+        slot->first = first;
+        slot->status = status;
+        slot->relres_true = (status == kSlotConverged) ? relres : (bb > 0 ? sqrt(rr / bb) : 0.0);
+    }
 }
 
 // kLds: the system has at most kBatchLdsRows rows and its search direction
@@ -163,7 +386,7 @@ __device__ void run_slot(BatchSlot *slot, double *s_red, double *s_p)
 __global__ __launch_bounds__(kBatchThreads) void batch_cg_kernel(BatchSlot *slots, int32_t nslots,
                                                                 int32_t *counter)
 {
-    __shared__ double s_red[kBatchWaves];
+    __shared__ double s_red[2 * kBatchWaves];
     __shared__ double s_p[kBatchLdsRows];
     __shared__ int32_t s_k;
     while (true) {
@@ -172,7 +395,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_cg_kernel(BatchSlot *slot
         const int32_t k = s_k;
         __syncthreads();
         if (k >= nslots) return;  // every work-group leaves once the slots are handed out
-        if (slots[k].n <= kBatchLdsRows) run_slot<true>(&slots[k], s_red, s_p);
+        if (slots[k].solver == kSlotBicgstab) run_slot_bicgstab(&slots[k], s_red);
+        else if (slots[k].n <= kBatchLdsRows) run_slot<true>(&slots[k], s_red, s_p);
         else run_slot<false>(&slots[k], s_red, s_p);
         __syncthreads();
     }
@@ -401,7 +625,9 @@ __global__ __launch_bounds__(kBSThreads) void batch_small_kernel(BatchSlot *slot
         __syncthreads();
         if (k >= nslots) return;  // every work-group leaves once the slots are handed out
         BatchSlot *slot = &slots[k];
-        if (slot->status != kSlotRunning || slot->budget <= 0 || slot->n > kBatchSmallRows) continue;
+        if (slot->status != kSlotRunning || slot->budget <= 0 || slot->n > kBatchSmallRows ||
+            slot->solver != kSlotCg)
+            continue;
         // the cached form when no row of this system has more than kBSLen entries
         bool long_row = false;
         for (int i = threadIdx.x; i < slot->n; i += kBSThreads)

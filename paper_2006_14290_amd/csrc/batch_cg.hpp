@@ -17,13 +17,20 @@ enum SlotStatus : int32_t {
     kSlotEmpty = 5,
 };
 
+// Krylov method of a slot.
+enum SlotSolver : int32_t {
+    kSlotCg = 0,        // CG (symmetric positive definite systems)
+    kSlotBicgstab = 1,  // BiCGSTAB (nonsymmetric systems)
+};
+
 // Device descriptor of one system (all pointers are device memory).
 struct BatchSlot {
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
     const double *b;
-    double *x, *r, *p, *q;
+    double *x, *r, *p, *q;  // BiCGSTAB: q holds v = A p
+    double *rh, *t;         // BiCGSTAB only: shadow residual, t = A s
     int32_t n;
     int32_t sub;       // lanes per row in the product (power of two <= 64)
     int32_t status;    // SlotStatus
@@ -31,6 +38,9 @@ struct BatchSlot {
     double tol2, bb, rho, rr;
     int32_t iters, maxit, budget, spmv;  // budget: iterations allowed in this launch
     double relres_true;
+    int32_t solver;  // SlotSolver
+    int32_t first;   // BiCGSTAB: the next step starts a (re)started recurrence (p = r)
+    double rho0, alpha, omega;  // BiCGSTAB scalars carried between steps
 };
 
 // Lanes per row for a mean row length (smallest power of two >= mean, <= 16).
@@ -123,11 +133,12 @@ constexpr int kBatchSmallRows = 4096;
 // one-group kernel (128 KB).
 constexpr int kBatchLdsRows = 16384;
 
-// Advance slots[0..nslots) by at most slot.budget CG iterations each (or to
+// Advance slots[0..nslots) by at most slot.budget iterations each (or to
 // convergence); work-groups take slots from *counter, which must be 0 at
 // launch (batch_reset does that). grid: number of resident work-groups.
-// batch_cg_launch skips systems of at most kBatchSmallRows rows and uses
-// counter[0]; batch_small_launch takes only those and uses counter[1].
+// batch_cg_launch runs every BiCGSTAB slot and the CG slots of more than
+// kBatchSmallRows rows, and uses counter[0]; batch_small_launch takes the
+// other CG slots and uses counter[1].
 spx_status batch_cg_launch(BatchSlot *slots, int32_t nslots, int32_t *counter, int64_t grid, hipStream_t stream);
 spx_status batch_small_launch(BatchSlot *slots, int32_t nslots, int32_t *counter, int64_t grid, hipStream_t stream);
 // Zeroes counter[0] and counter[1].

@@ -62,17 +62,19 @@ size_t wide_extra_bytes(int64_t n, int64_t nnz)
 }
 
 // Device bytes of one system: CSR arrays + b, x, r, p, q (+ the partials and
-// partition of the wide path).
-size_t system_bytes(int64_t n, int64_t nnz, bool wide)
+// partition of the wide path; BiCGSTAB adds r_hat and t).
+size_t system_bytes(int64_t n, int64_t nnz, bool wide, bool bicgstab)
 {
     return align256((size_t)(n + 1) * 4) + align256((size_t)nnz * 4) + align256((size_t)nnz * 8) +
-           5 * align256((size_t)n * 8) + (wide ? wide_extra_bytes(n, nnz) : 0);
+           (bicgstab ? 7 : 5) * align256((size_t)n * 8) + (wide ? wide_extra_bytes(n, nnz) : 0);
 }
 
-bool is_wide(int32_t wide_min_rows, int64_t n)
+// CG systems from wide_min_rows rows on take the wide path; BiCGSTAB
+// systems always run one work-group each.
+bool is_wide(int32_t wide_min_rows, int64_t n, int32_t solver)
 {
     const int64_t t = wide_min_rows == 0 ? kWideDefaultRows : wide_min_rows;
-    return wide_min_rows >= 0 && n >= t;
+    return solver == SPX_SOLVER_CG && wide_min_rows >= 0 && n >= t;
 }
 
 struct Pool {
@@ -205,12 +207,13 @@ struct spx_server {
 
 namespace {
 
-// Budget of CG iterations for one tick: about tick_us of one work-group's
-// streaming time (iteration bytes / an assumed 25 GB/s per work-group).
-int32_t budget_for(const spx_server &S, int64_t n, int64_t nnz, int32_t remaining)
+// Budget of iterations for one tick: about tick_us of one work-group's
+// streaming time (iteration bytes / an assumed 25 GB/s per work-group; a
+// BiCGSTAB step has two products and about twice the vector traffic).
+int32_t budget_for(const spx_server &S, int64_t n, int64_t nnz, int32_t remaining, bool bicgstab)
 {
     if (S.cfg.iters_per_tick > 0) return std::min(S.cfg.iters_per_tick, std::max(remaining, 1));
-    const double bytes = (double)nnz * 12.0 + (double)n * 76.0;
+    const double bytes = ((double)nnz * 12.0 + (double)n * 76.0) * (bicgstab ? 2.0 : 1.0);
     const double us_per_iter = bytes / 25e3;  // 25 GB/s = 25e3 bytes per microsecond
     const double tick_us = S.cfg.tick_us > 0 ? S.cfg.tick_us : 2000.0;
     int64_t b = (int64_t)(tick_us / std::max(us_per_iter, 0.01));
@@ -287,6 +290,9 @@ int admit(spx_server &S)
         double *r = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *pp = reinterpret_cast<double *>(carve((size_t)n * 8));
         double *q = reinterpret_cast<double *>(carve((size_t)n * 8));
+        const bool bicg = p.req.solver == SPX_SOLVER_BICGSTAB;
+        double *rh = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
+        double *tv = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
         double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 8)) : nullptr;
         double *part_a = p.wide ? reinterpret_cast<double *>(carve((size_t)csr_tiles(nnz) * 8)) : nullptr;
         int32_t *cpart = p.wide ? reinterpret_cast<int32_t *>(carve((size_t)csr_partition_bytes(nnz))) : nullptr;
@@ -349,6 +355,10 @@ int admit(spx_server &S)
         d.r = r;
         d.p = pp;
         d.q = q;
+        d.rh = rh;
+        d.t = tv;
+        d.solver = bicg ? kSlotBicgstab : kSlotCg;
+        d.first = 1;
         d.n = (int32_t)n;
         d.sub = narrow_sub_for(n, nnz);
         d.status = kSlotRunning;
@@ -529,7 +539,8 @@ void worker_main(spx_server *Sp)
                 d.budget = 0;
                 continue;
             }
-            d.budget = budget_for(S, S.active[i].n, S.active[i].nnz, std::max(1, d.maxit - d.iters));
+            d.budget = budget_for(S, S.active[i].n, S.active[i].nnz, std::max(1, d.maxit - d.iters),
+                                  d.solver == kSlotBicgstab);
             narrow = true;
         }
         hipError_t e = hipSuccess;
@@ -746,13 +757,14 @@ extern "C" spx_status spx_serve_submit(spx_server *S, const spx_request *req, ui
     SPX_REQUIRE(S && req && ticket, SPX_ERR_ARG, "spx_serve_submit: null argument");
     SPX_REQUIRE(req->n >= 1 && req->nnz >= 0 && req->rowptr && req->b && (req->nnz == 0 || (req->colidx && req->vals)),
                 SPX_ERR_ARG, "spx_serve_submit: bad request");
-    SPX_REQUIRE(req->solver == SPX_SOLVER_CG, SPX_ERR_ARG, "spx_serve_submit: only CG is served");
+    SPX_REQUIRE(req->solver == SPX_SOLVER_CG || req->solver == SPX_SOLVER_BICGSTAB, SPX_ERR_ARG,
+                "spx_serve_submit: solver %d is not served (CG and BiCGSTAB are)", req->solver);
     SPX_REQUIRE(req->tol >= 0.0, SPX_ERR_ARG, "spx_serve_submit: negative tolerance");
     SPX_REQUIRE(req->nnz <= INT32_MAX, SPX_ERR_ARG, "spx_serve_submit: nnz exceeds int32");
     // nothing malformed may reach the kernels that every resident system shares
     SPX_CHECK(validate_csr_host(req->n, req->n, req->nnz, req->rowptr, req->colidx));
-    const bool wide = is_wide(S->cfg.wide_min_rows, req->n);
-    const size_t bytes = system_bytes(req->n, req->nnz, wide);
+    const bool wide = is_wide(S->cfg.wide_min_rows, req->n, req->solver);
+    const size_t bytes = system_bytes(req->n, req->nnz, wide, req->solver == SPX_SOLVER_BICGSTAB);
     std::lock_guard<std::mutex> lk(S->mu);
     SPX_REQUIRE(S->fatal.empty(), SPX_ERR_HIP, "spx_serve_submit: server failed: %s", S->fatal.c_str());
     if (bytes > S->cfg.hbm_budget_bytes) {

@@ -523,14 +523,16 @@ class Server:
         self._h = h
         self._keep = {}  # ticket -> host arrays kept alive until completion
 
-    def submit(self, A, b: np.ndarray, tol: float = 1e-8, maxit: int = 0, x_out: Optional[np.ndarray] = None):
-        """A: host CSR (rowptr/col/val numpy); returns the ticket."""
+    def submit(self, A, b: np.ndarray, tol: float = 1e-8, maxit: int = 0, x_out: Optional[np.ndarray] = None,
+               solver: int = SOLVER_CG):
+        """A: host CSR (rowptr/col/val numpy); solver SOLVER_CG (SPD) or
+        SOLVER_BICGSTAB (nonsymmetric); returns the ticket."""
         rp = np.ascontiguousarray(A.rowptr, np.int32)
         ci = np.ascontiguousarray(A.col, np.int32)
         va = np.ascontiguousarray(A.val, np.float64)
         bb = np.ascontiguousarray(b, np.float64)
         x = np.empty(A.n, np.float64) if x_out is None else x_out
-        req = Request(int(A.n), SOLVER_CG, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+        req = Request(int(A.n), int(solver), int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
                       bb.ctypes.data, x.ctypes.data, tol, maxit, 0)
         t = ctypes.c_uint64(0)
         check(_lib.spx_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "spx_serve_submit")

@@ -295,3 +295,76 @@ def test_server_all_one_group_when_wide_disabled():
         np.testing.assert_array_equal(host(xs[0]).view(np.uint64), x.view(np.uint64))
     finally:
         srv.close()
+
+
+# ---------------------------------------------------------------- nonsymmetric requests
+NONSYM = [(12, 21), (20, 22), (28, 23), (36, 24)]  # convection-diffusion N^3: n = 1,728 .. 46,656
+
+
+def _nonsym(N, seed):
+    A = S.convdiff3d_upwind(N)
+    xs = S.uniform_vector(A.n, seed=seed, purpose="xstar")
+    b, _ = O.csr_spmv_dot2(A, xs)
+    return A, b
+
+
+def _served_alone(A, b, solver, **cfg):
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=256 << 20, **cfg)
+    try:
+        return srv.wait(srv.submit(A, b, tol=1e-8, solver=solver), timeout_s=120)
+    finally:
+        srv.close()
+
+
+def test_server_bicgstab_alone_mix_bitwise_and_oracle():
+    """Nonsymmetric (upwind convection-diffusion) systems served by BiCGSTAB
+    next to CG systems: each meets 1e-8 through the oracle's true residual,
+    takes about the oracle's BiCGSTAB iteration count, and is bitwise the
+    same served alone, in the mix, and with one iteration per tick."""
+    systems = [_nonsym(N, s) for N, s in NONSYM]
+    alone = [_served_alone(A, b, spx.SOLVER_BICGSTAB) for A, b in systems]
+    cg = [_system(*m) for m in MIX[:6]]
+    srv = spx.Server(max_slots=5, hbm_budget_bytes=512 << 20, tick_us=300)
+    try:
+        order = []
+        for i in range(max(len(systems), len(cg))):
+            if i < len(cg):
+                order.append(("cg", i, srv.submit(*cg[i], tol=1e-8)))
+            if i < len(systems):
+                order.append(("bi", i, srv.submit(*systems[i], tol=1e-8, solver=spx.SOLVER_BICGSTAB)))
+        for kind, i, t in order:
+            x, info = srv.wait(t, timeout_s=120)
+            assert info["status"] == spx.OK, (kind, i, info)
+            A, b = (systems if kind == "bi" else cg)[i]
+            assert _relres(A, b, x) <= 1e-8
+            if kind == "bi":
+                xa, ia = alone[i]
+                assert ia["iters"] == info["iters"]
+                np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+                _, io = O.bicgstab(A, b, tol=1e-8)
+                assert io["status"] == O.OK
+                assert abs(info["iters"] - io["iters"]) <= 0.1 * io["iters"] + 5, (info["iters"], io["iters"])
+                assert info["spmv_count"] >= 2 * info["iters"] - 1
+            else:
+                xa, _ = _alone(A, b, 1e-8)
+                np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+    finally:
+        srv.close()
+    # one BiCGSTAB step per tick: the state carried between launches gives the same bits
+    A, b = systems[1]
+    x1, i1 = _served_alone(A, b, spx.SOLVER_BICGSTAB, iters_per_tick=1)
+    assert i1["status"] == spx.OK and i1["iters"] == alone[1][1]["iters"]
+    np.testing.assert_array_equal(x1.view(np.uint64), alone[1][0].view(np.uint64))
+
+
+def test_server_bicgstab_solves_spd_and_refuses_other_solvers():
+    A, b = _system("spd", 3000, 31)
+    x, info = _served_alone(A, b, spx.SOLVER_BICGSTAB)
+    assert info["status"] == spx.OK and _relres(A, b, x) <= 1e-8
+    srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20)
+    try:
+        with pytest.raises(spx.SpxError, match="ERR_ARG"):
+            srv.submit(A, b, solver=spx.SOLVER_GMRES)
+        assert srv.stats()["submitted"] == 0
+    finally:
+        srv.close()
