@@ -382,6 +382,20 @@ spx_status spx_cg_batch_workspace(const spx_batch_system *sys, int32_t count, si
  * system's status (each sys[i].status tells). */
 spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* spx_cg_batch without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc). The workspace spx_cg_batch would
+ * take is carved from a fixed 64 MiB array of device memory inside the
+ * library instead (one per GPU, held until the process ends; its address is
+ * looked up on the device's first call). Same arguments otherwise, same
+ * results bit for bit. SPX_ERR_ARG when the batch needs more than 64 MiB of
+ * workspace (spx_cg_batch_workspace tells how much; about 3 * 8 * n bytes per
+ * system plus tables). Every call on a GPU shares that GPU's array and finds
+ * it as the last call left it; nothing in it needs clearing. Calls from this
+ * process on one device are serialised by the library; calls that overlap on
+ * one GPU from elsewhere (another copy of the library) would race. */
+spx_status spx_cg_batch_noalloc(spx_batch_system *sys, int32_t count, hipStream_t stream);
+
 /* Continuous-batching server. Requests carry HOST arrays (kept alive by the
  * caller until the ticket completes); the server copies them into its HBM
  * pool (one allocation of hbm_budget_bytes, made at creation) when a slot and

@@ -925,21 +925,25 @@ extern "C" spx_status spx_cg_batch_workspace(const spx_batch_system *sys, int32_
     return SPX_OK;
 }
 
-extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t ws_bytes,
-                                   hipStream_t stream)
+namespace {
+
+spx_status check_batch(const spx_batch_system *sys, int32_t count, const char *who)
 {
-    clear_error();
-    SPX_REQUIRE(sys && count >= 0, SPX_ERR_ARG, "spx_cg_batch: bad argument");
-    if (count == 0) return SPX_OK;
+    SPX_REQUIRE(sys && count >= 0, SPX_ERR_ARG, "%s: bad argument", who);
     for (int32_t i = 0; i < count; ++i) {
         SPX_REQUIRE(sys[i].n >= 1 && sys[i].rowptr && sys[i].b && sys[i].x && (sys[i].nnz == 0 || (sys[i].colidx && sys[i].vals)),
-                    SPX_ERR_ARG, "spx_cg_batch: bad system %d", i);
+                    SPX_ERR_ARG, "%s: bad system %d", who, i);
         SPX_REQUIRE(sys[i].path >= SPX_BATCH_AUTO && sys[i].path <= SPX_BATCH_WIDE, SPX_ERR_ARG,
-                    "spx_cg_batch: bad path of system %d", i);
+                    "%s: bad path of system %d", who, i);
     }
-    const BatchLayout L = batch_layout(sys, count);
-    SPX_REQUIRE(ws && ws_bytes >= L.total, SPX_ERR_ARG, "spx_cg_batch: workspace too small");
-    char *base = static_cast<char *>(ws);
+    return SPX_OK;
+}
+
+// The batch on a workspace of at least L.total bytes at base (checked by the
+// caller); the workspace needs no clearing (the work counter is reset by a
+// kernel, everything else is written before it is read).
+spx_status cg_batch_run(spx_batch_system *sys, int32_t count, const BatchLayout &L, char *base, hipStream_t stream)
+{
     BatchSlot *slots_dev = reinterpret_cast<BatchSlot *>(base + L.slots);
     int32_t *counter = reinterpret_cast<int32_t *>(base + L.counter);
     WideSlot *wslots_dev = reinterpret_cast<WideSlot *>(base + L.wslots);
@@ -1085,4 +1089,69 @@ extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *w
     }
     if (first != SPX_OK) set_error("spx_cg_batch: at least one system did not converge");
     return first;
+}
+
+// Device scratch of spx_cg_batch_noalloc: a fixed array in the code object,
+// so that the call needs no allocation. Each GPU the library runs on holds
+// its own copy until the process ends. Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol); it
+// uses the device address that hipGetSymbolAddress returned for the device.
+constexpr size_t kBatchScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu[kMaxScratchDevices];  // one no-allocation batch at a time per device
+std::mutex g_scratch_addr_mu;
+char *g_scratch_addr[kMaxScratchDevices] = {};
+
+// The scratch array's address on the current device, looked up on the
+// device's first call.
+spx_status scratch_address(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_addr_mu);
+    if (g_scratch_addr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("spx_cg_batch_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return SPX_ERR_HIP;
+        }
+        g_scratch_addr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return SPX_OK;
+}
+
+}  // namespace
+
+extern "C" spx_status spx_cg_batch(spx_batch_system *sys, int32_t count, void *ws, size_t ws_bytes,
+                                   hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_batch(sys, count, "spx_cg_batch"));
+    if (count == 0) return SPX_OK;
+    const BatchLayout L = batch_layout(sys, count);
+    SPX_REQUIRE(ws && ws_bytes >= L.total, SPX_ERR_ARG, "spx_cg_batch: workspace too small");
+    return cg_batch_run(sys, count, L, static_cast<char *>(ws), stream);
+}
+
+extern "C" spx_status spx_cg_batch_noalloc(spx_batch_system *sys, int32_t count, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_batch(sys, count, "spx_cg_batch_noalloc"));
+    if (count == 0) return SPX_OK;
+    const BatchLayout L = batch_layout(sys, count);
+    SPX_REQUIRE(L.total <= kBatchScratchBytes, SPX_ERR_ARG,
+                "spx_cg_batch_noalloc: the batch needs %zu bytes of scratch, more than the %zu available "
+                "(use spx_cg_batch with a workspace)",
+                L.total, kBatchScratchBytes);
+    int dev = 0;
+    SPX_HIP(hipGetDevice(&dev));
+    SPX_REQUIRE(dev >= 0 && dev < kMaxScratchDevices, SPX_ERR_ARG, "spx_cg_batch_noalloc: device %d out of range",
+                dev);
+    char *base = nullptr;
+    SPX_CHECK(scratch_address(dev, &base));
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    return cg_batch_run(sys, count, L, base, stream);
 }

@@ -138,6 +138,7 @@ class ServerStats(ctypes.Structure):
 
 _sig("spx_cg_batch_workspace", [ctypes.POINTER(BatchSystem), _i32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("spx_cg_batch", [ctypes.POINTER(BatchSystem), _i32, _vp, ctypes.c_size_t, _vp])
+_sig("spx_cg_batch_noalloc", [ctypes.POINTER(BatchSystem), _i32, _vp])
 _sig("spx_server_create", [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)])
 _sig("spx_serve_submit", [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
 _sig("spx_serve_poll", [_vp, ctypes.c_uint64, _SIP])
@@ -488,10 +489,11 @@ def ir_solve(A64: Matrix, Alow: Matrix, b: torch.Tensor, tol: float = 1e-10, inn
 BATCH_AUTO, BATCH_ONE_GROUP, BATCH_WIDE = 0, 1, 2
 
 
-def cg_batch(mats, bs, tol=1e-8, maxit=100000, path=BATCH_AUTO, stream=None):
+def cg_batch(mats, bs, tol=1e-8, maxit=100000, path=BATCH_AUTO, stream=None, noalloc=False):
     """Solve independent CSR systems (device Matrix objects, float64) together:
     one work-group per small system, the wide path for large ones (`path`
-    forces one). Returns (xs, infos)."""
+    forces one). noalloc=True calls spx_cg_batch_noalloc (the library's own
+    fixed device scratch instead of a workspace). Returns (xs, infos)."""
     count = len(mats)
     arr = (BatchSystem * count)()
     xs = []
@@ -500,12 +502,15 @@ def cg_batch(mats, bs, tol=1e-8, maxit=100000, path=BATCH_AUTO, stream=None):
         xs.append(x)
         arr[i] = BatchSystem(A.nrows, path, A.nnz, _ptr(A.rowptr), _ptr(A.colidx), _ptr(A.vals), _ptr(b), _ptr(x),
                              tol, maxit, 0, 0, 0, 0.0)
-    nbytes = ctypes.c_size_t(0)
-    check(_lib.spx_cg_batch_workspace(arr, count, ctypes.byref(nbytes)), "spx_cg_batch_workspace")
-    ws = _workspace(nbytes.value, bs[0].device)
-    st = _lib.spx_cg_batch(arr, count, _ptr(ws), ws.numel(), _stream(stream))
+    if noalloc:
+        st = _lib.spx_cg_batch_noalloc(arr, count, _stream(stream))
+    else:
+        nbytes = ctypes.c_size_t(0)
+        check(_lib.spx_cg_batch_workspace(arr, count, ctypes.byref(nbytes)), "spx_cg_batch_workspace")
+        ws = _workspace(nbytes.value, bs[0].device)
+        st = _lib.spx_cg_batch(arr, count, _ptr(ws), ws.numel(), _stream(stream))
     if st not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NONFINITE):
-        check(st, "spx_cg_batch")
+        check(st, "spx_cg_batch_noalloc" if noalloc else "spx_cg_batch")
     infos = [{"status": arr[i].status, "iters": arr[i].iters, "spmv_count": arr[i].spmv_count,
               "relres_true": arr[i].relres_true} for i in range(count)]
     return xs, infos
