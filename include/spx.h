@@ -50,7 +50,9 @@ typedef enum {
     SPX_ERR_BREAKDOWN = 11,    /* Krylov breakdown (p'Ap <= 0, rho = 0, ...)       */
     SPX_ERR_NONFINITE = 12,    /* NaN or Inf in a residual norm                    */
     SPX_PENDING = 13,          /* serving: request not finished yet                */
-    SPX_CANCELLED = 14         /* serving: request cancelled                       */
+    SPX_CANCELLED = 14,        /* serving: request cancelled                       */
+    SPX_STATUS_MAX_ENUM = 0x7fffffff /* not a status: makes every int32 value a valid
+                                        spx_status, so spx_status_string accepts any */
 } spx_status;
 
 typedef enum {

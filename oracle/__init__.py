@@ -25,6 +25,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "spx_oracle.c")
 _SRC_OMP = os.path.join(_HERE, "spx_oracle_omp.c")
 _LIB = os.path.join(_HERE, "_spx_oracle.so")
+# A differently built copy of the same sources (the sanitizer test builds one
+# with AddressSanitizer/UBSan) may be loaded instead.
+_LIB_OVERRIDE = os.environ.get("SPX_ORACLE_LIB")
 
 # Status codes of the oracle's solvers.
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE, ZERO_DIAG = 0, 1, 2, 3, 4
@@ -47,9 +50,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
             build()
-        _lib = ctypes.CDLL(_LIB)
+        _lib = ctypes.CDLL(_LIB_OVERRIDE or _LIB)
         _declare(_lib)
     return _lib
 

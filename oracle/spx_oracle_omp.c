@@ -9,7 +9,8 @@
  *    plain oracle does, so y is bitwise the plain oracle's;
  *  - CG (Hestenes-Stiefel; Barrett et al., "Templates", 1994) takes the
  *    same steps as orc_cg with precond 0 (none) or 1 (scalar Jacobi) from
- *    x0 = 0; the dot products are summed per thread and then combined, and
+ *    x0 = 0; the dot products are summed per thread over a fixed block and
+ *    the partials added in thread order (reproducible for a thread count), and
  *    the true residual that confirms convergence is summed in plain float64
  *    (orc_cg uses Dot2 there), so its iterates agree with orc_cg's to
  *    rounding.
@@ -36,11 +37,28 @@ void orc_csr_spmv_omp(int32_t n, const int32_t *rowptr, const int32_t *col, cons
     }
 }
 
+/* Thread t of T owns the entries [t*n/T, (t+1)*n/T). */
+static int32_t block_lo(int32_t n, int t, int T) { return (int32_t)((int64_t)n * t / T); }
+
+/* Partial sums, one per thread over its own block, are added in thread
+ * order: the same bits on every run with the same thread count (an OpenMP
+ * reduction clause combines the partials in an unspecified order). */
+#define ORC_MAX_THREADS 1024
+
 static double dot_omp(int32_t n, const double *a, const double *b)
 {
+    double part[ORC_MAX_THREADS];
+    int nt = 1;
+#pragma omp parallel num_threads(omp_get_max_threads() < ORC_MAX_THREADS ? omp_get_max_threads() : ORC_MAX_THREADS)
+    {
+        const int t = omp_get_thread_num(), T = omp_get_num_threads();
+        double s = 0.0;
+        for (int32_t i = block_lo(n, t, T); i < block_lo(n, t + 1, T); ++i) s += a[i] * b[i];
+        part[t] = s;
+        if (t == 0) nt = T;
+    }
     double s = 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : s)
-    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int t = 0; t < nt; ++t) s += part[t];
     return s;
 }
 
@@ -48,14 +66,23 @@ static double dot_omp(int32_t n, const double *a, const double *b)
 static double residual_omp(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                            const double *b, const double *x, double *r)
 {
-    double s2 = 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : s2)
-    for (int32_t i = 0; i < n; ++i) {
-        double s = b[i];
-        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s -= val[p] * x[col[p]];
-        r[i] = s;
-        s2 += s * s;
+    double part[ORC_MAX_THREADS];
+    int nt = 1;
+#pragma omp parallel num_threads(omp_get_max_threads() < ORC_MAX_THREADS ? omp_get_max_threads() : ORC_MAX_THREADS)
+    {
+        const int t = omp_get_thread_num(), T = omp_get_num_threads();
+        double s2 = 0.0;
+        for (int32_t i = block_lo(n, t, T); i < block_lo(n, t + 1, T); ++i) {
+            double s = b[i];
+            for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s -= val[p] * x[col[p]];
+            r[i] = s;
+            s2 += s * s;
+        }
+        part[t] = s2;
+        if (t == 0) nt = T;
     }
+    double s2 = 0.0;
+    for (int t = 0; t < nt; ++t) s2 += part[t];
     return sqrt(s2);
 }
 

@@ -123,6 +123,7 @@ extern "C" const char *spx_status_string(spx_status s)
     case SPX_ERR_NONFINITE: return "SPX_ERR_NONFINITE";
     case SPX_PENDING: return "SPX_PENDING";
     case SPX_CANCELLED: return "SPX_CANCELLED";
+    default: break;
     }
     return "SPX_UNKNOWN";
 }

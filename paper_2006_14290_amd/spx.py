@@ -249,7 +249,7 @@ def coo_from_host(n, row, col, val, dtype: int = F64, device="cuda") -> Matrix:
 
 def ell_from_host(n, K, ld, ecol, eval_, dtype: int = F64, device="cuda") -> Matrix:
     ecol = np.ascontiguousarray(ecol, np.int32)
-    return Matrix(ELL, dtype, int(n), int(n), int((ecol >= 0).sum()), ell_width=int(K), ell_ld=int(ld),
+    return Matrix(ELL, dtype, int(n), int(n), int((ecol != -1).sum()), ell_width=int(K), ell_ld=int(ld),
                   ell_col=torch.from_numpy(ecol).to(device), ell_val=_dev_vals(eval_, dtype, device))
 
 
@@ -257,14 +257,14 @@ def sellp_from_host(n, C, T, slice_sets, scol, sval, dtype: int = F64, device="c
     """Upload a host SELL-P matrix (slice size C, stride factor T)."""
     scol = np.ascontiguousarray(scol, np.int32)
     sets = np.ascontiguousarray(slice_sets, np.int32)
-    return Matrix(SELLP, dtype, int(n), int(n), int((scol >= 0).sum()), slice_size=int(C), stride_factor=int(T),
+    return Matrix(SELLP, dtype, int(n), int(n), int((scol != -1).sum()), slice_size=int(C), stride_factor=int(T),
                   slice_sets=torch.from_numpy(sets).to(device), slice_cols=int(sets[-1]),
                   ell_col=torch.from_numpy(scol).to(device), ell_val=_dev_vals(sval, dtype, device))
 
 
 def hyb_from_host(n, K, ld, ecol, eval_, row, col, val, dtype: int = F64, device="cuda") -> Matrix:
     ecol = np.ascontiguousarray(ecol, np.int32)
-    return Matrix(HYB, dtype, int(n), int(n), int((ecol >= 0).sum()) + int(len(row)), ell_width=int(K),
+    return Matrix(HYB, dtype, int(n), int(n), int((ecol != -1).sum()) + int(len(row)), ell_width=int(K),
                   ell_ld=int(ld), ell_col=torch.from_numpy(ecol).to(device), ell_val=_dev_vals(eval_, dtype, device),
                   coo_nnz=int(len(row)),
                   rowidx=torch.from_numpy(np.ascontiguousarray(row, np.int32)).to(device),
