@@ -125,6 +125,12 @@ def format_sweep(spx, torch, dev, A, x_h, args, tag, ell=True):
 
         if vt != spx.F16:
             variants["csr_lb"] = (no_hint, csr_bytes(n, nnz, sv, sx))
+        # column-blocked copy (for the random-column matrix only: a banded
+        # matrix already finds x in L2): its own bytes add 8 block row
+        # pointers and the 8 partial vectors (written and read)
+        if tag == "zipf":
+            variants["csr_cb"] = (lambda: spx.csr_colblock(spx.csr_analyse(spx.csr_from_host(A, vt, dev))),
+                                  csr_bytes(n, nnz, sv, sx) + 8 * (n + 1) * 4 + 2 * 8 * n * sx)
         for fmt, (make, vb) in variants.items():
             name = f"{tag}_{fmt}_{vname}"
             if vb > 0.8 * free:
@@ -585,19 +591,56 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False):
             worst = max(worst, info["relres_true"])
         total = last - start
         lat = np.array(lat) * 1e3
+        iters = np.array(iters)
+        kinds = np.array([k for k, _ in reqs])
+        fam = {}
+        for k in ("poisson", "spd"):
+            sel = kinds == k
+            if sel.any():
+                fam[k] = {"p50_ms": round(float(np.percentile(lat[sel], 50)), 2),
+                          "p99_ms": round(float(np.percentile(lat[sel], 99)), 2),
+                          "mean_iters": round(float(iters[sel].mean()), 1)}
+        # the slowest 1%: what they are (size, iterations)
+        slow = np.argsort(lat)[-max(1, nreq // 100):]
         return {"requests": nreq, "solves_per_s": round(nreq / total, 2), "wall_s": round(total, 3),
                 "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
                 "p99_over_p50": round(float(np.percentile(lat, 99) / np.percentile(lat, 50)), 2),
-                "mean_iters": round(float(np.mean(iters)), 1), "max_relres_true": worst}
+                "mean_iters": round(float(np.mean(iters)), 1), "max_relres_true": worst, "by_family": fam,
+                "slowest_1pct": {"n_median": int(np.median(n[slow])), "iters_median": int(np.median(iters[slow])),
+                                 "poisson_share": round(float(np.mean(kinds[slow] == "poisson")), 2)},
+                "_lat": lat, "_iters": iters}
 
     progress(f"serve: {nreq} requests built in {gen_s:.1f} s")
     burst = run(None, "burst")
+    burst_iters = burst.pop("_iters")
+    burst.pop("_lat")
     streams = {}
     for frac in fracs:
         rate = frac * burst["solves_per_s"]
         r = run(S.poisson_arrivals(nreq, rate, seed=seed), f"{frac:.1f}x")
+        r.pop("_iters")
+        r.pop("_lat")
         r["rate_per_s"] = round(rate, 2)
         streams[f"{frac:.1f}x"] = r
+    # unloaded latency of the heaviest requests (iterations x entries), each
+    # alone on the server: the floor the tail of a loaded stream sits on
+    heavy = np.argsort(burst_iters * (nnz + n))[-10:]
+    alone = []
+    for i in heavy:
+        A, b = systems[i]
+        t = srv.submit(A, b, tol=1e-8)
+        _, info = srv.wait(t, timeout_s=900)
+        alone.append(info["device_ms"])
+    light = np.argsort(burst_iters * (nnz + n))[nreq // 2 - 5:nreq // 2 + 5]
+    alone_mid = []
+    for i in light:
+        A, b = systems[i]
+        t = srv.submit(A, b, tol=1e-8)
+        _, info = srv.wait(t, timeout_s=900)
+        alone_mid.append(info["device_ms"])
+    unloaded = {"heaviest10_ms_median": round(float(np.median(alone)), 2),
+                "median_work10_ms_median": round(float(np.median(alone_mid)), 2),
+                "ratio": round(float(np.median(alone) / max(np.median(alone_mid), 1e-9)), 2)}
     st = srv.stats()
     srv.close()
     # sequential blocking float64 CG on a sample of the same requests
@@ -610,7 +653,7 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False):
         assert info["status"] == 0
     seq = len(sample) / (time.perf_counter() - t1)
     # the served throughput over the same first requests
-    out = {"burst": burst, "open_loop": streams, "sequential_cg_solves_per_s": round(seq, 2),
+    out = {"burst": burst, "open_loop": streams, "unloaded": unloaded, "sequential_cg_solves_per_s": round(seq, 2),
            "sequential_sample": len(sample), "served_over_sequential": round(burst["solves_per_s"] / seq, 2),
            "server": {k: st[k] for k in ("ticks", "pool_bytes_peak", "pool_bytes_total")}, "budget_gb": budget_gb,
            "mix": {"poisson": int(sum(k == "poisson" for k, _ in reqs)), "spd": int(sum(k == "spd" for k, _ in reqs)),

@@ -100,6 +100,9 @@ typedef struct spx_matrix {
     int32_t stride_factor;   /* SELLP */
     int32_t *slice_sets;     /* SELLP, [ceil(nrows/slice_size) + 1] */
     int64_t slice_cols;      /* SELLP, slice_sets[nslices] */
+    void *csr_cb;            /* optional column-blocked copy from spx_csr_colblock (NULL = none) */
+    int32_t csr_cb_tiles;    /* set by spx_csr_colblock: tiles of its largest column block */
+    int32_t csr_cb_live;     /* set by spx_csr_colblock: bit b set when column block b has entries */
 } spx_matrix;
 
 /* Name of a status code (static string). */
@@ -187,6 +190,32 @@ spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alph
  * Asynchronous. */
 int64_t spx_csr_analysis_bytes(const spx_matrix *A);
 spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream);
+
+/* Column-blocked CSR: for matrices whose column indices scatter over an x
+ * larger than one XCD's 4 MB L2 (the skewed, random-column matrices of the
+ * Section 4 test set), where the plain product's gathers of x miss L2 and
+ * pull whole lines from the Infinity Cache or HBM. The columns are cut into
+ * 8 equal ranges (ceil(ncols/8) columns each) and A is stored once more as 8
+ * CSR matrices A_b, the entries of A whose column lies in range b, in A's
+ * order. A product then runs the tiles of A_b on XCD b (work-group g goes to
+ * XCD g mod 8), so each XCD gathers only x's range b, which its L2 holds; each
+ * block writes its row sums to a partial vector and a second kernel forms
+ * y = alpha * (P_0 + ... + P_7) + beta * y in that order (a fixed order: the
+ * result is reproducible run to run; it differs from the plain product's by
+ * the order of each row's sum only). Costs beyond the plain product: 8 row
+ * pointers and 2 * 8 * nrows vector values (the partials) per product.
+ * spx_csr_colblock_bytes gives the device buffer size (about the matrix's own
+ * size plus 8 (nrows + 1) int32 and 8 nrows vector values);
+ * spx_csr_colblock fills `buf` (caller-owned device memory, 256-byte aligned,
+ * kept alive while A is used) from A's arrays, which must be in canonical
+ * form (spx_validate), and sets A->csr_cb, csr_cb_tiles and csr_cb_live.
+ * From then on spx_spmv and spx_csr_spmv on A use it (the solvers keep the
+ * plain CSR product). The buffer also holds the partials a product writes:
+ * products with one A on two streams at once would race. BLOCKING.
+ * Errors: SPX_ERR_ARG (not CSR, buffer too small or misaligned),
+ * SPX_ERR_FORMAT (the blocks' entries do not add up to nnz), SPX_ERR_HIP. */
+int64_t spx_csr_colblock_bytes(const spx_matrix *A);
+spx_status spx_csr_colblock(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ format conversion
  * Conversions between the formats of Section 1 and Sellp (Csr <-> Coo,

@@ -8,6 +8,7 @@
 #include "convert.hpp"
 #include "transpose.hpp"
 #include "spmv.hpp"
+#include "spmv_colblock.hpp"
 #include "spmv_csr.hpp"
 
 namespace spx {
@@ -71,13 +72,15 @@ spx_status check_matrix(const spx_matrix *A, const char *who)
 
 template <typename V, typename X>
 static spx_status spmv_typed(const spx_matrix &A, const void *x, void *y, double alpha, double beta,
-                             hipStream_t stream)
+                             hipStream_t stream, bool colblock)
 {
     const X *xx = static_cast<const X *>(x);
     X *yy = static_cast<X *>(y);
     const X a = static_cast<X>(alpha), b = static_cast<X>(beta);
     switch (A.fmt) {
-    case SPX_CSR: return csr_spmv_launch<V, X>(A, xx, yy, a, b, nullptr, nullptr, stream);
+    case SPX_CSR:
+        if (colblock && A.csr_cb != nullptr) return colblock_spmv_launch<V, X>(A, xx, yy, a, b, stream);
+        return csr_spmv_launch<V, X>(A, xx, yy, a, b, nullptr, nullptr, stream);
     case SPX_COO: return coo_spmv_launch<V, X>(A, xx, yy, a, b, stream);
     case SPX_ELL: return ell_spmv_launch<V, X>(A, xx, yy, a, b, stream);
     case SPX_HYB: return hyb_spmv_launch<V, X>(A, xx, yy, a, b, stream);
@@ -88,13 +91,14 @@ static spx_status spmv_typed(const spx_matrix &A, const void *x, void *y, double
     return SPX_ERR_ARG;
 }
 
-spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta, hipStream_t stream)
+spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta, hipStream_t stream,
+                         bool colblock)
 {
     if (A.nrows == 0) return SPX_OK;
     switch (A.val_type) {
-    case SPX_F64: return spmv_typed<double, double>(A, x, y, alpha, beta, stream);
-    case SPX_F32: return spmv_typed<float, float>(A, x, y, alpha, beta, stream);
-    case SPX_F16: return spmv_typed<_Float16, float>(A, x, y, alpha, beta, stream);
+    case SPX_F64: return spmv_typed<double, double>(A, x, y, alpha, beta, stream, colblock);
+    case SPX_F32: return spmv_typed<float, float>(A, x, y, alpha, beta, stream, colblock);
+    case SPX_F16: return spmv_typed<_Float16, float>(A, x, y, alpha, beta, stream, colblock);
     default: break;
     }
     set_error("spmv: bad val_type");
@@ -140,7 +144,7 @@ extern "C" spx_status spx_spmv(const spx_matrix *A, const void *x, void *y, doub
     SPX_REQUIRE(A->nrows == 0 || (y != nullptr && (A->ncols == 0 || x != nullptr)), SPX_ERR_ARG,
                 "spx_spmv: null vector");
     SPX_REQUIRE(x != y || A->nrows == 0, SPX_ERR_ARG, "spx_spmv: x aliases y");
-    return spmv_dispatch(*A, x, y, alpha, beta, stream);
+    return spmv_dispatch(*A, x, y, alpha, beta, stream, true);
 }
 
 extern "C" spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, double alpha, double beta,
@@ -152,7 +156,7 @@ extern "C" spx_status spx_csr_spmv(const spx_matrix *A, const void *x, void *y, 
     SPX_REQUIRE(A->nrows == 0 || (y != nullptr && (A->ncols == 0 || x != nullptr)), SPX_ERR_ARG,
                 "spx_csr_spmv: null vector");
     SPX_REQUIRE(x != y || A->nrows == 0, SPX_ERR_ARG, "spx_csr_spmv: x aliases y");
-    return spmv_dispatch(*A, x, y, alpha, beta, stream);
+    return spmv_dispatch(*A, x, y, alpha, beta, stream, true);
 }
 
 extern "C" int64_t spx_csr_analysis_bytes(const spx_matrix *A)
@@ -174,6 +178,20 @@ extern "C" spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hi
     if (A->nrows > 0) SPX_CHECK(csr_partition_launch(*A, static_cast<int32_t *>(buf), stream));
     A->csr_part = static_cast<const int32_t *>(buf);
     return SPX_OK;
+}
+
+extern "C" int64_t spx_csr_colblock_bytes(const spx_matrix *A)
+{
+    if (A == nullptr || A->fmt != SPX_CSR || A->nnz < 0 || A->nrows < 0) return 0;
+    return colblock_bytes(*A);
+}
+
+extern "C" spx_status spx_csr_colblock(spx_matrix *A, void *buf, size_t bytes, hipStream_t stream)
+{
+    clear_error();
+    SPX_CHECK(check_matrix(A, "spx_csr_colblock"));
+    SPX_REQUIRE(A->fmt == SPX_CSR, SPX_ERR_ARG, "spx_csr_colblock: matrix is not CSR");
+    return colblock_build(*A, buf, bytes, stream);
 }
 
 extern "C" spx_status spx_convert_plan(const spx_matrix *src, int32_t dst_fmt, int32_t ell_width, int64_t ell_ld,

@@ -49,28 +49,34 @@ __global__ __launch_bounds__(kPrimThreads) void segscan_kernel(const double *__r
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 // Streaming copy and read, the attainable-bandwidth references: a work-group
-// moves kStreamU * 256 consecutive 16-byte vectors, every thread issuing its
-// kStreamU non-temporal loads (coalesced across the wavefront) before any
-// store, so each CU keeps many loads in flight; one work-group per chunk.
-constexpr int kStreamU = 8;
-constexpr int64_t kStreamChunk = (int64_t)kStreamU * kPrimThreads;
+// moves U * 256 consecutive 16-byte vectors, every thread issuing its U
+// non-temporal loads (coalesced across the wavefront) before any store; one
+// work-group per chunk; stores are plain (non-temporal stores measured no
+// faster). Measured on MI355X (1 GiB copied, 2 GiB read): the
+// copy is fastest with one vector per thread and many small work-groups
+// (U = 1: 6.5 TB/s of reads plus writes; U = 4: 6.0; U = 8: 4.4), the read
+// with four (U = 4: 7.2 TB/s; 1, 2, 8 and 16: 6.8-7.1).
+constexpr int kCopyU = 1;
+constexpr int kReadU = 4;
+constexpr int64_t kCopyChunk = (int64_t)kCopyU * kPrimThreads;
+constexpr int64_t kReadChunk = (int64_t)kReadU * kPrimThreads;
 
 __global__ __launch_bounds__(kPrimThreads) void stream_copy_kernel(const dvec2 *__restrict__ src,
                                                                   dvec2 *__restrict__ dst, int64_t n2,
                                                                   const double *__restrict__ src1,
                                                                   double *__restrict__ dst1, int64_t n)
 {
-    const int64_t base = (int64_t)blockIdx.x * kStreamChunk + threadIdx.x;
-    dvec2 v[kStreamU];
+    const int64_t base = (int64_t)blockIdx.x * kCopyChunk + threadIdx.x;
+    dvec2 v[kCopyU];
 #pragma unroll
-    for (int u = 0; u < kStreamU; ++u) {
+    for (int u = 0; u < kCopyU; ++u) {
         const int64_t i = base + (int64_t)u * kPrimThreads;
         if (i < n2) v[u] = __builtin_nontemporal_load(src + i);
     }
 #pragma unroll
-    for (int u = 0; u < kStreamU; ++u) {
+    for (int u = 0; u < kCopyU; ++u) {
         const int64_t i = base + (int64_t)u * kPrimThreads;
-        if (i < n2) __builtin_nontemporal_store(v[u], dst + i);
+        if (i < n2) dst[i] = v[u];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) dst1[n - 1] = src1[n - 1];
 }
@@ -80,16 +86,16 @@ __global__ __launch_bounds__(kPrimThreads) void stream_copy_kernel(const dvec2 *
 __global__ __launch_bounds__(kPrimThreads) void stream_read_kernel(const dvec2 *__restrict__ src, int64_t n2,
                                                                   double *__restrict__ sink)
 {
-    const int64_t base = (int64_t)blockIdx.x * kStreamChunk + threadIdx.x;
-    dvec2 v[kStreamU];
+    const int64_t base = (int64_t)blockIdx.x * kReadChunk + threadIdx.x;
+    dvec2 v[kReadU];
 #pragma unroll
-    for (int u = 0; u < kStreamU; ++u) {
+    for (int u = 0; u < kReadU; ++u) {
         const int64_t i = base + (int64_t)u * kPrimThreads;
         v[u] = (i < n2) ? __builtin_nontemporal_load(src + i) : dvec2{0.0, 0.0};
     }
     double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < kStreamU; ++u) acc += v[u].x + v[u].y;
+    for (int u = 0; u < kReadU; ++u) acc += v[u].x + v[u].y;
     if (acc == -1.2345678e300) sink[0] = acc;
 }
 
@@ -161,7 +167,7 @@ extern "C" spx_status spx_stream_copy(const double *src, double *dst, int64_t n,
                 "spx_stream_copy: pointers must be 16-byte aligned");
     if (n == 0) return SPX_OK;
     const int64_t n2 = n / 2;
-    const int64_t grid = ceil_div(n2 > 0 ? n2 : 1, kStreamChunk);
+    const int64_t grid = ceil_div(n2 > 0 ? n2 : 1, kCopyChunk);
     SPX_REQUIRE(grid <= INT32_MAX, SPX_ERR_ARG, "spx_stream_copy: n too large");
     stream_copy_kernel<<<(unsigned)grid, kPrimThreads, 0, stream>>>(reinterpret_cast<const dvec2 *>(src),
                                                                    reinterpret_cast<dvec2 *>(dst), n2, src, dst, n);
@@ -177,7 +183,7 @@ extern "C" spx_status spx_stream_read(const double *src, int64_t n, double *sink
     SPX_REQUIRE(reinterpret_cast<uintptr_t>(src) % 16 == 0, SPX_ERR_ARG, "spx_stream_read: src must be 16-byte aligned");
     if (n == 0) return SPX_OK;
     const int64_t n2 = n / 2;
-    const int64_t grid = ceil_div(n2, kStreamChunk);
+    const int64_t grid = ceil_div(n2, kReadChunk);
     SPX_REQUIRE(grid <= INT32_MAX, SPX_ERR_ARG, "spx_stream_read: n too large");
     stream_read_kernel<<<(unsigned)grid, kPrimThreads, 0, stream>>>(reinterpret_cast<const dvec2 *>(src), n2, sink);
     SPX_LAUNCHED();

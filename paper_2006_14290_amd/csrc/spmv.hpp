@@ -9,8 +9,10 @@ namespace spx {
 spx_status check_matrix(const spx_matrix *A, const char *who);
 // Canonical-form checks of host CSR arrays (spx_validate_csr_host).
 spx_status validate_csr_host(int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *rowptr, const int32_t *col);
+// colblock: use A's column-blocked copy when it has one (the public product
+// entry points); the solvers call it with false (plain CSR product).
 spx_status spmv_dispatch(const spx_matrix &A, const void *x, void *y, double alpha, double beta,
-                         hipStream_t stream);
+                         hipStream_t stream, bool colblock = false);
 
 constexpr int kCooThreads = 256;
 constexpr int kCooTiles = 4;                      // 64-entry tiles per wavefront chunk

@@ -49,6 +49,7 @@ class MatrixDesc(ctypes.Structure):
         ("ell_ld", ctypes.c_int64), ("ell_col", ctypes.c_void_p), ("ell_val", ctypes.c_void_p),
         ("csr_part", ctypes.c_void_p), ("slice_size", ctypes.c_int32), ("stride_factor", ctypes.c_int32),
         ("slice_sets", ctypes.c_void_p), ("slice_cols", ctypes.c_int64),
+        ("csr_cb", ctypes.c_void_p), ("csr_cb_tiles", ctypes.c_int32), ("csr_cb_live", ctypes.c_int32),
     ]
 
 
@@ -72,6 +73,8 @@ _sig("spx_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_spmv", [_MP, _vp, _vp, _f64, _f64, _vp])
 _sig("spx_csr_analysis_bytes", [_MP], ctypes.c_int64)
 _sig("spx_csr_analyse", [_MP, _vp, ctypes.c_size_t, _vp])
+_sig("spx_csr_colblock_bytes", [_MP], ctypes.c_int64)
+_sig("spx_csr_colblock", [_MP, _vp, ctypes.c_size_t, _vp])
 _sig("spx_convert_plan", [_MP, _i32, _i32, _i64, _MP, ctypes.POINTER(ctypes.c_size_t), _vp])
 _sig("spx_convert", [_MP, _MP, _vp, ctypes.c_size_t, _vp])
 _sig("spx_cast_values", [_MP, _MP, _vp])
@@ -198,6 +201,9 @@ class Matrix:
     stride_factor: int = 0
     slice_sets: Optional[torch.Tensor] = None
     slice_cols: int = 0
+    csr_cb: Optional[torch.Tensor] = None
+    csr_cb_tiles: int = 0
+    csr_cb_live: int = 0
     _desc: MatrixDesc = field(default=None, repr=False)
 
     def desc(self) -> MatrixDesc:
@@ -210,6 +216,7 @@ class Matrix:
         d.csr_part = _ptr(self.csr_part)
         d.slice_size, d.stride_factor, d.slice_cols = self.slice_size, self.stride_factor, self.slice_cols
         d.slice_sets = _ptr(self.slice_sets)
+        d.csr_cb, d.csr_cb_tiles, d.csr_cb_live = _ptr(self.csr_cb), self.csr_cb_tiles, self.csr_cb_live
         self._desc = d
         return d
 
@@ -280,6 +287,18 @@ def csr_analyse(A: Matrix, stream=None) -> Matrix:
     buf = torch.empty(max(1, nbytes // 4), dtype=torch.int32, device=A.rowptr.device)
     check(_lib.spx_csr_analyse(ctypes.byref(d), _ptr(buf), nbytes, _stream(stream)), "spx_csr_analyse")
     A.csr_part = buf
+    return A
+
+
+def csr_colblock(A: Matrix, stream=None) -> Matrix:
+    """Build A's column-blocked copy (8 column ranges, one per XCD; blocking).
+    Later products on A through spmv/csr_spmv use it."""
+    d = A.desc()
+    nbytes = int(_lib.spx_csr_colblock_bytes(ctypes.byref(d)))
+    device = A.rowptr.device if A.rowptr is not None else torch.device("cuda", torch.cuda.current_device())
+    buf = torch.empty(max(256, nbytes), dtype=torch.uint8, device=device)
+    check(_lib.spx_csr_colblock(ctypes.byref(d), _ptr(buf), buf.numel(), _stream(stream)), "spx_csr_colblock")
+    A.csr_cb, A.csr_cb_tiles, A.csr_cb_live = buf, d.csr_cb_tiles, d.csr_cb_live
     return A
 
 
