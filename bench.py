@@ -30,7 +30,6 @@ import argparse
 import json
 import os
 import sys
-import threading
 import time
 
 import numpy as np
@@ -362,12 +361,13 @@ def bench_solvers(spx, S, torch, dev, cpu=True):
     """Krylov solvers at full size: CG+Jacobi on the anisotropic 7-point 128^3
     grid, BiCGSTAB and GMRES(30) + Jacobi on the upwind convection-diffusion
     128^3 grid, and mixed-precision IR (float32 / binary16 values) against
-    plain float64 CG on the 7-point 192^3 grid; all to 1e-10. The float64
-    oracle (all-core CG) solves the 192^3 system on the host meanwhile; the
-    IR and CG solutions are compared with its solution."""
+    plain float64 CG on the 7-point 192^3 grid; all to 1e-10. After the GPU
+    timings (never beside them: the solvers' host-side loops must not compete
+    with the oracle's threads for the CPU), the float64 oracle (all-core CG)
+    solves the 192^3 system on the host and the IR and CG solutions are
+    compared with its solution."""
     out = {}
     nrm = torch.linalg.vector_norm
-    # the host oracle's float64 CG on the 192^3 system runs while the GPU works
     P192 = S.poisson3d_7pt(192)
     xstar192 = S.uniform_vector(P192.n, seed=0, purpose="xstar")
     oracle = {}
@@ -379,10 +379,6 @@ def bench_solvers(spx, S, torch, dev, cpu=True):
         t = time.perf_counter()
         x, info = O.cg_omp(P192, b, tol=1e-10, maxit=5000)
         oracle.update(x=x, info=info, s=time.perf_counter() - t, threads=O.omp_threads())
-
-    th = threading.Thread(target=run_oracle) if cpu else None
-    if th:
-        th.start()
 
     progress("solvers: CG + Jacobi, anisotropic 128^3")
     A = S.poisson3d_7pt(128, 1, 1, 0.01)
@@ -481,9 +477,9 @@ def bench_solvers(spx, S, torch, dev, cpu=True):
     x64h = x64.cpu().numpy()
     del A64, E64
     torch.cuda.empty_cache()
-    if th:
-        progress("solvers: waiting for the host oracle's 192^3 CG")
-        th.join()
+    if cpu:
+        progress("solvers: the host oracle's 192^3 CG (all cores)")
+        run_oracle()
         xo = oracle["x"]
         no = np.linalg.norm(xo)
         out["oracle_fp64_cg_poisson192"] = {

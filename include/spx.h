@@ -456,6 +456,13 @@ typedef struct {
     int32_t debug_fail_tick; /* testing only: k > 0 makes the worker stop at its
                                 k-th tick as if a HIP call had failed (no device
                                 fault is involved); 0 = off                      */
+    int32_t reserved0;
+    int64_t inflight_bytes;  /* bound on the work admitted at once: the summed
+                                bytes one iteration of every resident system
+                                moves (CSR product + vector passes); a request
+                                that would pass it waits in FIFO order until
+                                enough retires (one is always admitted when
+                                nothing is resident). <= 0 = no bound          */
 } spx_server_config;
 
 typedef struct {

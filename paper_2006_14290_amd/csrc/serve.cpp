@@ -130,9 +130,18 @@ struct Pending {
     bool wide;
 };
 
+// Bytes one iteration of a request moves: the CSR product plus about nine
+// vector passes (CG); a BiCGSTAB step has two products and twice the passes.
+int64_t iter_work(const spx_request &r)
+{
+    const int64_t w = r.nnz * 12 + (int64_t)r.n * (4 + 9 * 8);
+    return r.solver == SPX_SOLVER_BICGSTAB ? 2 * w : w;
+}
+
 struct Active {
     uint64_t ticket = 0;
     size_t off = 0, bytes = 0;
+    int64_t work = 0;  // iter_work of the request (counted in spx_server::inflight)
     double *x_dev = nullptr;
     double *x_out = nullptr;
     int64_t n = 0, nnz = 0;
@@ -203,6 +212,8 @@ struct spx_server {
     uint64_t next_ticket = 1;
     spx_server_stats stats{};
     std::string fatal;
+    int64_t inflight = 0;  // summed iter_work of resident systems (under mu)
+    int64_t inflight_cap = 0;  // cfg.inflight_bytes (<= 0: no bound)
 };
 
 namespace {
@@ -242,6 +253,9 @@ int admit(spx_server &S)
         std::lock_guard<std::mutex> lk(S.mu);
         int scanned = 0;
         for (auto it = S.queue.begin(); it != S.queue.end() && scanned < kBackfill;) {
+            // work bound: strict FIFO (no request passes one held back by it)
+            const int64_t w = iter_work(it->req);
+            if (S.inflight_cap > 0 && S.inflight > 0 && S.inflight + w > S.inflight_cap) break;
             int free_slot = -1;
             for (int i = 0; i < (int)S.active.size(); ++i)
                 if (!S.active[i].live) {
@@ -257,6 +271,8 @@ int admit(spx_server &S)
                 Active &a = S.active[free_slot];
                 a.off = off;
                 a.bytes = it->bytes;
+                a.work = w;
+                S.inflight += w;
                 a.ticket = p.ticket;
                 a.cancel.store(false);
                 a.live = true;
@@ -478,6 +494,7 @@ void retire(spx_server &S)
         const spx_status st = a.cancel.load() ? SPX_CANCELLED : slot_status_to_spx(solver_status);
         info.status = st;
         S.pool.release(a.off, a.bytes);
+        S.inflight -= a.work;
         a.live = false;
         finish_locked(S, a.ticket, st, info);
     }
@@ -497,6 +514,7 @@ void fail_all(spx_server &S, spx_status st)
         if (a.live) {
             a.live = false;
             S.pool.release(a.off, a.bytes);
+            S.inflight -= a.work;
             finish_locked(S, a.ticket, st, info);
         }
     S.cv_done.notify_all();
@@ -671,6 +689,7 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     auto *S = new spx_server();
     S->cfg = *cfg;
     S->device = cfg->device;
+    S->inflight_cap = cfg->inflight_bytes;
     const size_t ms = (size_t)cfg->max_slots;
     // every wide row costs at least 44 pool bytes (row pointer + five vectors)
     S->vb_cap = (int64_t)(cfg->hbm_budget_bytes / (44 * (size_t)kWideRows)) + (int64_t)ms + 1;

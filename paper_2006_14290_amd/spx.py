@@ -119,7 +119,7 @@ class BatchSystem(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("iters_per_tick", ctypes.c_int32), ("tick_us", ctypes.c_int32), ("wide_min_rows", ctypes.c_int32),
-                ("debug_fail_tick", ctypes.c_int32)]
+                ("debug_fail_tick", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("inflight_bytes", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -539,9 +539,10 @@ class Server:
     """Continuous-batching CG server (host requests, results copied back)."""
 
     def __init__(self, device: int = 0, max_slots: int = 1024, hbm_budget_bytes: int = 32 << 30,
-                 iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0, debug_fail_tick: int = 0):
+                 iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0, debug_fail_tick: int = 0,
+                 inflight_bytes: int = 0):
         cfg = ServerConfig(device, max_slots, hbm_budget_bytes, iters_per_tick, tick_us, wide_min_rows,
-                           debug_fail_tick)
+                           debug_fail_tick, 0, inflight_bytes)
         h = ctypes.c_void_p()
         check(_lib.spx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "spx_server_create")
         self._h = h

@@ -101,6 +101,30 @@ def test_server_mix_alone_bitwise_and_stats():
         srv.close()
 
 
+def test_server_inflight_bound_fifo_same_bits():
+    """A work bound smaller than any request: one system resident at a time,
+    admitted in submission order (the queue drains FIFO), each result
+    bitwise its solo solve."""
+    systems = [_system(*m) for m in MIX[:6]]
+    srv = spx.Server(max_slots=8, hbm_budget_bytes=256 << 20, inflight_bytes=1)
+    try:
+        tickets = [srv.submit(A, b, tol=1e-8) for A, b in systems]
+        assert srv.stats()["queued"] >= 1
+        done_ms = []
+        for t, (A, b) in zip(tickets, systems):
+            x, info = srv.wait(t, timeout_s=120)
+            assert info["status"] == spx.OK, info
+            xa, ia = _alone(A, b, 1e-8)
+            np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
+            done_ms.append(info["device_ms"])
+        # submitted together, served one after another: completion times grow
+        assert all(b > a for a, b in zip(done_ms, done_ms[1:])), done_ms
+        st = srv.stats()
+        assert st["active"] == 0 and st["queued"] == 0
+    finally:
+        srv.close()
+
+
 def test_server_one_iteration_per_tick_same_bits():
     A, b = _system("poisson", 40, 11)
     srv = spx.Server(max_slots=2, hbm_budget_bytes=64 << 20, iters_per_tick=1)
