@@ -697,6 +697,8 @@ def main():
     ap.add_argument("--matrix", choices=("27pt", "zipf"), default="27pt",
                     help="matrix of the headline CSR product (27-point stencil or the Zipf(1.5) rows)")
     ap.add_argument("--quick", action="store_true", help="headline product only (no sweep, solvers, serving)")
+    ap.add_argument("--colblock", action="store_true",
+                    help="headline product through the column-blocked copy (spx_csr_colblock); GB/s stays CSR bytes")
     ap.add_argument("--no-sweep", action="store_true", help="skip the format sweep and conversions")
     ap.add_argument("--no-zipf", action="store_true", help="skip the Zipf(1.5) formats of the sweep")
     ap.add_argument("--zipf-ell", action="store_true", help="also time the 1e10-slot Zipf ELL (120 GB)")
@@ -742,6 +744,10 @@ def main():
     R = max(2, int(np.ceil((1 << 30) / fp)))
     mats = [spx.csr_analyse(spx.csr_from_host(A, spx.F64, dev)) for _ in range(R)]
     kname = csr_kernel_name(mats[0])
+    if args.colblock:
+        mats = [spx.csr_colblock(M) for M in mats]
+        kname = "cb_spmv_kernel (column-blocked, + cb_finish_kernel)"
+        mdesc += ", column-blocked copy"
     xs = [torch.from_numpy(x_h).to(dev) for _ in range(R)]
     ys = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(R)]
 
@@ -810,7 +816,7 @@ def main():
             cpu["solver_cg_poisson192"] = {
                 "value": o["s"], "unit": "s to 1e-10", "cores": o["threads"], "kind": "oracle",
                 "iters": o["iters"], "gpu_fp64_cg_s": round(solvers["cg_fp64_poisson192"]["ms"] / 1e3, 4),
-                "sample": "one oracle CG solve (all-core variant) of the 7-point 192^3 system, run beside the GPU"}
+                "sample": "one oracle CG solve (all-core variant) of the 7-point 192^3 system, run on the host after the GPU timings"}
         if cg_small is not None:
             # the oracle's CG on the 64x64 Poisson system (unpreconditioned, 1e-10), 1 thread
             P = S.poisson2d(64)
@@ -859,7 +865,7 @@ def main():
         "gen_s": round(gen_s, 1),
         "wall_s": round(time.time() - T0, 1),
     }
-    traffic = profile_traffic(f"csr_spmv_f64_{mtag}", b)
+    traffic = profile_traffic(f"csr_spmv_f64_{mtag}" + ("_colblock" if args.colblock else ""), b)
     if traffic is not None:
         line["roofline"]["traffic"] = traffic
         line["roofline"]["traffic_over_algorithmic"] = round(traffic / b, 4)
