@@ -71,6 +71,36 @@ def test_sellp_spmv_parity(mi, dtype, C, T):
         assert_spmv_low(y, yref, absax, np.diff(A.rowptr))
 
 
+@pytest.mark.parametrize("T", [1, 2])
+def test_sellp_zipf_256_row_slices(T):
+    """The largest slice size (256 rows, the kernel's whole work-group) on
+    Zipf(1.5) rows: a slice pads to its longest row (up to 10,000 entries),
+    so a smaller matrix (n = 5,000; about 5e7 slots) stands in for the
+    20,000-row case that the parametrised tests skip. Conversion bit-exact
+    both ways, product per row against the oracle in f64 and f32."""
+    A = S.zipf_matrix(5000, seed=9)
+    print(f"case zipf_5e3 C=256 T={T}", flush=True)
+    P = O.csr_to_sellp(A, C=256, T=T)
+    Ad = spx.csr_from_host(A)
+    Pd = spx.convert(Ad, spx.SELLP, slice_size=256, stride_factor=T)
+    assert Pd.slice_cols == int(P.slice_sets[-1])
+    np.testing.assert_array_equal(host(Pd.slice_sets), P.slice_sets)
+    np.testing.assert_array_equal(host(Pd.ell_col), P.col)
+    np.testing.assert_array_equal(_bits(host(Pd.ell_val)), _bits(P.val))
+    B = spx.convert(Pd, spx.CSR)
+    np.testing.assert_array_equal(host(B.rowptr), A.rowptr)
+    np.testing.assert_array_equal(host(B.colidx), A.col)
+    np.testing.assert_array_equal(_bits(host(B.vals)), _bits(np.asarray(A.val)))
+    x = S.uniform_vector(A.n, seed=12)
+    yref, absax = O.csr_spmv_dot2(A, x)
+    assert_spmv_f64(host(spx.spmv(Pd, dev(x))), yref, absax)
+    P32 = spx.sellp_from_host(A.n, 256, T, P.slice_sets, P.col, P.val, spx.F32)
+    xr = _round(x, "f32")
+    Ar = S.CSR(A.n, A.rowptr, A.col, _round(A.val, "f32"))
+    yref32, absax32 = O.csr_spmv_dot2(Ar, xr)
+    assert_spmv_low(host(spx.spmv(P32, dev(xr, P32.vec_dtype))), yref32, absax32, np.diff(A.rowptr))
+
+
 def test_sellp_bitwise_reproducible_and_matches_convert():
     A = S.zipf_matrix(30000, seed=4)
     Ad = spx.csr_from_host(A)
