@@ -210,7 +210,9 @@ spx_status spx_csr_analyse(spx_matrix *A, void *buf, size_t bytes, hipStream_t s
  * kept alive while A is used) from A's arrays, which must be in canonical
  * form (spx_validate), and sets A->csr_cb, csr_cb_tiles and csr_cb_live.
  * From then on spx_spmv and spx_csr_spmv on A use it (the solvers keep the
- * plain CSR product). The buffer also holds the partials a product writes:
+ * plain CSR product). The copy holds A's values as they were when it was
+ * built: after changing A's values or pattern, build it again (or clear
+ * A->csr_cb to return to the plain product). The buffer also holds the partials a product writes:
  * products with one A on two streams at once would race. BLOCKING.
  * Errors: SPX_ERR_ARG (not CSR, buffer too small or misaligned),
  * SPX_ERR_FORMAT (the blocks' entries do not add up to nnz), SPX_ERR_HIP. */
