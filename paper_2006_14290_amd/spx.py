@@ -231,10 +231,21 @@ class Matrix:
 
 
 def _dev_vals(vals: np.ndarray, dtype: int, device) -> torch.Tensor:
-    """Host float64 values stored as dtype on the device (round to nearest even)."""
-    v = np.ascontiguousarray(vals, dtype=np.float64)
-    np_t = {F64: np.float64, F32: np.float32, F16: np.float16}[dtype]
-    return torch.from_numpy(v.astype(np_t)).to(device)
+    """Host float64 values stored as dtype on the device: uploaded in float64
+    and rounded (nearest even) on the device by spx_cast_values."""
+    v = torch.from_numpy(np.ascontiguousarray(vals, dtype=np.float64)).to(device)
+    if dtype == F64 or v.numel() == 0:
+        return v if dtype == F64 else v.to(_VAL_DTYPE[dtype])
+    out = torch.empty(v.numel(), dtype=_VAL_DTYPE[dtype], device=v.device)
+    # a one-row CSR descriptor over the value array: the cast reads only the
+    # values (the column-index pointer is a placeholder it never follows)
+    rp = torch.tensor([0, v.numel()], dtype=torch.int32, device=v.device)
+    src = Matrix(CSR, F64, 1, 1, v.numel(), rowptr=rp, colidx=rp, vals=v)
+    dst = Matrix(CSR, dtype, 1, 1, v.numel(), rowptr=rp, colidx=rp, vals=out)
+    st = _lib.spx_cast_values(ctypes.byref(src.desc()), ctypes.byref(dst.desc()), _stream(None))
+    if st not in (OK, ERR_RANGE):  # ERR_RANGE: finite values beyond binary16, written as infinities
+        check(st, "spx_cast_values")
+    return out
 
 
 def csr_from_host(A, dtype: int = F64, device="cuda") -> Matrix:
