@@ -150,7 +150,12 @@ def test_server_budget_queueing_and_cancel():
         with pytest.raises(spx.SpxError, match="BUDGET"):
             huge = S.poisson2d(300)
             srv.submit(huge, np.ones(huge.n))
-        tickets = [srv.submit(big, bbig, tol=1e-8) for _ in range(4)]
+        # a blocker with an unreachable tolerance holds the budget until it is
+        # cancelled, so the requests behind it stay queued however fast the
+        # others would converge
+        blocker = srv.submit(big, bbig, tol=1e-300)
+        tickets = [srv.submit(big, bbig, tol=1e-8) for _ in range(3)]
+        assert srv.stats()["queued"] >= 3
         # an unreachable tolerance keeps the victim running (or queued) until
         # the cancel arrives, so the cancel must win
         victim = srv.submit(small, bsmall, tol=1e-300)
@@ -160,13 +165,16 @@ def test_server_budget_queueing_and_cancel():
         assert info["status"] == spx.CANCELLED
         # cancelled while still queued behind the budget
         queued = srv.submit(big, bbig, tol=1e-8)
-        assert srv.stats()["queued"] >= 1
+        assert srv.stats()["queued"] >= 4
         srv.cancel(queued)
         x, info = srv.wait(queued, timeout_s=60)
         assert info["status"] == spx.CANCELLED
-        saw_queue = False
+        p = srv.poll(blocker)
+        assert p[1]["status"] == spx.PENDING and srv.stats()["queued"] >= 3
+        srv.cancel(blocker)
+        x, info = srv.wait(blocker, timeout_s=60)
+        assert info["status"] == spx.CANCELLED
         for t in tickets:
-            saw_queue |= srv.stats()["queued"] > 0
             x, info = srv.wait(t, timeout_s=120)
             assert info["status"] == spx.OK
             assert _relres(big, bbig, x) <= 1e-8
