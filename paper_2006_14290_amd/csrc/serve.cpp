@@ -16,9 +16,7 @@
 // small-system kernel, then the general one) advances every system below
 // the wide threshold by its iteration budget; the wide graph (kWideIters iterations
 // of the three wide phases, the state alternating between two buffers)
-// advances every large system, launched as many times as fits the tick (fewer
-// when every listed system is predicted to converge sooner, from its r.r
-// decrease over the last tick). Between ticks the worker reads the state back,
+// advances every large system, launched as many times as fits the tick. Between ticks the worker reads the state back,
 // copies the solutions of finished systems to the callers' buffers, frees
 // their memory and slots, and admits more: new requests join within a few
 // milliseconds (continuous batching). Matrices and Krylov state stay resident
@@ -26,7 +24,6 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
-#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -158,10 +155,6 @@ struct Active {
     bool staged = false;  // descriptor waiting in spx_server::staged / wstaged
     bool wide = false;
     bool in_map = false;  // listed in the wide map uploaded for the current tick
-    // wide systems: iteration count and r.r read back after the last two
-    // ticks (to predict how many more iterations the system needs; -1 = none)
-    int32_t prev_iters = -1, last_iters = -1;
-    double prev_rr = 0.0, last_rr = 0.0;
 };
 
 struct Result {
@@ -328,7 +321,6 @@ int admit(spx_server &S)
         (void)hipMemsetAsync(x, 0, (size_t)n * 8, S.s_copy);
         a.wide = p.wide;
         a.in_map = false;
-        a.prev_iters = a.last_iters = -1;
         if (p.wide) {
             WideSlot &w = S.wstaged[si];
             std::memset(&w, 0, sizeof(w));
@@ -534,50 +526,6 @@ void set_fatal(spx_server &S, const char *what)
     S.fatal = what;
 }
 
-// Graph launches (kWideIters wide iterations each) the listed wide systems
-// still need this tick, predicted from each one's r.r decrease between the
-// read-backs of the last two ticks: once every listed system is expected to
-// converge within fewer launches than the tick would run, the tick runs only
-// those (with a margin), so it ends soon after the last of them instead of
-// launching work for finished systems. A system without a prediction (new,
-// restarted, checking its true residual, or not decreasing) keeps the full
-// count. A wrong prediction costs one more tick, never correctness.
-int wide_launches_needed(const spx_server &S)
-{
-    double need = 0.0;
-    for (int i = 0; i < (int)S.active.size(); ++i) {
-        const Active &a = S.active[i];
-        if (!a.in_map) continue;
-        if (a.prev_iters < 0 || a.last_iters <= a.prev_iters || !(a.last_rr > 0.0) || !(a.prev_rr > a.last_rr))
-            return 64;
-        const double per_iter = std::log(a.last_rr / a.prev_rr) / (double)(a.last_iters - a.prev_iters);  // < 0
-        const double target = std::log(S.wslots_host[i].tol2 * S.wstate_host[i].bb / a.last_rr);  // < 0 while running
-        const double left = target >= 0.0 ? 0.0 : target / per_iter;
-        if (!(left < 64.0 * kWideIters)) return 64;  // far off, or no finite target (tol2 = 0)
-        need = std::max(need, 1.25 * left + 2.0 * kWideIters);  // margin, plus the true-residual check
-    }
-    return (int)std::max(1.0, std::ceil(need / kWideIters));
-}
-
-// After a tick's read-back: shift each listed system's (iterations, r.r)
-// history by one.
-void record_wide_progress(spx_server &S)
-{
-    for (int i = 0; i < (int)S.active.size(); ++i) {
-        Active &a = S.active[i];
-        if (!a.in_map) continue;
-        const WideState &w = S.wstate_host[i];
-        if (w.mode == kWideRun) {
-            a.prev_iters = a.last_iters;
-            a.prev_rr = a.last_rr;
-            a.last_iters = w.iters;
-            a.last_rr = w.rr;
-        } else {
-            a.prev_iters = a.last_iters = -1;  // done, checking or restarting: no rate
-        }
-    }
-}
-
 void worker_main(spx_server *Sp)
 {
     spx_server &S = *Sp;
@@ -620,13 +568,11 @@ void worker_main(spx_server *Sp)
             if (e == hipSuccess) e = hipGraphLaunch(nwide > 0 ? S.tick_half : S.tick, S.s_compute);
             if (e == hipSuccess) e = hipMemcpyAsync(S.slots_host, S.slots_dev, tb, hipMemcpyDeviceToHost, S.s_compute);
         }
-        int launches = 0;
         if (nwide > 0 && e == hipSuccess) {
             const int32_t tot = std::max(S.wmap_host->total_vb, S.wmap_host->total_ta);
             const int gi = tot <= kWideGrids[0] ? 0 : (tot <= kWideGrids[1] ? 1 : 2);
-            launches = std::min(S.wide_launches, wide_launches_needed(S));
             e = hipEventRecord(S.ev_w0, S.s_wide);
-            for (int l = 0; l < launches && e == hipSuccess; ++l) e = hipGraphLaunch(S.wide_tick[gi], S.s_wide);
+            for (int l = 0; l < S.wide_launches && e == hipSuccess; ++l) e = hipGraphLaunch(S.wide_tick[gi], S.s_wide);
             if (e == hipSuccess) e = hipEventRecord(S.ev_w1, S.s_wide);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(S.wstate_host, S.wstate_dev, sizeof(WideState) * S.active.size(),
@@ -646,12 +592,11 @@ void worker_main(spx_server *Sp)
         if (nwide > 0) {
             // size the next tick's wide work to about tick_us
             float ms = 0.f;
-            if (launches > 0 && hipEventElapsedTime(&ms, S.ev_w0, S.ev_w1) == hipSuccess && ms > 0.f) {
+            if (hipEventElapsedTime(&ms, S.ev_w0, S.ev_w1) == hipSuccess && ms > 0.f) {
                 const double tick_ms = (S.cfg.tick_us > 0 ? S.cfg.tick_us : 2000) * 1e-3;
-                const double per = ms / launches;
+                const double per = ms / S.wide_launches;
                 S.wide_launches = (int)std::max(1.0, std::min(64.0, tick_ms / per));
             }
-            record_wide_progress(S);
         }
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
             set_fatal(S, "admission copy failed");
