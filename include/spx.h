@@ -382,7 +382,7 @@ spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const dou
  *    work-groups take systems from an atomic counter and run all of a
  *    system's CG iterations by themselves (product, updates and fixed-order
  *    reductions inside the group);
- *  - wide systems (n >= 16384 by default): several work-groups per system,
+ *  - wide systems (n > 4096 by default): several work-groups per system,
  *    one CG iteration as three grid-wide launches over every wide system at
  *    once, each system cut into fixed blocks of 1024 rows whose partial sums
  *    are added in a fixed order.
@@ -392,7 +392,7 @@ typedef enum { SPX_BATCH_AUTO = 0, SPX_BATCH_ONE_GROUP = 1, SPX_BATCH_WIDE = 2 }
 
 typedef struct {
     int32_t n;              /* rows (square system)                        */
-    int32_t path;           /* spx_batch_path (AUTO: wide iff n >= 16384)  */
+    int32_t path;           /* spx_batch_path (AUTO: wide iff n > 4096)    */
     int64_t nnz;
     const int32_t *rowptr;  /* DEVICE CSR, float64 values                  */
     const int32_t *colidx;
@@ -454,7 +454,7 @@ typedef struct {
     int32_t iters_per_tick;  /* CG iterations per system per tick (0 = adaptive) */
     int32_t tick_us;         /* adaptive budget: target tick length (0 = 2000)  */
     int32_t wide_min_rows;   /* systems with n >= this take the wide path
-                                (0 = 16384, as SPX_BATCH_AUTO; < 0 = never)      */
+                                (0 = 4097, as SPX_BATCH_AUTO; < 0 = never)       */
     int32_t debug_fail_tick; /* testing only: k > 0 makes the worker stop at its
                                 k-th tick as if a HIP call had failed (no device
                                 fault is involved); 0 = off                      */

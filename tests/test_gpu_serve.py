@@ -55,6 +55,22 @@ def test_cg_batch_mix_and_alone_bitwise():
         np.testing.assert_array_equal(xa.view(np.uint64), x.view(np.uint64))
 
 
+def test_cg_batch_one_group_mix_alone_bitwise():
+    # the one-work-group kernel for systems above the small-system range, asked
+    # for explicitly (by default those systems take the wide path)
+    systems = [(A, b) for A, b in (_system(*m) for m in MIX) if A.n > 4096]
+    assert len(systems) == 4
+    mats = [spx.csr_from_host(A) for A, _ in systems]
+    xs, infos = spx.cg_batch(mats, [dev(b) for _, b in systems], tol=1e-8, path=spx.BATCH_ONE_GROUP)
+    for (A, b), Ad, x, info in zip(systems, mats, xs, infos):
+        assert info["status"] == spx.OK, info
+        x = host(x)
+        assert _relres(A, b, x) <= 1e-8
+        xa, ia = spx.cg_batch([Ad], [dev(b)], tol=1e-8, path=spx.BATCH_ONE_GROUP)
+        assert ia[0]["iters"] == info["iters"]
+        np.testing.assert_array_equal(host(xa[0]).view(np.uint64), x.view(np.uint64))
+
+
 def test_cg_batch_matches_oracle_iterations():
     A, b = _system("poisson", 64, 0)
     x, info = _alone(A, b, 1e-10)
