@@ -383,9 +383,11 @@ spx_status spx_ir_solve(const spx_matrix *A64, const spx_matrix *Alow, const dou
  *    system's CG iterations by themselves (product, updates and fixed-order
  *    reductions inside the group);
  *  - wide systems (n > 4096 by default): several work-groups per system,
- *    one CG iteration as three grid-wide launches over every wide system at
- *    once, each system cut into fixed blocks of 1024 rows whose partial sums
- *    are added in a fixed order.
+ *    one CG step as two grid-wide launches over every wide system at once
+ *    (the single-reduction CG of Chronopoulos and Gear: the product w = A r
+ *    with the partials of r.w, then every vector update with the partials
+ *    of r.r), each system cut into fixed blocks of 1024 rows whose partial
+ *    sums are added in a fixed order.
  * Neither path lets one system's arithmetic depend on another's, so a
  * system's iterates are bitwise the same alone or in any batch or mix. */
 typedef enum { SPX_BATCH_AUTO = 0, SPX_BATCH_ONE_GROUP = 1, SPX_BATCH_WIDE = 2 } spx_batch_path;

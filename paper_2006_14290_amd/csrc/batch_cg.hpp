@@ -68,38 +68,45 @@ inline int32_t narrow_sub_for(int64_t n, int64_t nnz)
 // blocks of all wide systems (vb_slot maps a virtual block to its system).
 // A system's partition, partial sums and their fixed summation order depend
 // only on its own n, so its iterates are bitwise the same alone or in any mix.
-constexpr int kWideThreads = 256;  // vector and commit phases
-constexpr int kWideRows = 1024;    // rows per virtual block of the vector phases
+constexpr int kWideThreads = 256;  // vector phase
+constexpr int kWideRows = 1024;    // rows per virtual block of the vector phase
 
 enum WideMode : int32_t {
-    kWideInit = 0,   // r = b (x0 = 0), p = r, bb = ||b||^2
-    kWideRun = 1,    // one CG iteration per phase sequence
+    kWideInit = 0,   // r = b (x0 = 0)
+    kWideRun = 1,    // one CG step per product + vector phase pair
     kWideCheck = 2,  // true residual b - A x
     kWideDone = 3,
 };
 
 // Written by the host when the system is admitted. The product phase runs
 // the load-balanced CSR tile kernel over the system's ntiles tiles (its
-// partition in csr_part), one partial p.q per tile in part_a; the vector
-// phases work on nvb blocks of kWideRows rows, one partial each in part.
+// partition in csr_part), one partial r.w per tile in part_a; the vector
+// phase works on nvb blocks of kWideRows rows, one partial r.r each, into
+// one half of part while it reads the other half (the halves alternate).
 struct WideSlot {
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
     const double *b;
-    double *x, *r, *p, *q;
-    double *part;             // nvb partial sums of the vector phase
-    double *part_a;           // ntiles partial sums of the product phase
-    const int32_t *csr_part;  // tile partition of the product
+    double *x, *r, *p, *w, *s;  // w = A r, s = A p
+    double *part;               // 2 * nvb partial sums of the vector phase
+    double *part_a;             // ntiles partial sums of the product phase
+    const int32_t *csr_part;    // tile partition of the product
     int64_t nnz;
     int32_t n, nvb, ntiles, maxit;
     double tol2;
 };
 
-// Written by the device (the commit phase) and once at admission.
+// Written by the device (the vector phase's commit) and once at admission
+// (zero but mode = kWideInit).
 struct WideState {
     int32_t mode, status, iters, spmv;  // status: SlotStatus
-    double rho, bb, rr, relres_true;
+    double rho, bb, rr, relres_true;    // rho: r.r of the last step's residual
+    double alpha;                       // the last step length
+    int32_t restart;  // 1: the next step restarts the recurrences (p = r, s = w)
+    int32_t truer;    // r.r about to be summed is of r = b (2), of a true residual (1), recursive (0)
+    int32_t phase;    // which half of part the next vector phase reads
+    int32_t pad;
 };
 
 // Header of the virtual-block maps, device memory: {total virtual row blocks,
@@ -113,12 +120,13 @@ struct WideMap {
 
 inline int32_t wide_nvb(int64_t n) { return (int32_t)((n + kWideRows - 1) / kWideRows); }
 
-// One iteration (three launches: product, update, direction with commit)
-// for all listed wide systems, reading the systems' state from st and
-// writing it to st_next (callers alternate two buffers, so an even number
-// of iterations leaves the state in the first). grid: physical blocks of
-// every phase. ta_slot / ta_local map product tiles, vb_slot / vb_local
-// vector blocks to (system, local index).
+// One iteration (two launches: the product with its r.w partials, then the
+// vector phase with the scalar recurrences and the commit) for all listed
+// wide systems, reading the systems' state from st and writing it to st_next
+// (callers alternate two buffers, so an even number of iterations leaves the
+// state in the first). grid: physical blocks of every phase. ta_slot /
+// ta_local map product tiles, vb_slot / vb_local vector blocks to (system,
+// local index).
 spx_status wide_iteration_launch(const WideSlot *slots, const WideState *st, WideState *st_next,
                                  const WideMap *map, const int32_t *vb_slot, const int32_t *vb_local,
                                  const int32_t *ta_slot, const int32_t *ta_local, int grid, hipStream_t stream);

@@ -1,17 +1,25 @@
 // batch_wide.hip -- CG on many large systems at once, several work-groups per
 // system, no synchronisation between work-groups inside a launch.
 //
-// Unpreconditioned CG (Hestenes & Stiefel), x0 = 0, one iteration as three
-// grid-wide phases over every listed system (a launch boundary is the only
-// global synchronisation):
-//   A  q = A p (or q = A x in the true-residual mode), partial sums of p.q:
+// Unpreconditioned CG from x0 = 0 in the single-reduction form of Chronopoulos
+// and Gear (1989): besides r and p the recurrences carry w = A r and
+// s = A p, so both inner products of a step (r.r and r.w) come from one
+// pass and a step needs one grid-wide synchronisation fewer than the
+// Hestenes-Stiefel order (the same Krylov iterates in exact arithmetic).
+// One iteration is two grid-wide phases over every listed system (a launch
+// boundary is the only global synchronisation):
+//   A  w = A r (or w = A x in the true-residual mode), partial sums of r.w:
 //      the load-balanced CSR tile kernel over every listed system's tiles;
-//   B  alpha = rho / p.q from the partials; x += alpha p, r -= alpha q,
-//      partial sums of r.r (true-residual mode: r = b - q; init: r = b);
-//   C  beta = r.r / rho from the partials; p = r + beta p (or p = r on a
-//      restart or at init) -- skipped once r.r passes the tolerance; the
-//      first block of each system also commits its scalar state (rho,
-//      iteration count, mode, status) into the other of two state buffers.
+//   V  gamma = r.r and delta = r.w from the partials; beta = gamma / gamma_old,
+//      alpha = gamma / (delta - beta gamma / alpha_old) (beta = 0 and
+//      alpha = gamma / delta when the recurrences start); p = r + beta p,
+//      s = w + beta s, x += alpha p, r -= alpha s, partial sums of the new
+//      r.r (true-residual mode: r = b - w; init: r = b). The first block of
+//      each system commits its scalar state into the other of two state
+//      buffers.
+// The step is taken only while r.r is above the tolerance; below it the
+// system checks its true residual (one product of x) and either finishes or
+// restarts the recurrences from it.
 // Every work-group that needs a sum forms it from the same partials in the
 // same order, so all of them take the same decisions. A system's virtual
 // blocks, partials and summation order depend only on its own size; its
@@ -49,8 +57,8 @@ __device__ __forceinline__ double wide_part_sum(const double *part, int32_t cnt,
 }
 
 // Product phase: one work-group per virtual tile (system, tile). The tile
-// kernel runs with its p.q epilogue in both modes (the true-residual mode
-// multiplies x and ignores the partial).
+// kernel runs with its dot epilogue in both modes (w.r in the run mode; the
+// true-residual mode multiplies x and ignores the partial).
 __global__ __launch_bounds__(kCsrThreads) void wide_a_kernel(const WideSlot *__restrict__ slots,
                                                              const WideState *__restrict__ st,
                                                              const WideMap *__restrict__ map,
@@ -63,125 +71,56 @@ __global__ __launch_bounds__(kCsrThreads) void wide_a_kernel(const WideSlot *__r
         const int32_t mode = st[s].mode;
         if (mode != kWideRun && mode != kWideCheck) continue;
         const WideSlot S = slots[s];
-        const double *src = mode == kWideRun ? S.p : S.x;
+        const double *src = mode == kWideRun ? S.r : S.x;
         csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
-            k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, S.q, 1.0, 0.0, src, S.part_a, S.csr_part);
+            k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, S.w, 1.0, 0.0, src, S.part_a, S.csr_part);
     }
 }
 
-__global__ __launch_bounds__(kWideThreads) void wide_b_kernel(const WideSlot *__restrict__ slots,
-                                                              const WideState *__restrict__ st,
-                                                              const WideMap *__restrict__ map,
-                                                              const int32_t *__restrict__ vb_slot,
-                                                              const int32_t *__restrict__ vb_local)
+enum WideStep : int32_t { kStepTake = 0, kStepCheck = 1, kStepDone = 2 };
+
+// The run mode's decision, taken alike by every block of the system from the
+// two sums gamma = r.r and delta = r.w. On kStepTake, alpha and beta are set;
+// on kStepDone, W holds the final status.
+__device__ int32_t run_decision(WideState &W, const WideSlot &S, double gamma, double delta, double &alpha,
+                                double &beta)
 {
-    __shared__ double s_red[kWideWaves];
-    const int32_t total = map->total_vb;
-    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
-        const int32_t s = vb_slot[v], lv = vb_local[v];
-        const int32_t mode = st[s].mode;
-        if (mode == kWideDone) continue;
-        const WideSlot S = slots[s];
-        const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
-        double t = 0.0;
-        if (mode == kWideRun) {
-            const double pq = wide_part_sum(S.part_a, S.ntiles, s_red);
-            if (!(pq > 0.0) || !__builtin_isfinite(pq)) continue;  // the commit phase records the breakdown
-            const double alpha = st[s].rho / pq;
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
-                S.x[i] += alpha * S.p[i];
-                const double ri = S.r[i] - alpha * S.q[i];
-                S.r[i] = ri;
-                t += ri * ri;
-            }
-        } else if (mode == kWideCheck) {
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
-                const double ri = S.b[i] - S.q[i];
-                S.r[i] = ri;
-                t += ri * ri;
-            }
-        } else {  // init: x = 0 was written at admission
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
-                const double bi = S.b[i];
-                S.r[i] = bi;
-                t += bi * bi;
-            }
-        }
-        t = wide_wg_sum(t, s_red);
-        if (threadIdx.x == 0) S.part[lv] = t;
+    W.spmv += 1;
+    const double bb = W.truer == 2 ? gamma : W.bb;  // r = b: gamma is b.b
+    W.bb = bb;
+    W.rr = gamma;
+    if (!__builtin_isfinite(gamma)) {
+        W.status = kSlotNonfinite;
+        return kStepDone;
     }
+    if (gamma <= S.tol2 * bb) {  // also b = 0 (gamma = bb = 0)
+        if (W.truer == 0) return kStepCheck;
+        W.status = kSlotConverged;
+        W.relres_true = bb > 0.0 ? sqrt(gamma / bb) : 0.0;
+        return kStepDone;
+    }
+    if (W.iters >= S.maxit) {
+        W.status = kSlotMaxit;
+        return kStepDone;
+    }
+    beta = W.restart ? 0.0 : gamma / W.rho;
+    const double den = W.restart ? delta : delta - beta * gamma / W.alpha;
+    if (!__builtin_isfinite(delta) || !__builtin_isfinite(den)) {
+        W.status = kSlotNonfinite;
+        return kStepDone;
+    }
+    if (!(den > 0.0)) {  // p.A p <= 0: A is not positive definite along p
+        W.status = kSlotBreakdown;
+        return kStepDone;
+    }
+    alpha = gamma / den;
+    return kStepTake;
 }
 
-// Scalar state update of one system from the two partial sums of this
-// iteration (s1: p.q, s2: r.r or the true residual or b.b).
-__device__ void commit(WideState &W, const WideSlot &S, double s1, double s2)
-{
-    if (W.mode == kWideRun) {
-        W.spmv += 1;
-        if (!__builtin_isfinite(s1)) {
-            W.status = kSlotNonfinite;
-            W.mode = kWideDone;
-        } else if (!(s1 > 0.0)) {
-            W.status = kSlotBreakdown;
-            W.mode = kWideDone;
-        } else {
-            W.iters += 1;
-            W.rr = s2;
-            if (!__builtin_isfinite(s2)) {
-                W.status = kSlotNonfinite;
-                W.mode = kWideDone;
-            } else if (s2 <= S.tol2 * W.bb) {
-                W.mode = kWideCheck;
-            } else {
-                W.rho = s2;
-                if (W.iters >= S.maxit) {
-                    W.status = kSlotMaxit;
-                    W.mode = kWideDone;
-                }
-            }
-        }
-    } else if (W.mode == kWideCheck) {
-        W.spmv += 1;
-        W.rr = s2;
-        if (s2 <= S.tol2 * W.bb) {
-            W.status = kSlotConverged;
-            W.relres_true = sqrt(s2 / W.bb);
-            W.mode = kWideDone;
-        } else if (!__builtin_isfinite(s2)) {
-            W.status = kSlotNonfinite;
-            W.mode = kWideDone;
-        } else {
-            W.rho = s2;
-            W.mode = kWideRun;
-            if (W.iters >= S.maxit) {
-                W.status = kSlotMaxit;
-                W.mode = kWideDone;
-            }
-        }
-    } else {  // init
-        W.bb = s2;
-        W.rho = s2;
-        W.rr = s2;
-        if (!__builtin_isfinite(s2)) {
-            W.status = kSlotNonfinite;
-            W.mode = kWideDone;
-        } else if (s2 == 0.0) {
-            W.status = kSlotConverged;
-            W.relres_true = 0.0;
-            W.mode = kWideDone;
-        } else {
-            W.mode = kWideRun;
-        }
-    }
-    if (W.mode == kWideDone && W.status != kSlotConverged) W.relres_true = W.bb > 0 ? sqrt(W.rr / W.bb) : 0.0;
-}
-
-// Direction phase and commit. The first virtual block of every system also
-// forms the two sums of the iteration (the same partials in the same order
-// as every other block) and writes the system's updated state to st_next,
-// while all blocks read this iteration's state from st (the two buffers
-// alternate from one iteration to the next).
-__global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__restrict__ slots,
+// Vector phase and commit. Every block reads this iteration's state from st;
+// the first virtual block of each system writes the updated state to
+// st_next (the two buffers alternate from one iteration to the next).
+__global__ __launch_bounds__(kWideThreads) void wide_v_kernel(const WideSlot *__restrict__ slots,
                                                               const WideState *__restrict__ st,
                                                               WideState *__restrict__ st_next,
                                                               const WideMap *__restrict__ map,
@@ -200,29 +139,79 @@ __global__ __launch_bounds__(kWideThreads) void wide_c_kernel(const WideSlot *__
         }
         const WideSlot S = slots[s];
         const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
-        const double bb = W0.bb;
-        double s1 = 0.0, s2 = 0.0;
+        const double *part_in = S.part + (W0.phase ? S.nvb : 0);
+        double *part_out = S.part + (W0.phase ? 0 : S.nvb);
+        WideState W = W0;
+        bool wrote = false;  // this block stored a partial into part_out
+        double t = 0.0;
         if (W0.mode == kWideRun) {
-            s1 = wide_part_sum(S.part_a, S.ntiles, s_red);  // p.q
-            s2 = wide_part_sum(S.part, S.nvb, s_red);       // r.r
-            const bool step = s1 > 0.0 && __builtin_isfinite(s1) && __builtin_isfinite(s2) && !(s2 <= S.tol2 * bb);
-            if (step) {  // otherwise the solve stops or checks next
-                const double beta = s2 / W0.rho;
-                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i] + beta * S.p[i];
+            const double gamma = wide_part_sum(part_in, S.nvb, s_red);
+            const double delta = wide_part_sum(S.part_a, S.ntiles, s_red);
+            double alpha = 0.0, beta = 0.0;
+            const int32_t step = run_decision(W, S, gamma, delta, alpha, beta);
+            if (step == kStepTake) {
+                if (W0.restart) {
+                    for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                        const double pi = S.r[i], si = S.w[i];
+                        S.p[i] = pi;
+                        S.s[i] = si;
+                        S.x[i] += alpha * pi;
+                        const double ri = S.r[i] - alpha * si;
+                        S.r[i] = ri;
+                        t += ri * ri;
+                    }
+                } else {
+                    for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                        const double pi = S.r[i] + beta * S.p[i];
+                        const double si = S.w[i] + beta * S.s[i];
+                        S.p[i] = pi;
+                        S.s[i] = si;
+                        S.x[i] += alpha * pi;
+                        const double ri = S.r[i] - alpha * si;
+                        S.r[i] = ri;
+                        t += ri * ri;
+                    }
+                }
+                wrote = true;
+                W.iters += 1;
+                W.rho = gamma;
+                W.alpha = alpha;
+                W.restart = 0;
+                W.truer = 0;
+            } else if (step == kStepCheck) {
+                W.mode = kWideCheck;
+            } else {
+                W.mode = kWideDone;
+                if (W.status != kSlotConverged) W.relres_true = W.bb > 0.0 ? sqrt(W.rr / W.bb) : 0.0;
             }
         } else if (W0.mode == kWideCheck) {
-            s2 = wide_part_sum(S.part, S.nvb, s_red);  // true r.r
-            if (!(s2 <= S.tol2 * bb))
-                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];  // restart
-        } else {
-            if (lead) s2 = wide_part_sum(S.part, S.nvb, s_red);  // b.b
-            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                const double ri = S.b[i] - S.w[i];
+                S.r[i] = ri;
+                t += ri * ri;
+            }
+            wrote = true;
+            W.spmv += 1;
+            W.mode = kWideRun;
+            W.restart = 1;
+            W.truer = 1;
+        } else {  // init: x = 0 was written at admission
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                const double bi = S.b[i];
+                S.r[i] = bi;
+                t += bi * bi;
+            }
+            wrote = true;
+            W.mode = kWideRun;
+            W.restart = 1;
+            W.truer = 2;
         }
-        if (lead && threadIdx.x == 0) {
-            WideState W = W0;
-            commit(W, S, s1, s2);
-            st_next[s] = W;
+        if (wrote) {
+            t = wide_wg_sum(t, s_red);
+            if (threadIdx.x == 0) part_out[lv] = t;
+            W.phase = W0.phase ^ 1;
         }
+        if (lead && threadIdx.x == 0) st_next[s] = W;
     }
 }
 
@@ -232,9 +221,7 @@ spx_status wide_iteration_launch(const WideSlot *slots, const WideState *st, Wid
 {
     wide_a_kernel<<<grid, kCsrThreads, 0, stream>>>(slots, st, map, ta_slot, ta_local);
     SPX_LAUNCHED();
-    wide_b_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, map, vb_slot, vb_local);
-    SPX_LAUNCHED();
-    wide_c_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, st_next, map, vb_slot, vb_local);
+    wide_v_kernel<<<grid, kWideThreads, 0, stream>>>(slots, st, st_next, map, vb_slot, vb_local);
     SPX_LAUNCHED();
     return SPX_OK;
 }

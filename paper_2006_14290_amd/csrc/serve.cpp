@@ -15,7 +15,7 @@
 // persistent one-group-per-system kernels over the slot table: the
 // small-system kernel, then the general one) advances every system below
 // the wide threshold by its iteration budget; the wide graph (kWideIters iterations
-// of the three wide phases, the state alternating between two buffers)
+// of the two wide phases, the state alternating between two buffers)
 // advances every large system, launched as many times as fits the tick. Between ticks the worker reads the state back,
 // copies the solutions of finished systems to the callers' buffers, frees
 // their memory and slots, and admits more: new requests join within a few
@@ -57,11 +57,12 @@ static_assert(kWideIters % 2 == 0, "wide iterations per graph must be even");
 // a few thousand rows iterate faster on many work-groups than on one).
 constexpr int32_t kWideDefaultRows = kBatchSmallRows + 1;
 
-// Extra device bytes of a wide system: vector-phase partials, product
-// partials and the product's tile partition.
+// Extra device bytes of a wide system: the vector s = A p, the two halves of
+// the vector-phase partials, the product partials and the product's tile
+// partition.
 size_t wide_extra_bytes(int64_t n, int64_t nnz)
 {
-    return align256((size_t)wide_nvb(n) * 8) + align256((size_t)csr_tiles(nnz) * 8) +
+    return align256((size_t)n * 8) + align256((size_t)wide_nvb(n) * 2 * 8) + align256((size_t)csr_tiles(nnz) * 8) +
            align256((size_t)csr_partition_bytes(nnz));
 }
 
@@ -313,7 +314,8 @@ int admit(spx_server &S)
         const bool bicg = p.req.solver == SPX_SOLVER_BICGSTAB;
         double *rh = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
         double *tv = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
-        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 8)) : nullptr;
+        double *sv = p.wide ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
+        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 2 * 8)) : nullptr;
         double *part_a = p.wide ? reinterpret_cast<double *>(carve((size_t)csr_tiles(nnz) * 8)) : nullptr;
         int32_t *cpart = p.wide ? reinterpret_cast<int32_t *>(carve((size_t)csr_partition_bytes(nnz))) : nullptr;
         (void)hipMemcpyAsync(rp, p.req.rowptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, S.s_copy);
@@ -335,7 +337,8 @@ int admit(spx_server &S)
             w.x = x;
             w.r = r;
             w.p = pp;
-            w.q = q;
+            w.w = q;
+            w.s = sv;
             w.part = part;
             w.part_a = part_a;
             w.csr_part = cpart;
@@ -899,7 +902,8 @@ bool batch_is_wide(const spx_batch_system &s)
 }
 
 // Workspace: narrow slot table, counter, wide tables, then per system r, p, q
-// (+ 2 * nvb partial sums for wide systems).
+// (+ for wide systems: s, 2 * nvb vector-phase partials, the product
+// partials and the tile partition).
 struct BatchLayout {
     size_t slots, counter, wslots, wstate, wmap, vb, ta, vectors, total;
     int64_t nwide, total_vb, total_ta;
@@ -1000,10 +1004,12 @@ spx_status cg_batch_run(spx_batch_system *sys, int32_t count, const BatchLayout 
             w.x = sys[i].x;
             w.r = r;
             w.p = p;
-            w.q = q;
+            w.w = q;
             const int64_t nnz = sys[i].nnz;
+            w.s = reinterpret_cast<double *>(base + off);
+            off += align256((size_t)sys[i].n * 8);
             w.part = reinterpret_cast<double *>(base + off);
-            off += align256((size_t)wide_nvb(sys[i].n) * 8);
+            off += align256((size_t)wide_nvb(sys[i].n) * 2 * 8);
             w.part_a = reinterpret_cast<double *>(base + off);
             off += align256((size_t)csr_tiles(nnz) * 8);
             int32_t *cpart = reinterpret_cast<int32_t *>(base + off);
@@ -1075,9 +1081,10 @@ spx_status cg_batch_run(spx_batch_system *sys, int32_t count, const BatchLayout 
         SPX_HIP(hipMemcpyAsync(vb_dev, vb.data(), sizeof(int32_t) * vb.size(), hipMemcpyHostToDevice, stream));
         SPX_HIP(hipMemcpyAsync(ta_dev, ta.data(), sizeof(int32_t) * ta.size(), hipMemcpyHostToDevice, stream));
         const int grid = (int)std::min<int64_t>(std::max(L.total_vb, L.total_ta), 4096);
-        // every iteration either counts a CG step or is a true-residual check
-        // followed by one, so 2 * maxit + 4 iterations finish every system
-        const int64_t limit = 2 * (int64_t)maxit_max + 4;
+        // an iteration either takes a CG step or, at most twice per step, is
+        // the true-residual check that follows a small recursive residual or
+        // the decision after it, so 3 * maxit + 6 iterations finish every system
+        const int64_t limit = 3 * (int64_t)maxit_max + 6;
         for (int64_t done = 0; done < limit;) {
             for (int k = 0; k < 16; ++k, ++done)  // even: the state ends in the first buffer
                 SPX_CHECK(wide_iteration_launch(wslots_dev, (k & 1) ? wstate_dev + L.nwide : wstate_dev,
