@@ -19,7 +19,8 @@ The same run also measures (each section can be switched off):
     float32 / binary16-value iterative refinement against float64 CG on the
     7-point 192^3 grid, with the error against the float64 oracle solution;
   - the serving stream (Poisson arrivals, p50/p99 latency, solves/s, against
-    the same requests solved one by one);
+    the same requests solved one by one; request arrays in pinned host
+    memory, --serve-pageable for pageable ones);
   - the CPU oracle on the host's cores (one thread and all cores).
 
 Prints ONE JSON line; progress goes to stderr.
@@ -508,21 +509,39 @@ def serve_workload(S, nreq, seed):
     return [("poisson", int(pN[i])) if kinds[i] else ("spd", int(sn[i])) for i in range(nreq)]
 
 
-def build_requests(spx, S, torch, dev, reqs, seed):
+_PINNED = []  # torch tensors whose pinned host memory the request arrays view
+
+
+def _pinned_copy(torch, a):
+    """A numpy view of a pinned (page-locked) host copy of a; the tensor that
+    owns the memory is kept in _PINNED."""
+    t = torch.empty(a.shape, dtype=torch.from_numpy(a[:0]).dtype, pin_memory=True)
+    out = t.numpy()
+    out[...] = a
+    _PINNED.append(t)
+    return out
+
+
+def build_requests(spx, S, torch, dev, reqs, seed, pinned=False):
     """Host CSR matrices and right-hand sides of every request (Poisson
-    matrices shared by equal N; each SPD matrix generated for its request)."""
+    matrices shared by equal N; each SPD matrix generated for its request).
+    pinned: every array in page-locked host memory (as a receive path would
+    hold requests), so the server's uploads are plain DMA transfers."""
     pois = {}
     out = []
     t0 = time.time()
+    pin = (lambda a: _pinned_copy(torch, a)) if pinned else (lambda a: a)
     for i, (kind, size) in enumerate(reqs):
         if kind == "poisson":
             if size not in pois:
-                pois[size] = S.poisson2d(size)
+                P = S.poisson2d(size)
+                pois[size] = S.CSR(P.n, pin(P.rowptr), pin(P.col), pin(P.val))
             A = pois[size]
         else:
             A = S.spd_diag_dominant(size, seed=1_000_000 + seed * 100_000 + i, device=dev)
+            A = S.CSR(A.n, pin(A.rowptr), pin(A.col), pin(A.val))
         Ad = spx.csr_from_host(A, spx.F64, dev)
-        b = rhs(spx, S, torch, Ad, seed=seed * 100_000 + i).cpu().numpy()
+        b = pin(rhs(spx, S, torch, Ad, seed=seed * 100_000 + i).cpu().numpy())
         out.append((A, b))
         if (i + 1) % 500 == 0:
             progress(f"serve: {i + 1}/{len(reqs)} requests built ({time.time() - t0:.1f} s)")
@@ -550,16 +569,18 @@ def cpu_serve_sample(systems, nsample=200):
             "sample": f"first {len(sample)} requests of the stream, oracle CG to 1e-8, one solve per thread"}
 
 
-def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False):
+def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, pinned=True):
     """Serving: (1) all `nreq` requests submitted at once (capacity, solves/s);
     (2) open-loop Poisson arrival streams at `fracs` x that capacity (latency
     = completion - scheduled arrival, p50/p99; completion is the server's own
     submit-to-done time added to the submission time); (3) a sample of the
     same requests solved one by one with the blocking float64 CG
-    (spx_cg_solve), for comparison. Tolerance 1e-8."""
+    (spx_cg_solve), for comparison. Tolerance 1e-8. The request arrays are
+    in pinned host memory unless pinned=False (pageable numpy arrays, which
+    the runtime stages through its own buffers on the server's thread)."""
     reqs = serve_workload(S, nreq, seed)
     t0 = time.time()
-    systems = build_requests(spx, S, torch, dev, reqs, seed)
+    systems = build_requests(spx, S, torch, dev, reqs, seed, pinned=pinned)
     gen_s = time.time() - t0
     nnz = np.array([A.nnz for A, _ in systems])
     n = np.array([A.n for A, _ in systems])
@@ -655,9 +676,11 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False):
            "mix": {"poisson": int(sum(k == "poisson" for k, _ in reqs)), "spd": int(sum(k == "spd" for k, _ in reqs)),
                    "n_median": int(np.median(n)), "n_max": int(n.max()), "nnz_mean": int(nnz.mean()),
                    "nnz_max": int(nnz.max())},
-           "gen_s": round(gen_s, 1)}
+           "gen_s": round(gen_s, 1), "host_memory": "pinned" if pinned else "pageable"}
     if cpu:
         out["cpu_oracle"] = cpu_serve_sample(systems)
+    del systems
+    _PINNED.clear()
     return out
 
 
@@ -709,6 +732,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-fracs", default="0.5,0.7,0.9", help="open-loop arrival rates, fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="HBM budget of the serving run")
+    ap.add_argument("--serve-pageable", action="store_true",
+                    help="requests in pageable host memory (default: pinned, as a receive path holds them)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-subwarp", action="store_true", help="skip the subwarp reduction sweep")
     args = ap.parse_args()
@@ -798,7 +823,7 @@ def main():
     if args.serve_requests > 0:
         fracs = [float(f) for f in args.serve_fracs.split(",") if f]
         serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed, fracs, args.serve_budget_gb,
-                            not args.no_cpu)
+                            not args.no_cpu, pinned=not args.serve_pageable)
     subwarp = None
     if not args.no_subwarp:
         progress("subwarp sweep")
