@@ -296,7 +296,7 @@ def test_cg_batch_wide_mix_alone_bitwise():
 
 def test_cg_batch_wide_status_codes():
     n = 20000
-    # indefinite diagonal: p.q <= 0 at some step
+    # indefinite diagonal: p.A p <= 0 at some step
     d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
     rowptr = np.arange(n + 1, dtype=np.int32)
     col = np.arange(n, dtype=np.int32)
