@@ -316,6 +316,19 @@ def test_cg_batch_wide_status_codes():
     assert inf[0]["status"] == spx.ERR_NOT_CONVERGED and inf[0]["iters"] == 3
 
 
+def test_cg_batch_wide_true_residual_restarts():
+    """A tolerance below the attainable accuracy: the recursive residual keeps
+    passing it, each true-residual check fails and the recurrences restart
+    from the true residual, until maxit; the iterate stays accurate."""
+    A, b = _system("poisson", 130, 1)
+    xs, inf = spx.cg_batch([spx.csr_from_host(A)], [dev(b)], tol=1e-17, maxit=800, path=spx.BATCH_WIDE)
+    assert inf[0]["status"] == spx.ERR_NOT_CONVERGED and inf[0]["iters"] == 800, inf
+    # one product per step; each failed check adds two (the product whose
+    # step was not taken, and the check's), the stop at maxit one more
+    assert inf[0]["spmv_count"] >= inf[0]["iters"] + 5, inf
+    assert _relres(A, b, host(xs[0])) <= 1e-14
+
+
 def test_server_wide_and_narrow_mix_bitwise():
     srv = spx.Server(max_slots=6, hbm_budget_bytes=512 << 20, tick_us=500)
     try:
