@@ -5,12 +5,15 @@
 // kBatchSmallRows rows on their own kernel) and the grid-wide phases of the
 // wide path for large systems (batch_wide.hip).
 //
-// Server: requests (host CSR + right-hand side) are queued FIFO; a worker
+// Server: requests (host CSR + right-hand side) are queued FIFO; an admission
 // thread admits them while a slot is free and the HBM pool (one allocation of
 // hbm_budget_bytes made at creation, carved first-fit) can hold the matrix and
 // its Krylov vectors, looking past a request that does not fit at most
-// kBackfill places. Admitted requests are copied to the device on a copy
-// stream while the current tick runs. A tick runs two captured hipGraphs on
+// kBackfill places, and copies them to the device on a copy stream while the
+// worker thread runs ticks (copies from pageable host memory, which the
+// runtime stages through its own buffers, hold up only the admission
+// thread); the worker takes a system into its tables once its copies have
+// landed. A tick runs two captured hipGraphs on
 // two streams at once: the narrow graph (reset the work counters, run the
 // persistent one-group-per-system kernels over the slot table: the
 // small-system kernel, then the general one) advances every system below
@@ -156,8 +159,14 @@ struct Active {
     // when it retires the system, so a cancel that returned before the
     // retirement always ends in SPX_CANCELLED.
     std::atomic<bool> cancel{false};
-    bool live = false;  // written under the mutex (reserve, retire), read by the worker freely
-    bool staged = false;  // descriptor waiting in spx_server::staged / wstaged
+    // written under the mutex (reserve, retire), read by the worker freely
+    std::atomic<bool> live{false};
+    // reserved by the admission thread, not yet in the worker's tables; while
+    // it is set the worker reads no other field of the slot
+    std::atomic<bool> staged{false};
+    // set by the admission thread (release) once the slot's copies have
+    // landed and its descriptor in spx_server::staged / wstaged is written
+    std::atomic<bool> ready{false};
     bool wide = false;
     bool in_map = false;  // listed in the wide map uploaded for the current tick
 };
@@ -211,9 +220,12 @@ struct spx_server {
     std::deque<Pending> queue;
     std::unordered_map<uint64_t, Result> results;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::thread worker;
+    // cv_work: a new request or freed memory (admission thread); cv_ready: a
+    // slot became ready (worker); cv_done: a result (waiters)
+    std::condition_variable cv_work, cv_ready, cv_done;
+    std::thread worker, admitter;
     std::atomic<bool> stop{false};
+    std::atomic<bool> admit_failed{false};
     uint64_t next_ticket = 1;
     spx_server_stats stats{};
     std::string fatal;
@@ -249,9 +261,10 @@ void finish_locked(spx_server &S, uint64_t ticket, spx_status st, const spx_solv
     S.cv_done.notify_all();
 }
 
-// Admit queued requests into free slots and pool memory (copies on s_copy).
-// Returns the number admitted.
-int admit(spx_server &S)
+// Admit queued requests into free slots and pool memory (copies on s_copy;
+// the caller synchronizes s_copy before it marks the slots ready). Returns
+// the admitted slots.
+std::vector<int> admit(spx_server &S)
 {
     std::vector<std::pair<int, Pending>> take;
     {
@@ -280,8 +293,11 @@ int admit(spx_server &S)
                 S.inflight += w;
                 a.ticket = p.ticket;
                 a.cancel.store(false);
-                a.live = true;
-                a.staged = true;
+                // staged before live: a worker that sees the slot live
+                // also sees it staged, and leaves it alone
+                a.ready.store(false);
+                a.staged.store(true);
+                a.live.store(true);
                 take.emplace_back(free_slot, p);
                 it = S.queue.erase(it);
             } else {
@@ -395,7 +411,9 @@ int admit(spx_server &S)
         a.nnz = nnz;
         a.t_submit = p.t_submit;
     }
-    return (int)take.size();
+    std::vector<int> slots;
+    for (auto &tp : take) slots.push_back(tp.first);
+    return slots;
 }
 
 // Move the descriptors of newly admitted slots into the table mirror (only
@@ -403,7 +421,7 @@ int admit(spx_server &S)
 void apply_staged(spx_server &S)
 {
     for (int i = 0; i < (int)S.active.size(); ++i)
-        if (S.active[i].staged) {
+        if (S.active[i].staged.load() && S.active[i].ready.load(std::memory_order_acquire)) {
             if (S.active[i].wide) {
                 S.wslots_host[i] = S.wstaged[i];
                 S.wstate_host[i] = S.winit_host[i];
@@ -411,7 +429,8 @@ void apply_staged(spx_server &S)
             } else {
                 S.slots_host[i] = S.staged[i];
             }
-            S.active[i].staged = false;
+            S.active[i].ready.store(false);
+            S.active[i].staged.store(false);
         }
 }
 
@@ -423,8 +442,9 @@ bool rebuild_wide_map(spx_server &S)
     int64_t tot = 0, tta = 0;
     for (int i = 0; i < (int)S.active.size(); ++i) {
         Active &a = S.active[i];
+        if (!a.live || a.staged) continue;  // a staged slot's fields belong to the admission thread
         a.in_map = false;
-        if (!a.live || !a.wide || a.staged || a.cancel.load()) continue;
+        if (!a.wide || a.cancel.load()) continue;
         const int32_t nvb = S.wslots_host[i].nvb, nt = S.wslots_host[i].ntiles;
         if (tot + nvb > S.vb_cap || tta + nt > S.ta_cap) return false;
         ++nl;
@@ -533,24 +553,43 @@ void set_fatal(spx_server &S, const char *what)
     S.fatal = what;
 }
 
-void worker_main(spx_server *Sp)
+// Admission thread: reserves slots and pool memory for queued requests and
+// copies them in (s_copy); a slot becomes ready once its copies have landed.
+void admitter_main(spx_server *Sp)
 {
     spx_server &S = *Sp;
     (void)hipSetDevice(S.device);
     while (!S.stop.load()) {
-        admit(S);
-        bool any = false;
-        for (auto &a : S.active) any |= a.live;
-        if (!any) {
+        const std::vector<int> slots = admit(S);
+        if (slots.empty()) {
             std::unique_lock<std::mutex> lk(S.mu);
-            if (S.queue.empty() && !S.stop.load()) S.cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            if (!S.stop.load()) S.cv_work.wait_for(lk, std::chrono::milliseconds(1));
             continue;
         }
         if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
             set_fatal(S, "admission copy failed");
+            S.admit_failed.store(true);
+            S.cv_ready.notify_all();
             break;
         }
+        for (int si : slots) S.active[si].ready.store(true, std::memory_order_release);
+        S.cv_ready.notify_one();
+    }
+}
+
+void worker_main(spx_server *Sp)
+{
+    spx_server &S = *Sp;
+    (void)hipSetDevice(S.device);
+    while (!S.stop.load() && !S.admit_failed.load()) {
         apply_staged(S);
+        bool any = false;
+        for (auto &a : S.active) any |= a.live.load() && !a.staged.load();
+        if (!any) {
+            std::unique_lock<std::mutex> lk(S.mu);
+            if (!S.stop.load()) S.cv_ready.wait_for(lk, std::chrono::milliseconds(1));
+            continue;
+        }
         if (S.wide_dirty && !rebuild_wide_map(S)) {
             set_fatal(S, "wide map upload failed");
             break;
@@ -558,7 +597,7 @@ void worker_main(spx_server *Sp)
         const int32_t nwide = S.wmap_host->nlisted;
         bool narrow = false;
         for (int i = 0; i < (int)S.active.size(); ++i) {
-            if (!S.active[i].live || S.active[i].wide) continue;
+            if (!S.active[i].live || S.active[i].staged || S.active[i].wide) continue;
             BatchSlot &d = S.slots_host[i];
             if (S.active[i].cancel.load()) {
                 d.budget = 0;
@@ -585,9 +624,6 @@ void worker_main(spx_server *Sp)
                 e = hipMemcpyAsync(S.wstate_host, S.wstate_dev, sizeof(WideState) * S.active.size(),
                                    hipMemcpyDeviceToHost, S.s_wide);
         }
-        // admit more while the tick runs (descriptors stay staged until the
-        // read-back of the tables has landed)
-        admit(S);
         if (e == hipSuccess) e = hipStreamSynchronize(S.s_compute);
         if (e == hipSuccess) e = hipStreamSynchronize(S.s_wide);
         if (e == hipSuccess && S.cfg.debug_fail_tick > 0 && S.stats.ticks + 1 >= S.cfg.debug_fail_tick)
@@ -605,17 +641,20 @@ void worker_main(spx_server *Sp)
                 S.wide_launches = (int)std::max(1.0, std::min(64.0, tick_ms / per));
             }
         }
-        if (hipStreamSynchronize(S.s_copy) != hipSuccess) {
-            set_fatal(S, "admission copy failed");
-            break;
-        }
         {
             std::lock_guard<std::mutex> lk(S.mu);
             S.stats.ticks += 1;
         }
-        retire(S);  // before apply_staged: newly admitted systems have no state to read yet
-        apply_staged(S);
+        // before apply_staged (next iteration): newly admitted systems have
+        // no state to read yet; freed memory lets the admission thread go on
+        retire(S);
+        S.cv_work.notify_one();
     }
+    // the admission thread stops first, so no copy from a caller's arrays is
+    // in flight once the requests end
+    S.stop.store(true);
+    S.cv_work.notify_all();
+    if (S.admitter.joinable()) S.admitter.join();
     // whatever is left ends now: failed after an error, cancelled on a stop
     bool failed;
     {
@@ -772,6 +811,7 @@ extern "C" spx_status spx_server_create(const spx_server_config *cfg, spx_server
     S->staged.resize(ms);
     S->wstaged.resize(ms);
     S->stats.pool_bytes_total = cfg->hbm_budget_bytes;
+    S->admitter = std::thread(admitter_main, S);
     S->worker = std::thread(worker_main, S);
     *out = S;
     return SPX_OK;
@@ -883,7 +923,8 @@ extern "C" spx_status spx_server_destroy(spx_server *S)
     if (!S) return SPX_OK;
     S->stop.store(true);
     S->cv_work.notify_all();
-    if (S->worker.joinable()) S->worker.join();
+    S->cv_ready.notify_all();
+    if (S->worker.joinable()) S->worker.join();  // joins the admission thread first
     (void)hipStreamSynchronize(S->s_compute);
     (void)hipStreamSynchronize(S->s_wide);
     (void)hipStreamSynchronize(S->s_copy);
