@@ -505,10 +505,13 @@ spx_status spx_serve_wait(spx_server *server, uint64_t ticket, double timeout_s,
 spx_status spx_serve_cancel(spx_server *server, uint64_t ticket);
 /* Counters of the server. (Named _get_stats: spx_server_stats is the type.) */
 spx_status spx_server_get_stats(spx_server *server, spx_server_stats *stats);
-/* If a HIP call fails in the worker, the server stops: every queued and
- * resident request ends with SPX_ERR_HIP (waiters are woken) and later
- * submissions return SPX_ERR_HIP. */
-/* Stops the worker (queued and resident requests end as SPX_CANCELLED) and
+/* The server runs two threads: an admission thread (slots, pool memory and
+ * the copies of the request arrays; pinned host arrays are copied by DMA,
+ * pageable ones are staged by the runtime on this thread) and a worker
+ * (ticks, retirement). If a HIP call fails in either, the server stops:
+ * every queued and resident request ends with SPX_ERR_HIP (waiters are
+ * woken) and later submissions return SPX_ERR_HIP. */
+/* Stops both threads (queued and resident requests end as SPX_CANCELLED) and
  * frees everything. */
 spx_status spx_server_destroy(spx_server *server);
 
