@@ -442,8 +442,9 @@ spx_status spx_cg_batch_noalloc(spx_batch_system *sys, int32_t count, hipStream_
  * definite systems are solved by CG; nonsymmetric ones by BiCGSTAB (the BiCG
  * family the paper lists among the library's solvers, Section 1), request
  * field solver = SPX_SOLVER_BICGSTAB, unpreconditioned, from x = 0, with the
- * true-residual confirmation of spx_bicgstab_solve; BiCGSTAB systems always
- * run one work-group each (never the wide path). A finished CG request's
+ * true-residual confirmation of spx_bicgstab_solve; BiCGSTAB systems above
+ * the wide threshold take the wide path too (one step as three product +
+ * vector pairs). A finished CG request's
  * solution is bitwise the solution that spx_cg_batch gives for the same
  * system alone with the same path; every request's result is bitwise the
  * same alone or in any mix. */

@@ -80,33 +80,38 @@ enum WideMode : int32_t {
 
 // Written by the host when the system is admitted. The product phase runs
 // the load-balanced CSR tile kernel over the system's ntiles tiles (its
-// partition in csr_part), one partial r.w per tile in part_a; the vector
-// phase works on nvb blocks of kWideRows rows, one partial r.r each, into
-// one half of part while it reads the other half (the halves alternate).
+// partition in csr_part), one or two partials per tile in part_a (rows of
+// ntiles); the vector phase works on nvb blocks of kWideRows rows, one or
+// two partials each, into one half of part while it reads the other half
+// (the halves alternate; each half holds two rows of nvb).
 struct WideSlot {
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
     const double *b;
-    double *x, *r, *p, *w, *s;  // w = A r, s = A p
-    double *part;               // 2 * nvb partial sums of the vector phase
-    double *part_a;             // ntiles partial sums of the product phase
+    double *x, *r, *p, *w, *s;  // CG: w = A r, s = A p; BiCGSTAB: w holds v = A p
+    double *rh, *t;             // BiCGSTAB only: shadow residual, t = A s
+    double *part;               // 4 * nvb partial sums of the vector phase
+    double *part_a;             // 2 * ntiles partial sums of the product phase
     const int32_t *csr_part;    // tile partition of the product
     int64_t nnz;
     int32_t n, nvb, ntiles, maxit;
     double tol2;
+    int32_t solver;  // SlotSolver
+    int32_t pad;
 };
 
 // Written by the device (the vector phase's commit) and once at admission
 // (zero but mode = kWideInit).
 struct WideState {
     int32_t mode, status, iters, spmv;  // status: SlotStatus
-    double rho, bb, rr, relres_true;    // rho: r.r of the last step's residual
+    double rho, bb, rr, relres_true;    // CG: rho = r.r of the last step; BiCGSTAB: rho = r_hat.r
     double alpha;                       // the last step length
-    int32_t restart;  // 1: the next step restarts the recurrences (p = r, s = w)
+    int32_t restart;  // CG: 1 = the next step restarts the recurrences (p = r, s = w)
     int32_t truer;    // r.r about to be summed is of r = b (2), of a true residual (1), recursive (0)
     int32_t phase;    // which half of part the next vector phase reads
-    int32_t pad;
+    int32_t bphase;   // BiCGSTAB: which part of a step the next product + vector pair runs
+    double rho0, omega;  // BiCGSTAB: the previous r_hat.r, the last omega
 };
 
 // Header of the virtual-block maps, device memory: {total virtual row blocks,

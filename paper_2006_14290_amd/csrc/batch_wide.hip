@@ -20,6 +20,14 @@
 // The step is taken only while r.r is above the tolerance; below it the
 // system checks its true residual (one product of x) and either finishes or
 // restarts the recurrences from it.
+// Nonsymmetric systems run unpreconditioned BiCGSTAB (van der Vorst 1992, in
+// the order of the one-work-group kernel) on the same two kernels, one step
+// as three product + vector pairs (bphase 0: v = A p with r_hat.v partials,
+// then alpha and s = r - alpha v with s.s partials; bphase 1: t = A s with
+// t.s and t.t partials, then omega, x and r = s - omega t with r.r and
+// r_hat.r partials; bphase 2: no product, then beta and the new p). A small
+// ||s|| or ||r|| is confirmed with the true residual, whose sum is read by
+// one more pair (bphase 3), which also starts the recurrences after init.
 // Every work-group that needs a sum forms it from the same partials in the
 // same order, so all of them take the same decisions. A system's virtual
 // blocks, partials and summation order depend only on its own size; its
@@ -71,6 +79,16 @@ __global__ __launch_bounds__(kCsrThreads) void wide_a_kernel(const WideSlot *__r
         const int32_t mode = st[s].mode;
         if (mode != kWideRun && mode != kWideCheck) continue;
         const WideSlot S = slots[s];
+        if (S.solver == kSlotBicgstab && mode == kWideRun) {
+            const int32_t bp = st[s].bphase;
+            if (bp == 0)  // v = A p, r_hat.v
+                csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
+                    k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, S.p, S.w, 1.0, 0.0, S.rh, S.part_a, S.csr_part);
+            else if (bp == 1)  // t = A s (s is held in r), t.s and t.t
+                csr_tile<double, double, 2, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
+                    k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, S.r, S.t, 1.0, 0.0, S.r, S.part_a, S.csr_part);
+            continue;
+        }
         const double *src = mode == kWideRun ? S.r : S.x;
         csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
             k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, S.w, 1.0, 0.0, src, S.part_a, S.csr_part);
@@ -117,6 +135,146 @@ __device__ int32_t run_decision(WideState &W, const WideSlot &S, double gamma, d
     return kStepTake;
 }
 
+// BiCGSTAB's vector phase on one virtual block of one system; the lead block
+// commits the state to *next. part_in / part_out: two rows of nvb partials.
+__device__ void bicgstab_vector_phase(const WideSlot &S, const WideState &W0, bool lead, int32_t lv,
+                                      const double *part_in, double *part_out, WideState *next, double *s_red)
+{
+    const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
+    WideState W = W0;
+    int nw = 0;  // partial rows this block stores into part_out
+    double t0 = 0.0, t1 = 0.0;
+    auto done = [&](int32_t status) {
+        W.status = status;
+        W.mode = kWideDone;
+        if (status != kSlotConverged) W.relres_true = W.bb > 0.0 ? sqrt(W.rr / W.bb) : 0.0;
+    };
+    if (W0.mode == kWideInit) {  // x = 0 (written at admission): r = r_hat = b
+        for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+            const double bi = S.b[i];
+            S.r[i] = bi;
+            S.rh[i] = bi;
+            t0 += bi * bi;
+        }
+        nw = 1;
+        W.mode = kWideRun;
+        W.bphase = 3;
+        W.truer = 2;
+    } else if (W0.mode == kWideCheck) {  // r = b - A x (A x in w), r_hat = r
+        for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+            const double ri = S.b[i] - S.w[i];
+            S.r[i] = ri;
+            S.rh[i] = ri;
+            t0 += ri * ri;
+        }
+        nw = 1;
+        W.spmv += 1;
+        W.mode = kWideRun;
+        W.bphase = 3;
+        W.truer = 1;
+    } else if (W0.bphase == 3) {  // a true residual's r.r: converged, or (re)start
+        const double tr = wide_part_sum(part_in, S.nvb, s_red);
+        if (W0.truer == 2) W.bb = tr;
+        W.rr = tr;
+        if (!__builtin_isfinite(tr)) {
+            done(kSlotNonfinite);
+        } else if (tr <= S.tol2 * W.bb) {  // also b = 0
+            W.relres_true = W.bb > 0.0 ? sqrt(tr / W.bb) : 0.0;
+            done(kSlotConverged);
+        } else {
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.p[i] = S.r[i];
+            W.rho = tr;  // r_hat = r
+            W.rho0 = W.alpha = W.omega = 1.0;
+            W.truer = 0;
+            W.bphase = 0;
+        }
+    } else if (W0.bphase == 0) {  // v = A p is in w: alpha, s = r - alpha v
+        const double rhv = wide_part_sum(S.part_a, S.ntiles, s_red);
+        if (W0.iters >= S.maxit) {
+            done(kSlotMaxit);
+        } else {
+            W.iters += 1;
+            W.spmv += 1;
+            if (!__builtin_isfinite(rhv)) {
+                done(kSlotNonfinite);
+            } else if (rhv == 0.0) {
+                done(kSlotBreakdown);
+            } else {
+                const double alpha = W0.rho / rhv;
+                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                    const double si = S.r[i] - alpha * S.w[i];
+                    S.r[i] = si;
+                    t0 += si * si;
+                }
+                nw = 1;
+                W.alpha = alpha;
+                W.bphase = 1;
+            }
+        }
+    } else if (W0.bphase == 1) {  // t = A s is in t: omega, x, r = s - omega t
+        const double ss = wide_part_sum(part_in, S.nvb, s_red);
+        const double ts = wide_part_sum(S.part_a, S.ntiles, s_red);
+        const double tt = wide_part_sum(S.part_a + S.ntiles, S.ntiles, s_red);
+        W.rr = ss;
+        const double alpha = W0.alpha;
+        if (ss <= S.tol2 * W0.bb) {  // ||s|| small: x += alpha p, then confirm
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) S.x[i] += alpha * S.p[i];
+            W.mode = kWideCheck;
+        } else {
+            W.spmv += 1;  // t = A s
+            if (!__builtin_isfinite(tt) || !__builtin_isfinite(ss)) {
+                done(kSlotNonfinite);
+            } else if (tt == 0.0) {
+                done(kSlotBreakdown);
+            } else {
+                const double omega = ts / tt;
+                for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads) {
+                    const double si = S.r[i];
+                    S.x[i] += alpha * S.p[i] + omega * si;
+                    const double ri = si - omega * S.t[i];
+                    S.r[i] = ri;
+                    t0 += ri * ri;
+                    t1 += S.rh[i] * ri;
+                }
+                nw = 2;
+                W.omega = omega;
+                W.bphase = 2;
+            }
+        }
+    } else {  // bphase 2: r.r and r_hat.r: confirm, or beta and p
+        const double rr = wide_part_sum(part_in, S.nvb, s_red);
+        const double rho = wide_part_sum(part_in + S.nvb, S.nvb, s_red);
+        W.rr = rr;
+        if (!__builtin_isfinite(rr)) {
+            done(kSlotNonfinite);
+        } else if (rr <= S.tol2 * W0.bb) {
+            W.mode = kWideCheck;
+        } else if (W0.omega == 0.0 || rho == 0.0) {
+            done(kSlotBreakdown);
+        } else if (!__builtin_isfinite(rho)) {
+            done(kSlotNonfinite);
+        } else {
+            const double beta = (rho / W0.rho) * (W0.alpha / W0.omega);
+            const double omega = W0.omega;
+            for (int32_t i = r0 + threadIdx.x; i < r1; i += kWideThreads)
+                S.p[i] = S.r[i] + beta * (S.p[i] - omega * S.w[i]);
+            W.rho0 = W0.rho;
+            W.rho = rho;
+            W.bphase = 0;
+        }
+    }
+    if (nw > 0) {
+        t0 = wide_wg_sum(t0, s_red);
+        if (nw > 1) t1 = wide_wg_sum(t1, s_red);
+        if (threadIdx.x == 0) {
+            part_out[lv] = t0;
+            if (nw > 1) part_out[S.nvb + lv] = t1;
+        }
+        W.phase = W0.phase ^ 1;
+    }
+    if (lead && threadIdx.x == 0) *next = W;
+}
+
 // Vector phase and commit. Every block reads this iteration's state from st;
 // the first virtual block of each system writes the updated state to
 // st_next (the two buffers alternate from one iteration to the next).
@@ -139,8 +297,12 @@ __global__ __launch_bounds__(kWideThreads) void wide_v_kernel(const WideSlot *__
         }
         const WideSlot S = slots[s];
         const int32_t r0 = lv * kWideRows, r1 = min(S.n, r0 + kWideRows);
-        const double *part_in = S.part + (W0.phase ? S.nvb : 0);
-        double *part_out = S.part + (W0.phase ? 0 : S.nvb);
+        const double *part_in = S.part + (W0.phase ? 2 * S.nvb : 0);
+        double *part_out = S.part + (W0.phase ? 0 : 2 * S.nvb);
+        if (S.solver == kSlotBicgstab) {
+            bicgstab_vector_phase(S, W0, lead, lv, part_in, part_out, st_next + s, s_red);
+            continue;
+        }
         WideState W = W0;
         bool wrote = false;  // this block stored a partial into part_out
         double t = 0.0;

@@ -60,13 +60,13 @@ static_assert(kWideIters % 2 == 0, "wide iterations per graph must be even");
 // a few thousand rows iterate faster on many work-groups than on one).
 constexpr int32_t kWideDefaultRows = kBatchSmallRows + 1;
 
-// Extra device bytes of a wide system: the vector s = A p, the two halves of
-// the vector-phase partials, the product partials and the product's tile
-// partition.
+// Extra device bytes of a wide system: the vector s = A p (CG), the two
+// halves of two rows of vector-phase partials, two rows of product partials
+// and the product's tile partition.
 size_t wide_extra_bytes(int64_t n, int64_t nnz)
 {
-    return align256((size_t)n * 8) + align256((size_t)wide_nvb(n) * 2 * 8) + align256((size_t)csr_tiles(nnz) * 8) +
-           align256((size_t)csr_partition_bytes(nnz));
+    return align256((size_t)n * 8) + align256((size_t)wide_nvb(n) * 4 * 8) +
+           align256((size_t)csr_tiles(nnz) * 2 * 8) + align256((size_t)csr_partition_bytes(nnz));
 }
 
 // Device bytes of one system: CSR arrays + b, x, r, p, q (+ the partials and
@@ -77,12 +77,12 @@ size_t system_bytes(int64_t n, int64_t nnz, bool wide, bool bicgstab)
            (bicgstab ? 7 : 5) * align256((size_t)n * 8) + (wide ? wide_extra_bytes(n, nnz) : 0);
 }
 
-// CG systems from wide_min_rows rows on take the wide path; BiCGSTAB
-// systems always run one work-group each.
-bool is_wide(int32_t wide_min_rows, int64_t n, int32_t solver)
+// Systems from wide_min_rows rows on (CG and BiCGSTAB alike) take the wide
+// path.
+bool is_wide(int32_t wide_min_rows, int64_t n)
 {
     const int64_t t = wide_min_rows == 0 ? kWideDefaultRows : wide_min_rows;
-    return solver == SPX_SOLVER_CG && wide_min_rows >= 0 && n >= t;
+    return wide_min_rows >= 0 && n >= t;
 }
 
 struct Pool {
@@ -331,8 +331,8 @@ std::vector<int> admit(spx_server &S)
         double *rh = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
         double *tv = bicg ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
         double *sv = p.wide ? reinterpret_cast<double *>(carve((size_t)n * 8)) : nullptr;
-        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 2 * 8)) : nullptr;
-        double *part_a = p.wide ? reinterpret_cast<double *>(carve((size_t)csr_tiles(nnz) * 8)) : nullptr;
+        double *part = p.wide ? reinterpret_cast<double *>(carve((size_t)wide_nvb(n) * 4 * 8)) : nullptr;
+        double *part_a = p.wide ? reinterpret_cast<double *>(carve((size_t)csr_tiles(nnz) * 2 * 8)) : nullptr;
         int32_t *cpart = p.wide ? reinterpret_cast<int32_t *>(carve((size_t)csr_partition_bytes(nnz))) : nullptr;
         (void)hipMemcpyAsync(rp, p.req.rowptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, S.s_copy);
         if (nnz > 0) {
@@ -355,6 +355,9 @@ std::vector<int> admit(spx_server &S)
             w.p = pp;
             w.w = q;
             w.s = sv;
+            w.rh = rh;
+            w.t = tv;
+            w.solver = bicg ? kSlotBicgstab : kSlotCg;
             w.part = part;
             w.part_a = part_a;
             w.csr_part = cpart;
@@ -829,7 +832,7 @@ extern "C" spx_status spx_serve_submit(spx_server *S, const spx_request *req, ui
     SPX_REQUIRE(req->nnz <= INT32_MAX, SPX_ERR_ARG, "spx_serve_submit: nnz exceeds int32");
     // nothing malformed may reach the kernels that every resident system shares
     SPX_CHECK(validate_csr_host(req->n, req->n, req->nnz, req->rowptr, req->colidx));
-    const bool wide = is_wide(S->cfg.wide_min_rows, req->n, req->solver);
+    const bool wide = is_wide(S->cfg.wide_min_rows, req->n);
     const size_t bytes = system_bytes(req->n, req->nnz, wide, req->solver == SPX_SOLVER_BICGSTAB);
     std::lock_guard<std::mutex> lk(S->mu);
     SPX_REQUIRE(S->fatal.empty(), SPX_ERR_HIP, "spx_serve_submit: server failed: %s", S->fatal.c_str());
@@ -1050,9 +1053,10 @@ spx_status cg_batch_run(spx_batch_system *sys, int32_t count, const BatchLayout 
             w.s = reinterpret_cast<double *>(base + off);
             off += align256((size_t)sys[i].n * 8);
             w.part = reinterpret_cast<double *>(base + off);
-            off += align256((size_t)wide_nvb(sys[i].n) * 2 * 8);
+            off += align256((size_t)wide_nvb(sys[i].n) * 4 * 8);
             w.part_a = reinterpret_cast<double *>(base + off);
-            off += align256((size_t)csr_tiles(nnz) * 8);
+            off += align256((size_t)csr_tiles(nnz) * 2 * 8);
+            w.solver = kSlotCg;
             int32_t *cpart = reinterpret_cast<int32_t *>(base + off);
             off += align256((size_t)csr_partition_bytes(nnz));
             w.csr_part = cpart;

@@ -418,6 +418,41 @@ def test_server_bicgstab_alone_mix_bitwise_and_oracle():
     np.testing.assert_array_equal(x1.view(np.uint64), alone[1][0].view(np.uint64))
 
 
+def test_server_bicgstab_wide_and_one_group_agree():
+    """Large nonsymmetric requests take the wide path (three product + vector
+    pairs per BiCGSTAB step); the one-work-group path (wide path switched
+    off) solves the same systems in about as many steps."""
+    for N, seed in NONSYM[1:]:
+        A, b = _nonsym(N, seed)
+        assert A.n > 4096
+        xw, iw = _served_alone(A, b, spx.SOLVER_BICGSTAB)
+        xn, inn = _served_alone(A, b, spx.SOLVER_BICGSTAB, wide_min_rows=-1)
+        assert iw["status"] == inn["status"] == spx.OK, (iw, inn)
+        for x in (xw, xn):
+            assert _relres(A, b, x) <= 1e-8
+        assert abs(iw["iters"] - inn["iters"]) <= 0.1 * inn["iters"] + 5, (iw, inn)
+        assert iw["spmv_count"] >= 2 * iw["iters"] - 1
+
+
+def test_server_bicgstab_wide_status_codes():
+    A, b = _nonsym(28, 5)
+    srv = spx.Server(max_slots=4, hbm_budget_bytes=256 << 20)
+    try:
+        t1 = srv.submit(A, b, tol=1e-12, maxit=3, solver=spx.SOLVER_BICGSTAB)
+        t2 = srv.submit(A, np.zeros(A.n), tol=1e-8, solver=spx.SOLVER_BICGSTAB)
+        bn = b.copy()
+        bn[11] = np.nan
+        t3 = srv.submit(A, bn, tol=1e-8, solver=spx.SOLVER_BICGSTAB)
+        _, i1 = srv.wait(t1, timeout_s=60)
+        assert i1["status"] == spx.ERR_NOT_CONVERGED and i1["iters"] == 3, i1
+        x2, i2 = srv.wait(t2, timeout_s=60)
+        assert i2["status"] == spx.OK and i2["iters"] == 0 and not x2.any(), i2
+        _, i3 = srv.wait(t3, timeout_s=60)
+        assert i3["status"] == spx.ERR_NONFINITE, i3
+    finally:
+        srv.close()
+
+
 def test_server_bicgstab_solves_spd_and_refuses_other_solvers():
     A, b = _system("spd", 3000, 31)
     x, info = _served_alone(A, b, spx.SOLVER_BICGSTAB)
