@@ -583,6 +583,8 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
     reqs = serve_workload(S, nreq, seed)
     t0 = time.time()
     systems = build_requests(spx, S, torch, dev, reqs, seed, pinned=pinned)
+    # result buffers, pinned as well (the server copies each solution there)
+    xouts = [_pinned_copy(torch, np.zeros(A.n)) if pinned else None for A, _ in systems]
     gen_s = time.time() - t0
     nnz = np.array([A.nnz for A, _ in systems])
     n = np.array([A.n for A, _ in systems])
@@ -598,7 +600,7 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
                 while time.perf_counter() - start < arrivals[i]:
                     time.sleep(0.0002)
             t_sub.append(time.perf_counter())
-            tickets.append(server.submit(A, b, tol=1e-8))
+            tickets.append(server.submit(A, b, tol=1e-8, x_out=xouts[i]))
             t_sched.append(start + (arrivals[i] if arrivals is not None else 0.0))
         lat, iters, worst, last = [], [], 0.0, start
         for i, (t, ts, tu) in enumerate(zip(tickets, t_sched, t_sub)):

@@ -485,8 +485,19 @@ bool rebuild_wide_map(spx_server &S)
     return e == hipSuccess;
 }
 
-void retire(spx_server &S)
+// Retire finished and cancelled systems: copy their solutions out (all at
+// once on the compute stream, idle between ticks: one wait for every copy),
+// then free their memory and slots and record the results. Returns false if
+// a copy failed.
+bool retire(spx_server &S)
 {
+    struct Finished {
+        int slot;
+        int32_t solver_status;
+        spx_solve_info info;
+    };
+    std::vector<Finished> fin;
+    hipError_t e = hipSuccess;
     for (int i = 0; i < (int)S.active.size(); ++i) {
         Active &a = S.active[i];
         if (!a.live || a.staged) continue;
@@ -515,19 +526,29 @@ void retire(spx_server &S)
             info.relres_true = d.relres_true;
             d.status = kSlotEmpty;
         }
-        if (!cancel && a.x_out) (void)hipMemcpy(a.x_out, a.x_dev, (size_t)a.n * 8, hipMemcpyDeviceToHost);
-        info.device_ms = std::chrono::duration<double, std::milli>(Clock::now() - a.t_submit).count();
+        if (!cancel && a.x_out && e == hipSuccess)
+            e = hipMemcpyAsync(a.x_out, a.x_dev, (size_t)a.n * 8, hipMemcpyDeviceToHost, S.s_compute);
+        fin.push_back(Finished{i, solver_status, info});
+    }
+    if (fin.empty()) return true;
+    if (e == hipSuccess) e = hipStreamSynchronize(S.s_compute);
+    if (e != hipSuccess) return false;
+    const auto now = Clock::now();
+    for (Finished &f : fin) {
+        Active &a = S.active[f.slot];
+        f.info.device_ms = std::chrono::duration<double, std::milli>(now - a.t_submit).count();
         a.in_map = false;
         std::lock_guard<std::mutex> lk(S.mu);
         // a cancel that arrived after the first read still wins: it returned
         // while the system was live
-        const spx_status st = a.cancel.load() ? SPX_CANCELLED : slot_status_to_spx(solver_status);
-        info.status = st;
+        const spx_status st = a.cancel.load() ? SPX_CANCELLED : slot_status_to_spx(f.solver_status);
+        f.info.status = st;
         S.pool.release(a.off, a.bytes);
         S.inflight -= a.work;
         a.live = false;
-        finish_locked(S, a.ticket, st, info);
+        finish_locked(S, a.ticket, st, f.info);
     }
+    return true;
 }
 
 // Stop serving: every queued and every resident request ends with `st`
@@ -650,7 +671,10 @@ void worker_main(spx_server *Sp)
         }
         // before apply_staged (next iteration): newly admitted systems have
         // no state to read yet; freed memory lets the admission thread go on
-        retire(S);
+        if (!retire(S)) {
+            set_fatal(S, "result copy failed");
+            break;
+        }
         S.cv_work.notify_one();
     }
     // the admission thread stops first, so no copy from a caller's arrays is
