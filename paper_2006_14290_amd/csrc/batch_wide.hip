@@ -79,19 +79,25 @@ __global__ __launch_bounds__(kCsrThreads) void wide_a_kernel(const WideSlot *__r
         const int32_t mode = st[s].mode;
         if (mode != kWideRun && mode != kWideCheck) continue;
         const WideSlot S = slots[s];
+        // one instantiation of the tile kernel for every case (its LDS
+        // staging sets the occupancy); the second partial (y.y) is used by
+        // BiCGSTAB's t = A s only
+        const double *src = mode == kWideRun ? S.r : S.x;
+        const double *dw = src;
+        double *y = S.w;
         if (S.solver == kSlotBicgstab && mode == kWideRun) {
             const int32_t bp = st[s].bphase;
-            if (bp == 0)  // v = A p, r_hat.v
-                csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
-                    k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, S.p, S.w, 1.0, 0.0, S.rh, S.part_a, S.csr_part);
-            else if (bp == 1)  // t = A s (s is held in r), t.s and t.t
-                csr_tile<double, double, 2, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
-                    k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, S.r, S.t, 1.0, 0.0, S.r, S.part_a, S.csr_part);
-            continue;
+            if (bp == 0) {  // v = A p, r_hat.v
+                src = S.p;
+                dw = S.rh;
+            } else if (bp == 1) {  // t = A s (s is held in r), t.s and t.t
+                y = S.t;
+            } else {
+                continue;  // no product in this pair
+            }
         }
-        const double *src = mode == kWideRun ? S.r : S.x;
-        csr_tile<double, double, 1, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
-            k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, S.w, 1.0, 0.0, src, S.part_a, S.csr_part);
+        csr_tile<double, double, 2, kCsrThreads, kCsrTile, 1, kCsrLateGather>(
+            k, S.n, S.nnz, S.ntiles, S.rowptr, S.col, S.val, src, y, 1.0, 0.0, dw, S.part_a, S.csr_part);
     }
 }
 
