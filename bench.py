@@ -569,7 +569,7 @@ def cpu_serve_sample(systems, nsample=200):
             "sample": f"first {len(sample)} requests of the stream, oracle CG to 1e-8, one solve per thread"}
 
 
-def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, pinned=True, bound_mb=512):
+def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, pinned=True):
     """Serving: (1) all `nreq` requests submitted at once (capacity, solves/s);
     (2) open-loop Poisson arrival streams at `fracs` x that capacity (latency
     = completion - scheduled arrival, p50/p99; completion is the server's own
@@ -577,9 +577,7 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
     same requests solved one by one with the blocking float64 CG
     (spx_cg_solve), for comparison. Tolerance 1e-8. The request arrays are
     in pinned host memory unless pinned=False (pageable numpy arrays, which
-    the runtime stages through its own buffers on the server's thread).
-    bound_mb > 0: the highest-rate stream once more, at the same arrival
-    rate, on a server with that work bound (spx_server_config.inflight_bytes)."""
+    the runtime stages through its own buffers on the server's thread)."""
     reqs = serve_workload(S, nreq, seed)
     t0 = time.time()
     systems = build_requests(spx, S, torch, dev, reqs, seed, pinned=pinned)
@@ -590,8 +588,7 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
     n = np.array([A.n for A, _ in systems])
     srv = spx.Server(max_slots=2048, hbm_budget_bytes=int(budget_gb * (1 << 30)))
 
-    def run(arrivals, label, server=None):
-        server = server or srv
+    def run(arrivals, label):
         progress(f"serve {label}: submitting {nreq} requests")
         tickets, t_sched, t_sub = [], [], []
         start = time.perf_counter()
@@ -600,11 +597,11 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
                 while time.perf_counter() - start < arrivals[i]:
                     time.sleep(0.0002)
             t_sub.append(time.perf_counter())
-            tickets.append(server.submit(A, b, tol=1e-8, x_out=xouts[i]))
+            tickets.append(srv.submit(A, b, tol=1e-8, x_out=xouts[i]))
             t_sched.append(start + (arrivals[i] if arrivals is not None else 0.0))
         lat, iters, worst, last = [], [], 0.0, start
         for i, (t, ts, tu) in enumerate(zip(tickets, t_sched, t_sub)):
-            x, info = server.wait(t, timeout_s=900)
+            x, info = srv.wait(t, timeout_s=900)
             assert info["status"] == 0, info
             done = tu + info["device_ms"] * 1e-3
             last = max(last, done)
@@ -644,21 +641,6 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
         r.pop("_lat")
         r["rate_per_s"] = round(rate, 2)
         streams[f"{frac:.1f}x"] = r
-    bounded = None
-    if bound_mb > 0 and fracs:
-        frac = max(fracs)
-        rate = frac * burst["solves_per_s"]
-        srv_b = spx.Server(max_slots=2048, hbm_budget_bytes=int(budget_gb * (1 << 30)),
-                           inflight_bytes=int(bound_mb) << 20)
-        try:
-            r = run(S.poisson_arrivals(nreq, rate, seed=seed), f"{frac:.1f}x, {bound_mb} MB work bound", srv_b)
-        finally:
-            srv_b.close()
-        r.pop("_iters")
-        r.pop("_lat")
-        r["rate_per_s"] = round(rate, 2)
-        r["inflight_bytes"] = int(bound_mb) << 20
-        bounded = {f"{frac:.1f}x": r}
     # unloaded latency of the heaviest requests (iterations x entries), each
     # alone on the server: the floor the tail of a loaded stream sits on
     heavy = np.argsort(burst_iters * (nnz + n))[-10:]
@@ -690,7 +672,7 @@ def bench_serve(spx, S, torch, dev, nreq, seed, fracs, budget_gb=32, cpu=False, 
         assert info["status"] == 0
     seq = len(sample) / (time.perf_counter() - t1)
     # the served throughput over the same first requests
-    out = {"burst": burst, "open_loop": streams, "open_loop_work_bound": bounded, "unloaded": unloaded,
+    out = {"burst": burst, "open_loop": streams, "unloaded": unloaded,
            "sequential_cg_solves_per_s": round(seq, 2), "sequential_sample": len(sample), "served_over_sequential": round(burst["solves_per_s"] / seq, 2),
            "server": {k: st[k] for k in ("ticks", "pool_bytes_peak", "pool_bytes_total")}, "budget_gb": budget_gb,
            "mix": {"poisson": int(sum(k == "poisson" for k, _ in reqs)), "spd": int(sum(k == "spd" for k, _ in reqs)),
@@ -752,8 +734,6 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-fracs", default="0.5,0.7,0.9", help="open-loop arrival rates, fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="HBM budget of the serving run")
-    ap.add_argument("--serve-bound-mb", type=int, default=512,
-                    help="work bound (MB) of the extra highest-rate stream (0 = skip it)")
     ap.add_argument("--serve-pageable", action="store_true",
                     help="requests in pageable host memory (default: pinned, as a receive path holds them)")
     ap.add_argument("--seed", type=int, default=0)
@@ -845,7 +825,7 @@ def main():
     if args.serve_requests > 0:
         fracs = [float(f) for f in args.serve_fracs.split(",") if f]
         serve = bench_serve(spx, S, torch, dev, args.serve_requests, args.seed, fracs, args.serve_budget_gb,
-                            not args.no_cpu, pinned=not args.serve_pageable, bound_mb=args.serve_bound_mb)
+                            not args.no_cpu, pinned=not args.serve_pageable)
     subwarp = None
     if not args.no_subwarp:
         progress("subwarp sweep")

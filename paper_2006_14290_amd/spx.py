@@ -547,7 +547,9 @@ def cg_batch(mats, bs, tol=1e-8, maxit=100000, path=BATCH_AUTO, stream=None, noa
 
 
 class Server:
-    """Continuous-batching CG server (host requests, results copied back)."""
+    """Continuous-batching CG / BiCGSTAB server (host requests, results copied
+    back). inflight_bytes > 0: bound on the summed per-iteration bytes of the
+    resident systems (strict FIFO past it); <= 0: no bound."""
 
     def __init__(self, device: int = 0, max_slots: int = 1024, hbm_budget_bytes: int = 32 << 30,
                  iters_per_tick: int = 0, tick_us: int = 0, wide_min_rows: int = 0, debug_fail_tick: int = 0,
